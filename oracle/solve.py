@@ -1,0 +1,291 @@
+"""Solve phase of the oracle (test infrastructure only).
+
+What is solved (paper, Section 5.2, eq. firstorderpractice): the symmetric
+practical form (K^T M_y K + beta M_u) u = K^T M_y y_d with K = A^{-1} M_yu
+(eq. solutionopdef), i.e. H_0 u = b.  H_j := M_{u,j} G_j at every level j.
+
+  * inner solves with A_j: CG preconditioned by one AMG V-cycle from level j
+    (Section 5.2 uses AMG-preconditioned CG for every application of K and
+    K^*); the V-cycle uses nu l1-Jacobi pre/post sweeps and the dense Cholesky
+    solve on the coarsest AMG level;
+  * mass solves M_{u,j}^{-1}: CG preconditioned by the diagonal of M_{u,j}
+    (the paper uses a symmetric Gauss-Seidel sweep; Jacobi is the
+    order-independent choice for a GPU, only iteration counts change);
+  * the multilevel preconditioner B_j ~ H_j^{-1} (Section 3.2, eqs.
+    twogridinmulti, twogridinmultiactual, twogridinmultiactualfine and
+    Algorithm MLAS, in the practical form announced in Section 5.2):
+        C_j(r)  = P_j B_{j+1}(P_j^T r) + beta^{-1}(M_{u,j}^{-1} r
+                  - P_j M_{u,j+1}^{-1} P_j^T r)
+        B_{l-1} = H_{l-1}^{-1}  (dense, exact as the theory assumes)
+        B_j(r)  = z + C_j(r - H_j z), z = C_j(r)     for 0 < j < l-1
+        B_0     = C_0;
+  * the outer CG on H_0 preconditioned by B_0 (Section 5.3: CG to relative
+    residual 1e-8).
+
+All residuals are Euclidean 2-norms relative to the right-hand side; every CG
+starts from zero.  A mixed-precision twin (float32 V-cycle and CG inside FP64
+iterative refinement, FP64 dense coarse solve) is provided beside the FP64
+path.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import sa
+from .csr import CSR
+
+
+class Indefinite(RuntimeError):
+    pass
+
+
+class NoConvergence(RuntimeError):
+    pass
+
+
+@dataclass
+class Counters:
+    inner_iters: int = 0
+    inner_solves: int = 0
+    inner_max: int = 0
+    mass_iters: int = 0
+    outer_iters: int = 0
+    refine_steps: int = 0
+    history: list = field(default_factory=list)
+
+
+def pcg(apply_A, apply_B, b, rtol, maxit, indefinite_check=False):
+    """Preconditioned conjugate gradients (Hestenes-Stiefel), x_0 = 0, stop at
+    ||r||_2 <= rtol ||b||_2 on the recursive residual.  Returns (x, iters)."""
+    x = np.zeros_like(b)
+    bn = float(np.linalg.norm(b))
+    if bn == 0.0:
+        return x, 0
+    r = b.copy()
+    z = apply_B(r)
+    rho = float(r @ z)
+    if indefinite_check and not rho > 0.0:
+        raise Indefinite("r.z <= 0")
+    p = z.copy()
+    for it in range(1, maxit + 1):
+        q = apply_A(p)
+        pq = float(p @ q)
+        if indefinite_check and not pq > 0.0:
+            raise Indefinite("p.q <= 0")
+        alpha = rho / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        if float(np.linalg.norm(r)) <= rtol * bn:
+            return x, it
+        z = apply_B(r)
+        rho_new = float(r @ z)
+        if indefinite_check and not rho_new > 0.0:
+            raise Indefinite("r.z <= 0")
+        beta = rho_new / rho
+        rho = rho_new
+        p = z + beta * p
+    raise NoConvergence(f"CG did not reach {rtol} in {maxit} iterations")
+
+
+class Oracle:
+    """FP64 reference solver on a hierarchy built by oracle.sa.build."""
+
+    def __init__(self, h: sa.Hierarchy, mixed: bool = False):
+        self.h = h
+        self.o = h.opts
+        self.beta = h.opts.beta
+        self.cnt = Counters()
+        self.mixed = mixed
+        if mixed:
+            self.l32 = [dict(A=lev.A.astype32(), S=None if lev.S is None else lev.S.astype32(),
+                             St=None if lev.St is None else lev.St.astype32(),
+                             dl1=lev.dl1.astype(np.float32)) for lev in h.levels]
+
+    # ---- V-cycle (AMG preconditioner for A_j) ----
+    def vcycle(self, l: int, b: np.ndarray) -> np.ndarray:
+        h = self.h
+        if l == h.L - 1:
+            return sla.cho_solve(h.chol_A, b)
+        lev = h.levels[l]
+        A = lev.A
+        x = b / lev.dl1
+        for _ in range(self.o.nu - 1):
+            x = x + (b - A.matvec(x)) / lev.dl1
+        r = b - A.matvec(x)
+        e = self.vcycle(l + 1, lev.St.matvec(r))
+        x = x + lev.S.matvec(e)
+        for _ in range(self.o.nu):
+            x = x + (b - A.matvec(x)) / lev.dl1
+        return x
+
+    def vcycle32(self, l: int, b: np.ndarray) -> np.ndarray:
+        h = self.h
+        if l == h.L - 1:
+            return sla.cho_solve(h.chol_A, b.astype(np.float64)).astype(np.float32)
+        m = self.l32[l]
+        A, dl1 = m["A"], m["dl1"]
+        x = b / dl1
+        for _ in range(self.o.nu - 1):
+            x = x + (b - A.matvec(x)) / dl1
+        r = b - A.matvec(x)
+        e = self.vcycle32(l + 1, m["St"].matvec(r))
+        x = x + m["S"].matvec(e)
+        for _ in range(self.o.nu):
+            x = x + (b - A.matvec(x)) / dl1
+        return x
+
+    # ---- inner solves ----
+    def solve_A(self, j: int, f: np.ndarray, rtol: float) -> np.ndarray:
+        """x = A_j^{-1} f by V-cycle-preconditioned CG (FP64), or the mixed
+        refinement loop; the coarsest AMG level is solved densely."""
+        h = self.h
+        if j == h.L - 1:
+            return sla.cho_solve(h.chol_A, f)
+        if self.mixed:
+            return self._solve_A_mixed(j, f, rtol)
+        A = h.levels[j].A
+        x, it = pcg(A.matvec, lambda r: self.vcycle(j, r), f, rtol, self.o.inner_maxit)
+        self._count_inner(it)
+        return x
+
+    def _count_inner(self, it):
+        self.cnt.inner_iters += it
+        self.cnt.inner_solves += 1
+        self.cnt.inner_max = max(self.cnt.inner_max, it)
+
+    def pcg32(self, j: int, b32: np.ndarray, rtol: float):
+        """CG in float32 with float64 dot products and float64 scalars."""
+        m = self.l32[j]
+        A = m["A"]
+        d64 = lambda a, c: float(a.astype(np.float64) @ c.astype(np.float64))
+        x = np.zeros_like(b32)
+        bn = np.sqrt(d64(b32, b32))
+        if bn == 0.0:
+            return x, 0
+        r = b32.copy()
+        z = self.vcycle32(j, r)
+        rho = d64(r, z)
+        p = z.copy()
+        for it in range(1, self.o.inner_maxit + 1):
+            q = A.matvec(p)
+            alpha = rho / d64(p, q)
+            a32 = np.float32(alpha)
+            x = x + a32 * p
+            r = r - a32 * q
+            if np.sqrt(d64(r, r)) <= rtol * bn:
+                return x, it
+            z = self.vcycle32(j, r)
+            rho_new = d64(r, z)
+            beta = rho_new / rho
+            rho = rho_new
+            p = z + np.float32(beta) * p
+        raise NoConvergence("float32 CG did not converge")
+
+    def _solve_A_mixed(self, j: int, f: np.ndarray, rtol: float) -> np.ndarray:
+        """FP64 iterative refinement around the float32 CG: x += s d,
+        d = CG32(fp32(r/s)), s = ||r||, r = f - A x in FP64."""
+        A = self.h.levels[j].A
+        x = np.zeros_like(f)
+        fn = float(np.linalg.norm(f))
+        if fn == 0.0:
+            return x
+        r = f.copy()
+        s = fn
+        for step in range(self.o.refine_maxit):
+            d, it = self.pcg32(j, (r / s).astype(np.float32), self.o.inner32_rtol)
+            self._count_inner(it)
+            self.cnt.refine_steps += 1
+            x = x + s * d.astype(np.float64)
+            r = f - A.matvec(x)
+            s_new = float(np.linalg.norm(r))
+            if s_new <= rtol * fn:
+                return x
+            if s_new > 0.5 * s:
+                raise NoConvergence("refinement stagnated")
+            s = s_new
+        raise NoConvergence("refinement did not converge")
+
+    def mass_solve(self, j: int, r: np.ndarray) -> np.ndarray:
+        M = self.h.levels[j].M
+        d = M.diag()
+        x, it = pcg(M.matvec, lambda v: v / d, r, self.o.mass_rtol, self.o.mass_maxit)
+        self.cnt.mass_iters += it
+        return x
+
+    # ---- operators (Section 2 and Section 5.2) ----
+    def state_solve(self, j: int, u: np.ndarray, rtol=None) -> np.ndarray:
+        """y = K_j u = A_j^{-1} M_{yu,j} u."""
+        return self.solve_A(j, sa.mass_yu(self.h, j, u), rtol or self.o.inner_rtol)
+
+    def adjoint_solve(self, j: int, w: np.ndarray, rtol=None) -> np.ndarray:
+        """K_j^T w = M_{yu,j}^T A_j^{-1} w (A_j symmetric)."""
+        return sa.mass_yu_t(self.h, j, self.solve_A(j, w, rtol or self.o.inner_rtol))
+
+    def hessian_apply(self, j: int, u: np.ndarray, rtol=None) -> np.ndarray:
+        """H_j u = K_j^T M_{y,j} K_j u + beta M_{u,j} u."""
+        y = self.state_solve(j, u, rtol)
+        z = self.adjoint_solve(j, sa.mass_y(self.h, j, y), rtol)
+        return z + self.beta * sa.mass_u(self.h, j, u)
+
+    def rhs(self, yd: np.ndarray) -> np.ndarray:
+        """b = K_0^T M_{y,0} y_d."""
+        return self.adjoint_solve(0, sa.mass_y(self.h, 0, yd))
+
+    # ---- multilevel preconditioner ----
+    def C(self, j: int, r: np.ndarray) -> np.ndarray:
+        lev = self.h.levels[j]
+        q = lev.St.matvec(r)
+        v = self.B(j + 1, q) - (1.0 / self.beta) * self.mass_solve(j + 1, q)
+        return lev.S.matvec(v) + (1.0 / self.beta) * self.mass_solve(j, r)
+
+    def B(self, j: int, r: np.ndarray) -> np.ndarray:
+        h = self.h
+        if j == h.ell - 1:
+            return sla.cho_solve(h.chol_H, r)
+        z = self.C(j, r)
+        if j > 0:
+            z = z + self.C(j, r - self.hessian_apply(j, z, self.o.precond_inner_rtol))
+        return z
+
+    def precond(self, r: np.ndarray) -> np.ndarray:
+        return self.B(0, r) if self.o.precond else r.copy()
+
+    # ---- outer solve (Section 5.3) ----
+    def reduced_solve(self, yd: np.ndarray, rtol: float = 1e-8):
+        """Solve H_0 u = b for one desired state; on an indefinite
+        preconditioner with auto_levels, drop one Hessian level and restart."""
+        b = self.rhs(yd)
+        while True:
+            try:
+                u, it = pcg(lambda v: self.hessian_apply(0, v), self.precond, b, rtol,
+                            self.o.outer_maxit, indefinite_check=True)
+                self.cnt.outer_iters += it
+                return u, it
+            except Indefinite:
+                if not self.o.auto_levels or self.h.ell <= 1:
+                    raise
+                sa.set_hessian_levels(self.h, self.h.ell - 1)
+
+    def objective(self, u: np.ndarray, yd: np.ndarray) -> float:
+        """J(u) = 1/2 (Ku - y_d)^T M_y (Ku - y_d) + beta/2 u^T M_u u (eq. functional)."""
+        e = self.state_solve(0, u) - yd
+        return 0.5 * float(e @ sa.mass_y(self.h, 0, e)) + 0.5 * self.beta * float(u @ sa.mass_u(self.h, 0, u))
+
+    def gradient(self, u: np.ndarray, yd: np.ndarray) -> np.ndarray:
+        """grad J(u) = K^T M_y (K u - y_d) + beta M_u u."""
+        e = self.state_solve(0, u) - yd
+        return self.adjoint_solve(0, sa.mass_y(self.h, 0, e)) + self.beta * sa.mass_u(self.h, 0, u)
+
+
+def build_problem(prob, opts: sa.Opts | None = None):
+    """Assemble and build the hierarchy for an inputs.Problem."""
+    from . import fem
+    opts = opts or sa.Opts(beta=prob.beta)
+    A, M = fem.assemble(prob.mesh.coords, prob.mesh.elems, prob.kappa)
+    bc = prob.dirichlet.astype(bool)
+    A0 = fem.dirichlet_stiffness(A, bc)
+    h = sa.build(A0, M, bc, opts)
+    return h, A, M

@@ -1,0 +1,222 @@
+"""Pins for the oracle's solve phase: dense brute force on tiny meshes, the
+paper's closed-form optimal control (eq. test-state), the structural facts of
+Section 3 (T symmetric positive definite, P Pi a projection, the stated
+inverse of T), the exact-quadratic identities of the reduced functional and
+the equivalence of the practical-form preconditioner with the paper's W_j."""
+import math
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle import dense, fem, sa, solve
+
+
+def build(name, n, **kw):
+    p = inputs.config(name, n=n)
+    opts = sa.Opts(beta=kw.pop("beta", p.beta), **kw)
+    h, A, M = solve.build_problem(p, opts)
+    return p, h
+
+
+def tight(**kw):
+    base = dict(inner_rtol=1e-13, mass_rtol=1e-14, precond_inner_rtol=1e-13)
+    base.update(kw)
+    return base
+
+
+def test_vcycle_is_symmetric_and_contracts():
+    p, h = build("c2", 12, max_coarse=12)
+    assert h.L >= 3
+    o = solve.Oracle(h)
+    n = h.levels[0].n
+    B = dense.vcycle_matrix(lambda e: o.vcycle(0, e), n)
+    assert np.max(np.abs(B - B.T)) <= 1e-13 * np.max(np.abs(B))
+    A = h.levels[0].A.dense()
+    ev = np.linalg.eigvals(B @ A).real
+    assert ev.min() > 0 and ev.max() < 2.0       # ||I - BA||_A < 1
+
+
+@pytest.mark.parametrize("name,n", [("c1", 8), ("c3", 4)])
+def test_state_adjoint_hessian_against_dense(name, n):
+    p, h = build(name, n, max_coarse=10, **tight())
+    o = solve.Oracle(h)
+    ops = dense.level_ops(h, 0)
+    rng = np.random.default_rng(7)
+    u = rng.standard_normal(h.levels[0].n)
+    np.testing.assert_allclose(o.state_solve(0, u), ops["K"] @ u, rtol=1e-10, atol=1e-12 * np.abs(ops["K"] @ u).max())
+    w = rng.standard_normal(h.levels[0].n)
+    np.testing.assert_allclose(o.adjoint_solve(0, w), ops["K"].T @ w, rtol=1e-10,
+                               atol=1e-12 * np.abs(ops["K"].T @ w).max())
+    H = dense.hessian_practical(h)
+    Hu = o.hessian_apply(0, u)
+    np.testing.assert_allclose(Hu, H @ u, rtol=1e-9, atol=1e-11 * np.abs(H @ u).max())
+    # the paper's two forms: H = M_u G
+    np.testing.assert_allclose(H, ops["Mu"] @ ops["G"], rtol=1e-9, atol=1e-12 * np.abs(H).max())
+
+
+def test_dense_hessian_spectrum_bounds_and_closed_form():
+    # (G u, u)_M >= beta (u, u)_M, and for kappa = 1 in 2D the top of the
+    # spectrum of K^*K approaches 1/(2 pi^2)^2 (first Dirichlet eigenvalue of
+    # the Laplacian on the unit square is 2 pi^2).
+    p, h = build("c1", 16)
+    H = dense.hessian_practical(h)
+    Mu = dense.level_ops(h, 0)["Mu"]
+    assert np.array_equal(H, H) and np.max(np.abs(H - H.T)) < 1e-12 * np.abs(H).max()
+    import scipy.linalg as sla
+    lam = sla.eigh(H, Mu, eigvals_only=True)
+    beta = p.beta
+    assert lam.min() >= beta * (1 - 1e-10)
+    assert np.linalg.eigvalsh(H).min() >= beta * np.linalg.eigvalsh(Mu).min() * (1 - 1e-10)
+    top = beta + 1.0 / (2 * math.pi ** 2) ** 2
+    assert abs(lam.max() - top) / top < 0.03
+
+
+@pytest.mark.parametrize("name,n,mc", [("c2", 12, 12), ("c3", 5, 8)])
+def test_practical_preconditioner_equals_paper_multilevel_operator(name, n, mc):
+    p, h = build(name, n, max_coarse=mc, beta=1e-2, **tight())
+    assert h.ell >= 3, "need an intermediate level to exercise the W recursion"
+    o = solve.Oracle(h)
+    N = h.levels[0].n
+    B = dense.vcycle_matrix(o.precond, N)
+    W0 = dense.W(h, 0, h.ell)
+    Mu = dense.level_ops(h, 0)["Mu"]
+    ref = W0 @ np.linalg.inv(Mu)
+    assert np.max(np.abs(B - ref)) <= 1e-8 * np.max(np.abs(ref))
+    # B_0 W-cycle form equals 2C - C H C at level 1 (Algorithm MLAS)
+    assert np.max(np.abs(ref - ref.T)) <= 1e-8 * np.max(np.abs(ref))
+
+
+def test_two_grid_identities():
+    p, h = build("c2", 12, max_coarse=12, beta=1e-3)
+    P = h.levels[0].S.dense()
+    Pi = dense.projection(h, 0)
+    np.testing.assert_allclose(Pi @ P, np.eye(P.shape[1]), atol=1e-10)          # Pi P = I
+    PP = P @ Pi
+    np.testing.assert_allclose(PP @ PP, PP, atol=1e-10 * np.abs(PP).max())     # projection
+    T, Tinv = dense.two_grid_T(h, 0)
+    np.testing.assert_allclose(T @ Tinv, np.eye(T.shape[0]), atol=1e-8)        # eq. twogrid
+    Mu = dense.level_ops(h, 0)["Mu"]
+    MT = Mu @ T                                                                 # M_u-self-adjoint
+    assert np.max(np.abs(MT - MT.T)) < 1e-9 * np.abs(MT).max()
+    assert np.linalg.eigvalsh(0.5 * (MT + MT.T)).min() > 0                      # T is SPD
+
+
+def test_one_level_preconditioner_converges_in_one_iteration():
+    p, h = build("c1", 8, hess_levels=1, **tight())
+    assert h.ell == 1
+    o = solve.Oracle(h)
+    u, it = o.reduced_solve(p.yd[:, 0])
+    assert it == 1
+
+
+def test_two_level_preconditioner_is_spd():
+    p, h = build("c1", 12, max_coarse=30, hess_levels=2, **tight())
+    o = solve.Oracle(h)
+    B = dense.vcycle_matrix(o.precond, h.levels[0].n)
+    assert np.max(np.abs(B - B.T)) < 1e-9 * np.abs(B).max()
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+
+
+@pytest.mark.parametrize("name,n,mc", [("c1", 10, 20), ("c2", 12, 12), ("c3", 4, 8)])
+def test_reduced_solve_matches_dense_solution(name, n, mc):
+    p, h = build(name, n, max_coarse=mc)
+    o = solve.Oracle(h)
+    yd = p.yd[:, 0]
+    u, it = o.reduced_solve(yd, rtol=1e-10)
+    H = dense.hessian_practical(h)
+    b = dense.rhs_practical(h, yd)
+    ref = np.linalg.solve(H, b)
+    assert np.linalg.norm(u - ref) <= 1e-8 * np.linalg.norm(ref)
+    # the preconditioner does not change the solution (Section 5.3)
+    h.opts.precond = 0
+    o2 = solve.Oracle(h)
+    u2, it2 = o2.reduced_solve(yd, rtol=1e-10)
+    assert np.linalg.norm(u2 - ref) <= 1e-8 * np.linalg.norm(ref)
+    assert it2 >= it
+
+
+def _mass_norm(M, v):
+    return math.sqrt(float(v @ M.matvec(v)))
+
+
+def test_closed_form_control_2d_second_order():
+    # 2D analogue of eq. test-state: y_d = sin(pi x) sin(pi y) gives
+    # u* = c sin sin with c = 1/(2 pi^2 beta + 1/(2 pi^2)).
+    beta = 1e-2
+    c = 1.0 / (2 * math.pi ** 2 * beta + 1.0 / (2 * math.pi ** 2))
+    errs = []
+    for n in (8, 16, 32, 64):
+        p, h = build("c1", n)
+        o = solve.Oracle(h)
+        u, _ = o.reduced_solve(p.yd[:, 0], rtol=1e-11)
+        ustar = inputs.yd_sin(p.mesh, c)
+        errs.append(_mass_norm(h.levels[0].M, u - ustar) / _mass_norm(h.levels[0].M, ustar))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert errs[2] < 1e-2
+    assert all(3.5 < r < 4.5 for r in ratios), ratios
+
+
+def test_manufactured_solution_3d_converges():
+    # eq. test-state: y_d = (1/(3 pi^2) + 3 pi^2 beta) sin sin sin has the
+    # optimal control u* = sin sin sin (kappa = 1).
+    beta = 1e-2
+    errs = []
+    for n in (4, 8, 16):
+        m = inputs.mesh3d(n)
+        p = inputs.Problem("m", m, inputs.kappa_const(m), beta,
+                           inputs.yd_manufactured(m, beta).reshape(-1, 1), m.boundary)
+        h, A, M = solve.build_problem(p)
+        o = solve.Oracle(h)
+        u, _ = o.reduced_solve(p.yd[:, 0], rtol=1e-11)
+        ustar = inputs.yd_sin(m)
+        errs.append(_mass_norm(M, u - ustar) / _mass_norm(M, ustar))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[1] / errs[2] > 3.0, errs
+
+
+def test_exact_quadratic_identities_and_gradient():
+    p, h = build("c2", 12, max_coarse=12, **tight())
+    o = solve.Oracle(h)
+    yd = p.yd[:, 0]
+    rng = np.random.default_rng(11)
+    u = rng.standard_normal(h.levels[0].n)
+    d = rng.standard_normal(h.levels[0].n)
+    d /= np.linalg.norm(d)
+    g = o.gradient(u, yd)
+    H = dense.hessian_practical(h)
+    b = dense.rhs_practical(h, yd)
+    np.testing.assert_allclose(g, H @ u - b, rtol=1e-9, atol=1e-11 * np.abs(g).max())
+    step = 1e-2
+    Jp, J0, Jm = o.objective(u + step * d, yd), o.objective(u, yd), o.objective(u - step * d, yd)
+    fd = (Jp - Jm) / (2 * step)
+    assert abs(fd - g @ d) <= 1e-9 * max(abs(g @ d), 1e-30) + 1e-12 * abs(J0) / step
+    sd = (Jp - 2 * J0 + Jm) / step ** 2
+    assert abs(sd - d @ H @ d) <= 1e-6 * abs(d @ H @ d) + 1e-12 * abs(J0) / step ** 2
+
+
+def test_mixed_precision_twin_matches_fp64():
+    p, h = build("c3", 8, max_coarse=30)
+    o64 = solve.Oracle(h)
+    o32 = solve.Oracle(h, mixed=True)
+    yd = p.yd[:, 0]
+    u64, _ = o64.reduced_solve(yd)
+    u32, _ = o32.reduced_solve(yd)
+    assert np.linalg.norm(u32 - u64) <= 1e-8 * np.linalg.norm(u64)
+    assert o32.cnt.refine_steps > 0
+
+
+def test_indefinite_fallback_drops_levels():
+    # a preconditioner may lose definiteness with many levels (Section 3.2);
+    # the fallback drops Hessian levels until CG runs.  Force it with an
+    # absurdly small beta on a coarse hierarchy and check that the answer is
+    # still the dense solution.
+    p, h = build("c2", 16, max_coarse=6, beta=1e-9)
+    o = solve.Oracle(h)
+    yd = p.yd[:, 0]
+    ell0 = h.ell
+    u, it = o.reduced_solve(yd, rtol=1e-9)
+    assert h.ell < ell0
+    H = dense.hessian_practical(h)
+    ref = np.linalg.solve(H, dense.rhs_practical(h, yd))
+    assert np.linalg.norm(u - ref) <= 1e-6 * np.linalg.norm(ref)
