@@ -1,0 +1,588 @@
+// C ABI of the library (declared in include/amghess.h).  Every entry point
+// catches internal errors and returns a status code.
+#include <chrono>
+#include <cstring>
+
+#include "solver.hpp"
+
+namespace amg {
+namespace {
+
+thread_local std::string g_setup_err;
+
+int pad_nb(int nb) { return nb <= 1 ? 1 : nb <= 2 ? 2 : nb <= 4 ? 4 : nb <= 8 ? 8 : 16; }
+
+template <class F> int dispatch_nb(int nbp, F &&f) {
+    switch (nbp) {
+        case 1: return f(std::integral_constant<int, 1>{});
+        case 2: return f(std::integral_constant<int, 2>{});
+        case 4: return f(std::integral_constant<int, 4>{});
+        case 8: return f(std::integral_constant<int, 8>{});
+        default: return f(std::integral_constant<int, 16>{});
+    }
+}
+
+template <class F> int guarded(Ctx *c, F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        if (c) c->err = e.msg;
+        else g_setup_err = e.msg;
+        (void)hipGetLastError();
+        return e.code;
+    } catch (const std::exception &e) {
+        if (c) c->err = e.what();
+        else g_setup_err = e.what();
+        return AMG_ERR_HIP;
+    }
+}
+
+void alloc_cg(Arena &a, CgWs<double> &w, size_t m) {
+    w.r = a.alloc<double>(m);
+    w.z = a.alloc<double>(m);
+    w.p0 = a.alloc<double>(m);
+    w.p1 = a.alloc<double>(m);
+    w.q = a.alloc<double>(m);
+    w.sc = a.alloc<CgScal>(1);
+}
+void alloc_cg(Arena &a, CgWs<float> &w, size_t m) {
+    w.r = a.alloc<float>(m);
+    w.z = a.alloc<float>(m);
+    w.p0 = a.alloc<float>(m);
+    w.p1 = a.alloc<float>(m);
+    w.q = a.alloc<float>(m);
+    w.sc = a.alloc<CgScal>(1);
+}
+template <typename T> void alloc_vc(Arena &a, VcWs<T> &v, size_t m) {
+    v.b = a.alloc<T>(m);
+    v.x = a.alloc<T>(m);
+    v.r = a.alloc<T>(m);
+    v.x2 = a.alloc<T>(m);
+}
+
+void alloc_workspaces(Ctx &c) {
+    Arena &a = c.arena;
+    const int nbp = c.nbp;
+    c.ws.assign(c.L, LevelWs{});
+    const bool mixed = c.o.inner_precision == 32;
+    for (int l = 0; l < c.L; ++l) {
+        LevelWs &w = c.ws[l];
+        const size_t m = (size_t)c.lev[l].n * nbp;
+        alloc_cg(a, w.in64, m);
+        alloc_cg(a, w.mass, m);
+        alloc_vc(a, w.vc64, m);
+        if (mixed) {
+            alloc_cg(a, w.in32, m);
+            alloc_vc(a, w.vc32, m);
+            w.rr = a.alloc<double>(m);
+            w.b32 = a.alloc<float>(m);
+            w.d32 = a.alloc<float>(m);
+        }
+        w.hf = a.alloc<double>(m);
+        w.hy = a.alloc<double>(m);
+        w.hw = a.alloc<double>(m);
+        w.ht = a.alloc<double>(m);
+        w.ml_in = a.alloc<double>(m);
+        w.ml_out = a.alloc<double>(m);
+        w.ml_mup = a.alloc<double>(m);
+        w.ml_mself = a.alloc<double>(m);
+        w.ml_z1 = a.alloc<double>(m);
+        w.ml_t = a.alloc<double>(m);
+    }
+    const size_t m0 = (size_t)c.N * nbp;
+    alloc_cg(a, c.outer, m0);
+    c.ox = a.alloc<double>(m0);
+    c.ob = a.alloc<double>(m0);
+    c.obq = a.alloc<double>(m0);
+    c.pk_in = a.alloc<double>(m0);
+    c.pk_out = a.alloc<double>(m0);
+    c.rsd = a.alloc<RefScal>(1);
+}
+
+void fill_info(Ctx &c, amg_info *info, int n, double ms, int outer_it) {
+    if (!info) return;
+    for (int k = 0; k < n; ++k) {
+        amg_info &f = info[k];
+        std::memset(&f, 0, sizeof(f));
+        f.outer_iters = outer_it;
+        f.inner_solves = (int)c.st.inner_solves;
+        f.inner_iters_total = (int)c.st.inner_iters;
+        f.inner_iters_max = (int)c.st.inner_max;
+        f.mass_iters_total = (int)c.st.mass_iters;
+        f.refine_steps = (int)c.st.refine;
+        f.levels = c.L;
+        f.ell = c.ell;
+        f.ms_total = ms;
+    }
+}
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0) {
+    return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+int check_vec_call(Ctx *c, int level, int nb) {
+    if (!c) return AMG_ERR_ARG;
+    if (level < 0 || level >= c->L) {
+        c->err = "level out of range";
+        return AMG_ERR_ARG;
+    }
+    if (nb < 1 || nb > c->nbp || nb > 16) {
+        c->err = "nb out of range (1..nb_max)";
+        return AMG_ERR_ARG;
+    }
+    return AMG_OK;
+}
+
+}  // namespace
+}  // namespace amg
+
+using namespace amg;
+
+struct amg_ctx {
+    Ctx c;
+};
+
+extern "C" {
+
+int amg_opts_default(amg_opts *o) {
+    if (!o) return AMG_ERR_ARG;
+    std::memset(o, 0, sizeof(*o));
+    o->beta = 1e-2;
+    o->hess_levels = 0;
+    o->auto_levels = 1;
+    o->max_levels = 10;
+    o->max_coarse = 200;
+    o->dense_max = 4096;
+    o->theta0 = 0.08;
+    o->agg_seed = 0x200111533ull;
+    o->nu = 1;
+    o->inner_rtol = 1e-10;
+    o->mass_rtol = 1e-10;
+    o->precond_inner_rtol = 1e-10;
+    o->inner_maxit = 500;
+    o->mass_maxit = 500;
+    o->outer_maxit = 200;
+    o->inner_precision = 64;
+    o->inner32_rtol = 1e-6;
+    o->refine_maxit = 6;
+    o->nb_max = 1;
+    o->precond = 1;
+    o->check_every = 1;
+    return AMG_OK;
+}
+
+const char *amg_last_error(amg_ctx *ctx) { return ctx ? ctx->c.err.c_str() : g_setup_err.c_str(); }
+
+int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, const amg_opts *opts, void *stream,
+              amg_ctx **out) {
+    if (!out) return AMG_ERR_ARG;
+    *out = nullptr;
+    g_setup_err.clear();
+    if (!A || !M || !A->rowptr || !A->col || !A->val || !M->rowptr || !M->col || !M->val) {
+        g_setup_err = "null matrix argument";
+        return AMG_ERR_ARG;
+    }
+    if (A->nrows <= 0 || A->nrows != A->ncols || M->nrows != A->nrows || M->ncols != A->ncols || A->nnz <= 0 ||
+        M->nnz <= 0) {
+        g_setup_err = "matrix sizes invalid or mismatching";
+        return AMG_ERR_ARG;
+    }
+    amg_opts o;
+    if (opts) o = *opts;
+    else amg_opts_default(&o);
+    if (!(o.beta > 0.0) || o.nb_max < 1 || o.nb_max > 16 || o.max_levels < 1 || o.max_coarse < 1 ||
+        o.dense_max < 1 || o.dense_max > 4096 || (o.inner_precision != 32 && o.inner_precision != 64) ||
+        o.nu != 1 || o.inner_maxit < 1 || o.mass_maxit < 1 || o.outer_maxit < 1 || o.hess_levels < 0 ||
+        !(o.theta0 >= 0.0) || o.refine_maxit < 1) {
+        g_setup_err = "invalid options (beta > 0, 1 <= nb_max <= 16, dense_max <= 4096, nu = 1, precision 32/64)";
+        return AMG_ERR_ARG;
+    }
+    amg_ctx *h = new (std::nothrow) amg_ctx;
+    if (!h) return AMG_ERR_OOM;
+    Ctx &c = h->c;
+    c.o = o;
+    c.stream = reinterpret_cast<hipStream_t>(stream);
+    c.nbp = pad_nb(o.nb_max);
+    int rc = guarded(nullptr, [&]() {
+        c.lev.reserve(o.max_levels + 1);
+        c.partial = c.arena.alloc<double>((size_t)2 * 16 * kMaxGrid);
+        c.counter = c.arena.alloc<unsigned>(16);
+        c.dscratch = c.arena.alloc<double>(64);
+        c.iscratch = c.arena.alloc<int>(64);
+        AMG_HIP(hipMemsetAsync(c.counter, 0, 16 * sizeof(unsigned), c.stream));
+        AMG_HIP(hipHostMalloc((void **)&c.hsc, sizeof(CgScal), hipHostMallocDefault));
+        AMG_HIP(hipHostMalloc((void **)&c.hscr, 64 * sizeof(double), hipHostMallocDefault));
+        AMG_HIP(hipHostMalloc((void **)&c.hiscr, 64 * sizeof(int), hipHostMallocDefault));
+        AMG_HIP(hipHostMalloc((void **)&c.rsh, sizeof(RefScal), hipHostMallocDefault));
+        build_hierarchy(c, *A, *M, dirichlet);
+        form_dense_hessian(c, o.hess_levels > 0 ? o.hess_levels : c.L);
+        alloc_workspaces(c);
+        AMG_HIP(hipStreamSynchronize(c.stream));
+        return AMG_OK;
+    });
+    if (rc != AMG_OK) {
+        amg_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return AMG_OK;
+}
+
+int amg_destroy(amg_ctx *ctx) {
+    if (!ctx) return AMG_OK;
+    Ctx &c = ctx->c;
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    c.arena.free_all();
+    if (c.hsc) (void)hipHostFree(c.hsc);
+    if (c.hscr) (void)hipHostFree(c.hscr);
+    if (c.hiscr) (void)hipHostFree(c.hiscr);
+    if (c.rsh) (void)hipHostFree(c.rsh);
+    delete ctx;
+    return AMG_OK;
+}
+
+int state_solve(amg_ctx *ctx, int level, const double *u, double *y, int nb, amg_info *info) {
+    if (int e = check_vec_call(ctx ? &ctx->c : nullptr, level, nb)) return e;
+    if (!u || !y) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    return guarded(&c, [&]() {
+        auto t0 = clk::now();
+        c.st.reset();
+        const int n = c.lev[level].n;
+        return dispatch_nb(c.nbp, [&](auto tag) {
+            constexpr int NB = decltype(tag)::value;
+            Solver<NB> S(c);
+            S.template elem<0>(n, OpPack<NB>{c.pk_in, u, nb}, NoFin{}, nullptr);
+            S.state_solve(level, c.pk_in, c.pk_out, c.o.inner_rtol);
+            S.template elem<0>(n, OpUnpack<NB>{y, c.pk_out, nb}, NoFin{}, nullptr);
+            AMG_HIP(hipStreamSynchronize(c.stream));
+            fill_info(c, info, 1, ms_since(t0), 0);
+            return AMG_OK;
+        });
+    });
+}
+
+int adjoint_solve(amg_ctx *ctx, int level, const double *w, double *z, int nb, amg_info *info) {
+    if (int e = check_vec_call(ctx ? &ctx->c : nullptr, level, nb)) return e;
+    if (!w || !z) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    return guarded(&c, [&]() {
+        auto t0 = clk::now();
+        c.st.reset();
+        const int n = c.lev[level].n;
+        return dispatch_nb(c.nbp, [&](auto tag) {
+            constexpr int NB = decltype(tag)::value;
+            Solver<NB> S(c);
+            S.template elem<0>(n, OpPack<NB>{c.pk_in, w, nb}, NoFin{}, nullptr);
+            S.adjoint_solve(level, c.pk_in, c.pk_out, c.o.inner_rtol);
+            S.template elem<0>(n, OpUnpack<NB>{z, c.pk_out, nb}, NoFin{}, nullptr);
+            AMG_HIP(hipStreamSynchronize(c.stream));
+            fill_info(c, info, 1, ms_since(t0), 0);
+            return AMG_OK;
+        });
+    });
+}
+
+int hessian_apply(amg_ctx *ctx, int level, const double *u, double *Hu, int nb, amg_info *info) {
+    if (int e = check_vec_call(ctx ? &ctx->c : nullptr, level, nb)) return e;
+    if (!u || !Hu) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    return guarded(&c, [&]() {
+        auto t0 = clk::now();
+        c.st.reset();
+        const int n = c.lev[level].n;
+        return dispatch_nb(c.nbp, [&](auto tag) {
+            constexpr int NB = decltype(tag)::value;
+            Solver<NB> S(c);
+            S.template elem<0>(n, OpPack<NB>{c.pk_in, u, nb}, NoFin{}, nullptr);
+            S.hessian_apply(level, c.pk_in, c.pk_out, c.o.inner_rtol, nullptr);
+            S.template elem<0>(n, OpUnpack<NB>{Hu, c.pk_out, nb}, NoFin{}, nullptr);
+            AMG_HIP(hipStreamSynchronize(c.stream));
+            fill_info(c, info, 1, ms_since(t0), 0);
+            return AMG_OK;
+        });
+    });
+}
+
+int hessian_precond_apply(amg_ctx *ctx, const double *r, double *z, int nb, amg_info *info) {
+    if (int e = check_vec_call(ctx ? &ctx->c : nullptr, 0, nb)) return e;
+    if (!r || !z) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    return guarded(&c, [&]() {
+        auto t0 = clk::now();
+        c.st.reset();
+        const int n = c.N;
+        return dispatch_nb(c.nbp, [&](auto tag) {
+            constexpr int NB = decltype(tag)::value;
+            Solver<NB> S(c);
+            S.template elem<0>(n, OpPack<NB>{c.pk_in, r, nb}, NoFin{}, nullptr);
+            S.Bop(0, c.pk_in, c.pk_out);
+            S.template elem<0>(n, OpUnpack<NB>{z, c.pk_out, nb}, NoFin{}, nullptr);
+            AMG_HIP(hipStreamSynchronize(c.stream));
+            fill_info(c, info, 1, ms_since(t0), 0);
+            return AMG_OK;
+        });
+    });
+}
+
+int reduced_solve(amg_ctx *ctx, const double *yd, const double *u0, double *u, int nb, double rtol,
+                  amg_info *info) {
+    if (int e = check_vec_call(ctx ? &ctx->c : nullptr, 0, nb)) return e;
+    if (!yd || !u || !(rtol > 0.0)) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    return guarded(&c, [&]() {
+        auto t0 = clk::now();
+        c.st.reset();
+        const int n = c.N;
+        return dispatch_nb(c.nbp, [&](auto tag) {
+            constexpr int NB = decltype(tag)::value;
+            Solver<NB> S(c);
+            // b = K^T M_y y_d
+            S.template elem<0>(n, OpPack<NB>{c.pk_in, yd, nb}, NoFin{}, nullptr);
+            S.mass_apply(0, 1, c.pk_in, c.obq, nullptr, nullptr);
+            S.adjoint_solve(0, c.obq, c.ob, c.o.inner_rtol);
+            if (u0) S.template elem<0>(n, OpPack<NB>{c.ox, u0, nb}, NoFin{}, nullptr);
+            int it = 0;
+            const int rc = S.outer(c.ob, c.ox, u0 != nullptr, rtol, nb, &it);
+            S.template elem<0>(n, OpUnpack<NB>{u, c.ox, nb}, NoFin{}, nullptr);
+            AMG_HIP(hipStreamSynchronize(c.stream));
+            fill_info(c, info, nb, ms_since(t0), it);
+            if (info) {
+                S.read_sc(c.outer.sc);
+                for (int k = 0; k < nb; ++k) {
+                    const ColScal &cs = c.hsc->s[k];
+                    info[k].rel_resid = cs.bb > 0 ? std::sqrt(cs.rr / cs.bb) : 0.0;
+                    info[k].status_detail = cs.iters;
+                }
+            }
+            if (rc == AMG_ERR_NOCONV) c.err = "outer CG reached outer_maxit";
+            if (rc == AMG_ERR_INDEFINITE) c.err = "indefinite preconditioner";
+            return rc;
+        });
+    });
+}
+
+int reduced_objective(amg_ctx *ctx, const double *u, const double *yd, double *J_host, double *grad, int nb,
+                      amg_info *info) {
+    if (int e = check_vec_call(ctx ? &ctx->c : nullptr, 0, nb)) return e;
+    if (!u || !yd || (!J_host && !grad)) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    return guarded(&c, [&]() {
+        auto t0 = clk::now();
+        c.st.reset();
+        const int n = c.N;
+        return dispatch_nb(c.nbp, [&](auto tag) {
+            constexpr int NB = decltype(tag)::value;
+            Solver<NB> S(c);
+            LevelWs &w = c.ws[0];
+            S.template elem<0>(n, OpPack<NB>{c.pk_in, u, nb}, NoFin{}, nullptr);
+            S.template elem<0>(n, OpPack<NB>{c.obq, yd, nb}, NoFin{}, nullptr);
+            S.state_solve(0, c.pk_in, c.ox, c.o.inner_rtol);                                        // y = K u
+            S.template elem<0>(n, OpAxpby<NB>{c.ox, c.ox, c.obq, 1.0, -1.0}, NoFin{}, nullptr);     // e = y - y_d
+            S.mass_apply(0, 1, c.ox, c.ob, c.ox, c.dscratch);                                       // M_y e, e.M_y e
+            S.mass_apply(0, 0, c.pk_in, c.pk_out, c.pk_in, c.dscratch + 16);                        // u.M_u u
+            if (J_host) {
+                AMG_HIP(hipMemcpyAsync(c.hscr, c.dscratch, 32 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+                AMG_HIP(hipStreamSynchronize(c.stream));
+                for (int k = 0; k < nb; ++k) J_host[k] = 0.5 * c.hscr[k] + 0.5 * c.o.beta * c.hscr[16 + k];
+            }
+            if (grad) {
+                // grad = M (D A^{-1} M_y e) + beta M u
+                S.solve_A(0, c.ob, w.ht, c.o.inner_rtol);
+                const uint8_t *mk = c.has_mask ? c.mask0 : nullptr;
+                S.template spmv<double, 0>(c.lev[0].M, c.lev[0].M.v, GLin<NB>{w.ht, mk, c.pk_in, c.o.beta},
+                                           ELin<NB>{c.pk_out, nullptr, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr},
+                                           NoFin{}, nullptr);
+                S.template elem<0>(n, OpUnpack<NB>{grad, c.pk_out, nb}, NoFin{}, nullptr);
+            }
+            AMG_HIP(hipStreamSynchronize(c.stream));
+            fill_info(c, info, 1, ms_since(t0), 0);
+            return AMG_OK;
+        });
+    });
+}
+
+int amg_mass_apply(amg_ctx *ctx, int level, int which, const double *x, double *y, int nb) {
+    if (int e = check_vec_call(ctx ? &ctx->c : nullptr, level, nb)) return e;
+    if (!x || !y || which < 0 || which > 3) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    return guarded(&c, [&]() {
+        const int n = c.lev[level].n;
+        return dispatch_nb(c.nbp, [&](auto tag) {
+            constexpr int NB = decltype(tag)::value;
+            Solver<NB> S(c);
+            S.template elem<0>(n, OpPack<NB>{c.pk_in, x, nb}, NoFin{}, nullptr);
+            S.mass_apply(level, which, c.pk_in, c.pk_out, nullptr, nullptr);
+            S.template elem<0>(n, OpUnpack<NB>{y, c.pk_out, nb}, NoFin{}, nullptr);
+            AMG_HIP(hipStreamSynchronize(c.stream));
+            return AMG_OK;
+        });
+    });
+}
+
+int amg_mass_quad(amg_ctx *ctx, int which, const double *x, double *q_host, int nb) {
+    if (int e = check_vec_call(ctx ? &ctx->c : nullptr, 0, nb)) return e;
+    if (!x || !q_host || which < 0 || which > 1) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    return guarded(&c, [&]() {
+        const int n = c.N;
+        return dispatch_nb(c.nbp, [&](auto tag) {
+            constexpr int NB = decltype(tag)::value;
+            Solver<NB> S(c);
+            S.template elem<0>(n, OpPack<NB>{c.pk_in, x, nb}, NoFin{}, nullptr);
+            S.mass_apply(0, which, c.pk_in, c.pk_out, c.pk_in, c.dscratch);
+            AMG_HIP(hipMemcpyAsync(c.hscr, c.dscratch, 16 * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+            AMG_HIP(hipStreamSynchronize(c.stream));
+            for (int k = 0; k < nb; ++k) q_host[k] = c.hscr[k];
+            return AMG_OK;
+        });
+    });
+}
+
+int amg_num_levels(amg_ctx *ctx, int32_t *L, int32_t *ell) {
+    if (!ctx) return AMG_ERR_ARG;
+    if (L) *L = ctx->c.L;
+    if (ell) *ell = ctx->c.ell;
+    return AMG_OK;
+}
+
+int amg_level_size(amg_ctx *ctx, int level, int32_t *n, int32_t *nnzA, int32_t *nnzS, int32_t *nnzM) {
+    if (!ctx || level < 0 || level >= ctx->c.L) return AMG_ERR_ARG;
+    const Level &L = ctx->c.lev[level];
+    if (n) *n = L.n;
+    if (nnzA) *nnzA = L.A.nnz;
+    if (nnzS) *nnzS = L.S.nnz;
+    if (nnzM) *nnzM = L.M.nnz;
+    return AMG_OK;
+}
+
+int amg_copy_aggregates(amg_ctx *ctx, int level, int32_t *agg, uint8_t *root) {
+    if (!ctx || level < 0 || level >= ctx->c.L - 1) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    return guarded(&c, [&]() {
+        const Level &L = c.lev[level];
+        if (agg) AMG_HIP(hipMemcpy(agg, L.agg, sizeof(int) * L.n, hipMemcpyDeviceToHost));
+        if (root) AMG_HIP(hipMemcpy(root, L.root, L.n, hipMemcpyDeviceToHost));
+        return AMG_OK;
+    });
+}
+
+int amg_copy_csr(amg_ctx *ctx, int level, int which, int32_t *rowptr, int32_t *col, double *val) {
+    if (!ctx || level < 0 || level >= ctx->c.L || which < 0 || which > 3) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    const Level &L = c.lev[level];
+    const DCsr &m = which == 0 ? L.A : which == 1 ? L.S : which == 2 ? L.St : L.M;
+    if (!m.rp) return AMG_ERR_ARG;
+    return guarded(&c, [&]() {
+        AMG_HIP(hipStreamSynchronize(c.stream));
+        if (rowptr) AMG_HIP(hipMemcpy(rowptr, m.rp, sizeof(int) * (m.n + 1), hipMemcpyDeviceToHost));
+        if (col) AMG_HIP(hipMemcpy(col, m.ci, sizeof(int) * m.nnz, hipMemcpyDeviceToHost));
+        if (val) AMG_HIP(hipMemcpy(val, m.v, sizeof(double) * m.nnz, hipMemcpyDeviceToHost));
+        return AMG_OK;
+    });
+}
+
+int amg_copy_dense(amg_ctx *ctx, int which, int32_t *n, double *out) {
+    if (!ctx || which < 0 || which > 2) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    const int m = which == 0 ? c.nAinv : c.nH;
+    if (n) *n = m;
+    if (!out) return AMG_OK;
+    const double *src = which == 0 ? c.Ainv : which == 1 ? c.Hdense : c.Hinv;
+    return guarded(&c, [&]() {
+        AMG_HIP(hipStreamSynchronize(c.stream));
+        AMG_HIP(hipMemcpy(out, src, sizeof(double) * m * m, hipMemcpyDeviceToHost));
+        return AMG_OK;
+    });
+}
+
+int amg_set_hess_levels(amg_ctx *ctx, int ell) {
+    if (!ctx || ell < 1 || ell > ctx->c.L) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    return guarded(&c, [&]() {
+        form_dense_hessian(c, ell);
+        return AMG_OK;
+    });
+}
+
+int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double *ms_avg, double *bytes) {
+    if (int e = check_vec_call(ctx ? &ctx->c : nullptr, 0, nb)) return e;
+    if (which < 0 || which > 2 || (prec != 32 && prec != 64) || reps < 1 || !ms_avg) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    if (prec == 32 && c.o.inner_precision != 32) {
+        c.err = "float32 kernels need inner_precision = 32";
+        return AMG_ERR_ARG;
+    }
+    if (c.L < 2 && which > 0) return AMG_ERR_ARG;
+    return guarded(&c, [&]() {
+        return dispatch_nb(c.nbp, [&](auto tag) {
+            constexpr int NB = decltype(tag)::value;
+            Solver<NB> S(c);
+            const Level &L0 = c.lev[0];
+            const int n = L0.n;
+            const double sz = prec == 64 ? 8.0 : 4.0;
+            const double nbd = NB;
+            // algorithmic bytes: row pointers, (col, val) per stored entry, x read
+            // once, y written once (per column)
+            const double spmv_b = 4.0 * (n + 1) + (4.0 + sz) * L0.A.nnz + 2.0 * sz * n * nbd;
+            hipEvent_t e0, e1;
+            AMG_HIP(hipEventCreate(&e0));
+            AMG_HIP(hipEventCreate(&e1));
+            auto run = [&](auto tT) {
+                using T = decltype(tT);
+                VcWs<T> &v = vcws<T>(c.ws[0]);
+                auto once = [&]() {
+                    if (which == 0)
+                        S.template spmv<T, 0>(L0.A, avals<T>(L0.A), GPlain<T, NB>{v.x}, EStore<T, NB>{v.r}, NoFin{},
+                                              nullptr);
+                    else if (which == 1)
+                        S.template spmv<T, 0>(L0.A, avals<T>(L0.A), GPlain<T, NB>{v.x},
+                                              EPost<T, NB, false>{dl1inv<T>(L0), v.b, v.x, v.x2}, NoFin{}, nullptr);
+                    else
+                        S.template vcycle<T>(0, v.b, v.x2, nullptr, nullptr);
+                };
+                // defined inputs
+                AMG_HIP(hipMemsetAsync(v.x, 0, sizeof(T) * n * NB, c.stream));
+                AMG_HIP(hipMemsetAsync(v.b, 0, sizeof(T) * n * NB, c.stream));
+                once();
+                AMG_HIP(hipStreamSynchronize(c.stream));
+                AMG_HIP(hipEventRecord(e0, c.stream));
+                for (int r = 0; r < reps; ++r) once();
+                AMG_HIP(hipEventRecord(e1, c.stream));
+                AMG_HIP(hipEventSynchronize(e1));
+            };
+            if (prec == 64) run(double{});
+            else run(float{});
+            float ms = 0.f;
+            AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            *ms_avg = ms / reps;
+            if (bytes) {
+                if (which == 0) *bytes = spmv_b;
+                else if (which == 1) *bytes = spmv_b + sz * n * nbd /*b*/ + sz * n /*dinv*/;
+                else {
+                    double tot = 0.0;
+                    for (int l = 0; l < c.L - 1; ++l) {
+                        const Level &Lv = c.lev[l];
+                        const double nl = Lv.n, nc = c.lev[l + 1].n;
+                        const double a = 4.0 * (nl + 1) + (4.0 + sz) * Lv.A.nnz;
+                        // pre + residual (b, dinv in; x, r out), post (x, b, dinv in; out)
+                        tot += a + sz * nl * nbd * 3 + sz * nl;
+                        tot += a + sz * nl * nbd * 3 + sz * nl;
+                        // restriction and prolongation (+ add)
+                        tot += 4.0 * (nc + 1) + (4.0 + sz) * Lv.St.nnz + sz * (nl + nc) * nbd;
+                        tot += 4.0 * (nl + 1) + (4.0 + sz) * Lv.S.nnz + sz * (nc + 2 * nl) * nbd;
+                    }
+                    const double nc = c.nAinv;
+                    tot += 8.0 * nc * nc + 2.0 * sz * nc * nbd;
+                    *bytes = tot;
+                }
+            }
+            return AMG_OK;
+        });
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// The library context: the AMG hierarchy, dense coarse data and all solve
+// workspaces, sized once at setup for the widest batch.
+#pragma once
+
+#include <memory>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace amg {
+
+struct Level {
+    int n = 0;
+    DCsr A, S, St, M;           // A_j, S_j (n_j x n_{j+1}), S_j^T, mass M_j
+    double *dl1inv = nullptr;   // 1 / sum_k |a_ik|
+    float *dl1inv32 = nullptr;
+    double *mdinv = nullptr;    // 1 / diag(M_j)
+    int *agg = nullptr;         // level < L-1
+    uint8_t *root = nullptr;
+    const uint8_t *mask = nullptr;  // Dirichlet flags, level 0 only
+    double omega = 0.0, rho = 0.0;
+};
+
+template <typename T> struct CgWs {
+    T *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+    CgScal *sc = nullptr;
+    int pred = 0;  // iteration count of the previous solve (poll schedule)
+};
+
+template <typename T> struct VcWs {
+    T *b = nullptr, *x = nullptr, *r = nullptr, *x2 = nullptr;
+};
+
+struct LevelWs {
+    CgWs<double> in64, mass;
+    CgWs<float> in32;
+    VcWs<double> vc64;
+    VcWs<float> vc32;
+    // mixed refinement
+    double *rx = nullptr, *rr = nullptr;
+    float *b32 = nullptr, *d32 = nullptr;
+    // Hessian apply temporaries
+    double *hf = nullptr, *hy = nullptr, *hw = nullptr, *ht = nullptr;
+    // multilevel preconditioner
+    double *ml_in = nullptr, *ml_out = nullptr, *ml_mup = nullptr, *ml_mself = nullptr;
+    double *ml_z1 = nullptr, *ml_t = nullptr;
+};
+
+struct Stats {
+    long inner_solves = 0, inner_iters = 0, inner_max = 0, mass_iters = 0, refine = 0;
+    void reset() { *this = Stats(); }
+};
+
+struct Ctx {
+    hipStream_t stream = nullptr;
+    amg_opts o{};
+    Arena arena;
+    int N = 0;
+    int L = 0, ell = 0;
+    int nbp = 1;  // padded batch width of the workspaces
+    std::vector<Level> lev;
+    std::vector<LevelWs> ws;
+    // dense coarse data
+    double *Ainv = nullptr;  // inverse of A_{L-1}, row-major
+    int nAinv = 0;
+    double *Hdense = nullptr, *Hinv = nullptr;  // practical-form Hessian at level ell-1
+    int nH = 0;
+    // reductions (one stream: a single partial buffer and ticket suffice)
+    double *partial = nullptr;
+    unsigned *counter = nullptr;
+    double *dscratch = nullptr;  // small device scalars [64]
+    int *iscratch = nullptr;     // small device ints [64]
+    // host mirrors
+    CgScal *hsc = nullptr;       // pinned
+    double *hscr = nullptr;      // pinned [64]
+    int *hiscr = nullptr;        // pinned [64]
+    // outer CG workspace (level 0)
+    CgWs<double> outer;
+    double *ox = nullptr, *ob = nullptr, *obq = nullptr;
+    double *pk_in = nullptr, *pk_out = nullptr;  // packing buffers [N x nbp]
+    // refinement per-column data (device) and its pinned host mirror
+    RefScal *rsd = nullptr;
+    RefScal *rsh = nullptr;
+    Stats st;
+    std::string err;
+    bool has_mask = false;
+    uint8_t *mask0 = nullptr;
+};
+
+// setup.hip
+void build_hierarchy(Ctx &c, const amg_csr &A, const amg_csr &M, const uint8_t *dirichlet);
+void form_dense_hessian(Ctx &c, int ell);
+
+template <typename T> inline const T *avals(const DCsr &A) {
+    if constexpr (std::is_same_v<T, double>) return A.v;
+    else return A.v32;
+}
+template <typename T> inline const T *dl1inv(const Level &L) {
+    if constexpr (std::is_same_v<T, double>) return L.dl1inv;
+    else return L.dl1inv32;
+}
+template <typename T> inline VcWs<T> &vcws(LevelWs &w) {
+    if constexpr (std::is_same_v<T, double>) return w.vc64;
+    else return w.vc32;
+}
+
+}  // namespace amg

@@ -1,0 +1,724 @@
+// Solve-phase device code for gfx950: row-blocked CSR SpMV/SpMM with fused
+// epilogues, elementwise kernels with fused dot products, deterministic
+// two-stage grid reductions, and the dense coarse-level apply.
+//
+// Layout: every work vector is row-major [n x NB] (entry (i, c) at i*NB + c),
+// NB in {1, 2, 4, 8, 16}.  A row of a CSR matrix is handled by LPR =
+// max(8, NB) consecutive lanes of one wavefront: lane l works on column
+// c = l % NB and on the stored entries g, g + G, ... of the row, g = l / NB,
+// G = LPR / NB; the G partial sums are combined with wavefront shuffles.
+// For NB >= 8 every lane owns one column and the NB lanes of a row read the
+// same (col, val) entry, so the matrix is fetched once per row for all
+// right-hand sides while the x gathers are NB-contiguous.
+//
+// Reductions are deterministic: each workgroup reduces its contribution in a
+// fixed LDS tree, writes one partial per (quantity, column), and the last
+// workgroup to finish (atomic ticket) sums the partials in a fixed order and
+// runs a small "finalize" step on thread 0 (CG scalars, convergence flags).
+#pragma once
+
+#include "common.hpp"
+
+namespace amg {
+
+__device__ __forceinline__ int ceil_div_dev(int a, int b) { return (a + b - 1) / b; }
+__device__ __forceinline__ long ceil_div_dev_l(long a, long b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// per-column CG state kept in device memory
+struct ColScal {
+    double rho, alpha, beta, bb, tol2, rr, pq, rz;
+    int conv, iters, bad, pad;
+};
+
+struct CgScal {
+    ColScal s[16];
+    int all_conv;
+    int nb;          // live columns; columns >= nb are padding and stay frozen
+    int indefinite;  // outer CG: p.q <= 0 or r.z <= 0 met on a live column
+    int pad;
+};
+
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+    // Workgroups are dispatched round-robin over the XCDs; give each XCD a
+    // contiguous run of row blocks so neighbouring rows share an L2.
+    const int per = nblk / kXcd;
+    return (b % kXcd) * per + b / kXcd;
+}
+
+template <int NB> struct Geo {
+    static constexpr int LPR = NB >= 8 ? NB : 8;
+    static constexpr int G = LPR / NB;
+    static constexpr int RPB = kBlock / LPR;
+};
+
+template <int NV, int NB> struct Reducer {
+    double *partial;    // [NV*NB][gridDim.x]
+    unsigned *counter;  // zero between launches
+};
+
+constexpr int pow2floor(int x) {
+    int p = 1;
+    while (p * 2 <= x) p *= 2;
+    return p;
+}
+
+// Block reduction of acc[NV] over threads of equal column (t % NB), then the
+// grid-level ticket.  Returns true in the last workgroup, with the totals in
+// tot (LDS, valid for every thread of that workgroup).
+template <int NV, int NB>
+__device__ bool grid_reduce(const double (&acc)[NV], Reducer<NV, NB> r, double (&tot)[NV][NB]) {
+    __shared__ double red[NV][kBlock];
+    __shared__ int last;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) red[v][t] = acc[v];
+    __syncthreads();
+    for (int s = kBlock / 2; s >= NB; s >>= 1) {
+        if (t < s) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) red[v][t] += red[v][t + s];
+        }
+        __syncthreads();
+    }
+    const int nblk = gridDim.x;
+    if (t < NV * NB) r.partial[(size_t)t * nblk + blockIdx.x] = red[t / NB][t % NB];
+    __threadfence();
+    __syncthreads();
+    if (t == 0) last = (atomicAdd(r.counter, 1u) == (unsigned)nblk - 1u);
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    constexpr int Q = NV * NB;
+    constexpr int LPS = pow2floor(kBlock / Q);
+    const int q = t / LPS, sub = t % LPS;
+    double s = 0.0;
+    if (q < Q) {
+        const volatile double *pp = r.partial + (size_t)q * nblk;
+        for (int b = sub; b < nblk; b += LPS) s += pp[b];
+    }
+    red[0][t] = s;
+    __syncthreads();
+    for (int w = LPS / 2; w >= 1; w >>= 1) {
+        if (q < Q && sub < w) red[0][t] += red[0][t + w];
+        __syncthreads();
+    }
+    if (q < Q && sub == 0) tot[q / NB][q % NB] = red[0][t];
+    __syncthreads();
+    if (t == 0) *r.counter = 0u;
+    return true;
+}
+
+struct NoFin {
+    template <int NV, int NB> __device__ void operator()(double (&)[NV][NB]) const {}
+};
+
+// ---------------------------------------------------------------------------
+// CSR SpMV / SpMM with a gather functor (how x_k is formed) and an epilogue
+// functor (what is written for row i); optional fused reductions.
+template <typename T, int NB, int NV, class GX, class EP, class FIN>
+__global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__restrict__ rp,
+                                                      const int *__restrict__ ci,
+                                                      const T *__restrict__ av, GX gx, EP ep,
+                                                      Reducer<(NV > 0 ? NV : 1), NB> red, FIN fin,
+                                                      const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    using Gm = Geo<NB>;
+    const int t = threadIdx.x;
+    const int lane = t % Gm::LPR, c = lane % NB, g = lane / NB, rl = t / Gm::LPR;
+    const int nblk = gridDim.x, b = xcd_block(blockIdx.x, nblk);
+    const int span = ceil_div_dev(nrows, nblk * Gm::RPB) * Gm::RPB;
+    const int r0 = b * span;
+    const int r1 = min(nrows, r0 + span);
+    gx.prep(c);
+    ep.prep(c);
+    constexpr int NVA = NV > 0 ? NV : 1;
+    double acc[NVA];
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) acc[v] = 0.0;
+    for (int base = r0; base < r1; base += Gm::RPB) {
+        const int row = base + rl;
+        T sum = T(0);
+        if (row < r1) {
+            const int p1 = rp[row + 1];
+            for (int p = rp[row] + g; p < p1; p += Gm::G) sum += av[p] * gx(ci[p], c);
+        }
+#pragma unroll
+        for (int off = NB; off < Gm::LPR; off <<= 1) sum += __shfl_xor(sum, off);
+        if (row < r1 && g == 0) ep(row, c, sum, acc);
+    }
+    if constexpr (NV > 0) {
+        __shared__ double tot[NV][NB];
+        if (grid_reduce<NV, NB>(acc, red, tot)) {
+            if (t == 0) fin(tot);
+        }
+    }
+}
+
+// Elementwise kernel over n rows x NB columns with fused reductions.
+template <int NB, int NV, class OP, class FIN>
+__global__ __launch_bounds__(kBlock) void elem_kernel(int n, OP op, Reducer<(NV > 0 ? NV : 1), NB> red,
+                                                      FIN fin, const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    const int t = threadIdx.x, c = t % NB;
+    const int nblk = gridDim.x, b = xcd_block(blockIdx.x, nblk);
+    const long total = (long)n * NB;
+    const long span = (long)ceil_div_dev_l(total, (long)nblk * kBlock) * kBlock;
+    const long e0 = (long)b * span;
+    const long e1 = total < e0 + span ? total : e0 + span;
+    op.prep(c);
+    constexpr int NVA = NV > 0 ? NV : 1;
+    double acc[NVA];
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) acc[v] = 0.0;
+    for (long e = e0 + t; e < e1; e += kBlock) op((int)(e / NB), c, acc);
+    if constexpr (NV > 0) {
+        __shared__ double tot[NV][NB];
+        if (grid_reduce<NV, NB>(acc, red, tot)) {
+            if (t == 0) fin(tot);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// gathers
+template <typename T, int NB> struct GPlain {  // x_k
+    const T *x;
+    __device__ void prep(int) {}
+    __device__ T operator()(int k, int c) const { return x[(size_t)k * NB + c]; }
+};
+
+template <typename T, int NB> struct GDinvB {  // x_k = dinv_k b_k (first pre-sweep from zero)
+    const T *dinv;
+    const T *b;
+    __device__ void prep(int) {}
+    __device__ T operator()(int k, int c) const { return dinv[k] * b[(size_t)k * NB + c]; }
+};
+
+template <typename T, int NB> struct GZBP {  // p_k = z_k + beta_c pold_k
+    const T *z;
+    const T *pold;
+    const CgScal *sc;
+    T beta;
+    __device__ void prep(int c) { beta = (T)sc->s[c].beta; }
+    __device__ T operator()(int k, int c) const {
+        return z[(size_t)k * NB + c] + beta * pold[(size_t)k * NB + c];
+    }
+};
+
+// x_k = keep_k a_k + s b_k with keep_k = (mask == null || mask[k] == 0)
+template <int NB> struct GLin {
+    const double *a;
+    const uint8_t *mask;
+    const double *b;
+    double s;
+    __device__ void prep(int) {}
+    __device__ double operator()(int k, int c) const {
+        double v = a[(size_t)k * NB + c];
+        if (mask && mask[k]) v = 0.0;
+        if (b) v += s * b[(size_t)k * NB + c];
+        return v;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// epilogues
+template <typename T, int NB> struct EStore {  // y_i = sum
+    T *y;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, T s, double (&)[NV]) const {
+        y[(size_t)i * NB + c] = s;
+    }
+};
+
+template <typename T, int NB> struct EAdd {  // y_i += sum
+    T *y;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, T s, double (&)[NV]) const {
+        y[(size_t)i * NB + c] += s;
+    }
+};
+
+// pre-smoothing + residual: x_i = dinv_i b_i, r_i = b_i - (A x)_i
+template <typename T, int NB> struct EPre {
+    const T *dinv;
+    const T *b;
+    T *x;
+    T *r;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, T s, double (&)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        const T bi = b[o];
+        x[o] = dinv[i] * bi;
+        r[o] = bi - s;
+    }
+};
+
+// post-smoothing: out_i = x_i + dinv_i (b_i - (A x)_i); optionally acc += b_i out_i
+template <typename T, int NB, bool DOT> struct EPost {
+    const T *dinv;
+    const T *b;
+    const T *x;
+    T *out;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, T s, double (&acc)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        const T bi = b[o];
+        const T v = x[o] + dinv[i] * (bi - s);
+        out[o] = v;
+        if constexpr (DOT) acc[0] += (double)bi * (double)v;
+    }
+};
+
+// CG search direction and operator: p_i = z_i + beta pold_i, q_i = (A p)_i, acc p.q
+template <typename T, int NB> struct ECgQ {
+    const T *z;
+    const T *pold;
+    T *p;
+    T *q;
+    const CgScal *sc;
+    T beta;
+    __device__ void prep(int c) { beta = (T)sc->s[c].beta; }
+    template <int NV> __device__ void operator()(int i, int c, T s, double (&acc)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        const T pi = z[o] + beta * pold[o];
+        p[o] = pi;
+        q[o] = s;
+        acc[0] += (double)pi * (double)s;
+    }
+};
+
+// out_i = s1 keep_i sum + s2 y_i + s3 w_i (+ acc x_i out_i)
+template <int NB> struct ELin {
+    double *out;
+    const uint8_t *mask;
+    double s1;
+    const double *y;
+    double s2;
+    const double *w;
+    double s3;
+    const double *dotx;  // acc[0] += dotx_i * out_i when not null
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, double s, double (&acc)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        double v = (mask && mask[i]) ? 0.0 : s1 * s;
+        if (y) v += s2 * y[o];
+        if (w) v += s3 * w[o];
+        out[o] = v;
+        if constexpr (NV > 0) {
+            if (dotx) acc[0] += dotx[o] * v;
+        }
+    }
+};
+
+// residual for refinement: r_i = f_i - (A x)_i (FP64), acc r.r
+template <int NB> struct EResid {
+    const double *f;
+    double *r;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, double s, double (&acc)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        const double v = f[o] - s;
+        r[o] = v;
+        acc[0] += v * v;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// finalize steps (thread 0 of the last workgroup)
+template <int NB> struct FinAlpha {  // alpha = rho / p.q on live columns
+    CgScal *sc;
+    int outer;  // 1: flag indefiniteness instead of treating it as breakdown
+    __device__ void operator()(double (&tot)[1][NB]) const {
+        for (int c = 0; c < NB; ++c) {
+            ColScal &s = sc->s[c];
+            s.pq = tot[0][c];
+            if (s.conv) {
+                s.alpha = 0.0;
+                continue;
+            }
+            if (!(s.pq > 0.0)) {
+                s.alpha = 0.0;
+                s.bad = 1;
+                if (outer) sc->indefinite = 1;
+                s.conv = 1;
+                continue;
+            }
+            s.alpha = s.rho / s.pq;
+        }
+        int all = 1;
+        for (int c = 0; c < NB; ++c) all &= sc->s[c].conv;
+        sc->all_conv = all;
+    }
+};
+
+template <int NB, bool JAC> struct FinUpd {  // convergence test on r.r (and Jacobi beta)
+    CgScal *sc;
+    __device__ void operator()(double (&tot)[JAC ? 2 : 1][NB]) const {
+        int all = 1;
+        for (int c = 0; c < NB; ++c) {
+            ColScal &s = sc->s[c];
+            if (!s.conv) {
+                s.iters += 1;
+                s.rr = tot[0][c];
+                if (s.rr <= s.tol2) s.conv = 1;
+                if constexpr (JAC) {
+                    const double rz = tot[1][c];
+                    s.rz = rz;
+                    s.beta = s.conv ? 0.0 : rz / s.rho;
+                    s.rho = rz;
+                }
+            }
+            all &= s.conv;
+        }
+        sc->all_conv = all;
+    }
+};
+
+template <int NB> struct FinBeta {  // beta = r.z / rho after the preconditioner
+    CgScal *sc;
+    int outer;
+    __device__ void operator()(double (&tot)[1][NB]) const {
+        for (int c = 0; c < NB; ++c) {
+            ColScal &s = sc->s[c];
+            if (s.conv) {
+                s.beta = 0.0;
+                continue;
+            }
+            const double rz = tot[0][c];
+            if (!(rz > 0.0)) {
+                s.bad = 1;
+                if (outer) sc->indefinite = 1;
+                s.conv = 1;
+                s.beta = 0.0;
+                continue;
+            }
+            s.rz = rz;
+            s.beta = rz / s.rho;
+            s.rho = rz;
+        }
+        int all = 1;
+        for (int c = 0; c < NB; ++c) all &= sc->s[c].conv;
+        sc->all_conv = all;
+    }
+};
+
+// initial state: bb = b.b, tol2 = rtol^2 bb, conv = (bb == 0); Jacobi: rho = r.z
+template <int NB, bool JAC> struct FinInit {
+    CgScal *sc;
+    double rtol;
+    int nlive;
+    __device__ void operator()(double (&tot)[JAC ? 2 : 1][NB]) const {
+        sc->nb = nlive;
+        int all = 1;
+        for (int c = 0; c < NB; ++c) {
+            ColScal &s = sc->s[c];
+            s.bb = tot[0][c];
+            s.tol2 = rtol * rtol * s.bb;
+            s.rr = s.bb;
+            s.iters = 0;
+            s.bad = 0;
+            s.alpha = 0.0;
+            s.beta = 0.0;
+            s.rho = 1.0;
+            s.conv = (c >= sc->nb) || !(s.bb > 0.0);
+            if constexpr (JAC) {
+                s.rz = tot[1][c];
+                s.rho = s.conv ? 1.0 : s.rz;
+            }
+            all &= s.conv;
+        }
+        sc->all_conv = all;
+        sc->indefinite = 0;
+    }
+};
+
+template <int NB> struct FinStore {  // plain reduction result into out[v*NB + c]
+    double *out;
+    template <int NV> __device__ void operator()(double (&tot)[NV][NB]) const {
+        for (int v = 0; v < NV; ++v)
+            for (int c = 0; c < NB; ++c) out[v * NB + c] = tot[v][c];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// elementwise operations
+template <typename T, int NB, bool JAC> struct OpInit {  // r = b, x = 0, pold = 0 (Jacobi: z = dinv r)
+    const T *b;
+    T *r, *x, *pold, *z;
+    const T *dinv;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, double (&acc)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        const T v = b[o];
+        r[o] = v;
+        x[o] = T(0);
+        pold[o] = T(0);
+        acc[0] += (double)v * (double)v;
+        if constexpr (JAC) {
+            const T zz = dinv[i] * v;
+            z[o] = zz;
+            acc[1] += (double)v * (double)zz;
+        }
+    }
+};
+
+template <typename T, int NB, bool JAC> struct OpUpd {  // x += a p, r -= a q (Jacobi: z = dinv r)
+    T *x, *r, *z;
+    const T *p, *q, *dinv;
+    const CgScal *sc;
+    T a;
+    int live;
+    __device__ void prep(int c) {
+        a = (T)sc->s[c].alpha;
+        live = !sc->s[c].conv;
+    }
+    template <int NV> __device__ void operator()(int i, int c, double (&acc)[NV]) const {
+        if (!live) return;
+        const size_t o = (size_t)i * NB + c;
+        x[o] += a * p[o];
+        const T rv = r[o] - a * q[o];
+        r[o] = rv;
+        acc[0] += (double)rv * (double)rv;
+        if constexpr (JAC) {
+            const T zz = dinv[i] * rv;
+            z[o] = zz;
+            acc[1] += (double)rv * (double)zz;
+        }
+    }
+};
+
+template <int NB> struct OpDot {  // acc[v] += x_v . y_v (up to 2 pairs)
+    const double *x0, *y0, *x1, *y1;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, double (&acc)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        acc[0] += x0[o] * y0[o];
+        if constexpr (NV > 1) acc[1] += x1[o] * y1[o];
+    }
+};
+
+template <int NB> struct OpAxpby {  // out = a x + b y (a, b per column or scalar), out may alias x or y
+    double *out;
+    const double *x, *y;
+    double a, b;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, double (&)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        double v = a * x[o];
+        if (y) v += b * y[o];
+        out[o] = v;
+    }
+};
+
+// outer CG direction update: p = z + beta_c p
+template <int NB> struct OpPUpd {
+    double *p;
+    const double *z;
+    const CgScal *sc;
+    double beta;
+    int live;
+    __device__ void prep(int c) {
+        beta = sc->s[c].beta;
+        live = !sc->s[c].conv;
+    }
+    template <int NV> __device__ void operator()(int i, int c, double (&)[NV]) const {
+        if (!live) return;
+        const size_t o = (size_t)i * NB + c;
+        p[o] = z[o] + beta * p[o];
+    }
+};
+
+// FP64 refinement state per column, kept on the device
+struct RefScal {
+    double fn[16];  // ||f||
+    double s[16];   // current ||r||
+    int live[16];
+    int nlive;
+    int stagnated;
+    double rtol;
+};
+
+template <int NB> struct OpCopyNorm {  // r = f, x = 0, acc f.f
+    const double *f;
+    double *r, *x;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, double (&acc)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        const double v = f[o];
+        r[o] = v;
+        x[o] = 0.0;
+        acc[0] += v * v;
+    }
+};
+
+template <int NB> struct FinRefInit {
+    RefScal *rs;
+    double rtol;
+    int nlive;
+    __device__ void operator()(double (&tot)[1][NB]) const {
+        int nl = 0;
+        rs->rtol = rtol;
+        rs->stagnated = 0;
+        for (int c = 0; c < 16; ++c) {
+            const double fn = c < NB ? sqrt(tot[0][c]) : 0.0;
+            rs->fn[c] = fn;
+            rs->s[c] = fn;
+            rs->live[c] = (c < nlive) && fn > 0.0;
+            nl += rs->live[c];
+        }
+        rs->nlive = nl;
+    }
+};
+
+// after r = f - A x: a live column finishes at ||r|| <= rtol ||f||; it has
+// stagnated when the residual did not at least halve
+template <int NB> struct FinRefine {
+    RefScal *rs;
+    __device__ void operator()(double (&tot)[1][NB]) const {
+        int nl = 0;
+        for (int c = 0; c < NB; ++c) {
+            if (!rs->live[c]) continue;
+            const double r = sqrt(tot[0][c]);
+            if (r <= rs->rtol * rs->fn[c]) {
+                rs->live[c] = 0;
+                continue;
+            }
+            if (!(r <= 0.5 * rs->s[c])) rs->stagnated = 1;
+            rs->s[c] = r;
+            ++nl;
+        }
+        rs->nlive = nl;
+    }
+};
+
+template <int NB> struct OpRefAdd {  // x64 += s_c d32 on live columns
+    double *x;
+    const float *d;
+    const RefScal *rs;
+    double sc;
+    int on;
+    __device__ void prep(int c) {
+        sc = rs->s[c];
+        on = rs->live[c];
+    }
+    template <int NV> __device__ void operator()(int i, int c, double (&)[NV]) const {
+        if (!on) return;
+        const size_t o = (size_t)i * NB + c;
+        x[o] += sc * (double)d[o];
+    }
+};
+
+template <int NB> struct OpCastScale {  // b32 = fp32(r / s_c), zero on finished columns
+    float *b;
+    const double *r;
+    const RefScal *rs;
+    double inv;
+    __device__ void prep(int c) { inv = rs->live[c] ? 1.0 / rs->s[c] : 0.0; }
+    template <int NV> __device__ void operator()(int i, int c, double (&)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        b[o] = (float)(r[o] * inv);
+    }
+};
+
+// outer CG start: bb = b.b, rr = r.r
+template <int NB> struct FinOuterInit {
+    CgScal *sc;
+    double rtol;
+    int nlive;
+    __device__ void operator()(double (&tot)[2][NB]) const {
+        sc->nb = nlive;
+        sc->indefinite = 0;
+        int all = 1;
+        for (int c = 0; c < NB; ++c) {
+            ColScal &s = sc->s[c];
+            s.bb = tot[0][c];
+            s.rr = tot[1][c];
+            s.tol2 = rtol * rtol * s.bb;
+            s.iters = 0;
+            s.bad = 0;
+            s.alpha = s.beta = 0.0;
+            s.rho = 1.0;
+            s.conv = (c >= nlive) || !(s.bb > 0.0) || s.rr <= s.tol2;
+            all &= s.conv;
+        }
+        sc->all_conv = all;
+    }
+};
+
+template <int NB> struct FinRho {  // rho = r.z at the start of the outer CG
+    CgScal *sc;
+    __device__ void operator()(double (&tot)[1][NB]) const {
+        for (int c = 0; c < NB; ++c) {
+            ColScal &s = sc->s[c];
+            if (s.conv) continue;
+            const double rz = tot[0][c];
+            if (!(rz > 0.0)) {
+                s.bad = 1;
+                sc->indefinite = 1;
+                continue;
+            }
+            s.rho = rz;
+            s.rz = rz;
+        }
+    }
+};
+
+template <int NB> struct OpPack {  // out[i*NB + c] = c < nb ? in[i*nb + c] : 0
+    double *out;
+    const double *in;
+    int nb;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, double (&)[NV]) const {
+        out[(size_t)i * NB + c] = c < nb ? in[(size_t)i * nb + c] : 0.0;
+    }
+};
+
+template <int NB> struct OpUnpack {  // out[i*nb + c] = in[i*NB + c], c < nb
+    double *out;
+    const double *in;
+    int nb;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, double (&)[NV]) const {
+        if (c < nb) out[(size_t)i * nb + c] = in[(size_t)i * NB + c];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// dense coarse-level apply: x = Inv b (Inv row-major n x n, FP64), one
+// wavefront per row, FP64 accumulation.
+template <typename T, int NB>
+__global__ __launch_bounds__(kBlock) void dense_apply_kernel(int n, const double *__restrict__ inv,
+                                                             const T *__restrict__ b, T *__restrict__ x,
+                                                             const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    const int lane = threadIdx.x % 64;
+    const int w = (blockIdx.x * kBlock + threadIdx.x) / 64;
+    const int nw = gridDim.x * kBlock / 64;
+    for (int i = w; i < n; i += nw) {
+        double acc[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[c] = 0.0;
+        const double *row = inv + (size_t)i * n;
+        for (int k = lane; k < n; k += 64) {
+            const double a = row[k];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) acc[c] += a * (double)b[(size_t)k * NB + c];
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            double v = acc[c];
+            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+            acc[c] = v;
+        }
+        if (lane < NB) {
+            double v = acc[0];
+#pragma unroll
+            for (int c = 1; c < NB; ++c)
+                if (lane == c) v = acc[c];
+            x[(size_t)i * NB + lane] = (T)v;
+        }
+    }
+}
+
+}  // namespace amg

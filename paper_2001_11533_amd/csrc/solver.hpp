@@ -1,0 +1,332 @@
+// Solve phase: V-cycle, inner CG (FP64, or float32 inside FP64 refinement),
+// mass-matrix CG, Hessian action, the multilevel Hessian preconditioner in
+// practical form and the outer CG (paper, Sections 2, 3.2 and 5.2).
+//
+// Every vector is [n x NB] with NB the padded batch width.  Columns converge
+// and freeze independently.  Kernels of a CG iteration return at once when
+// every column has converged, so the host only polls the convergence flags
+// from the iteration count of the previous solve at that level onwards.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+
+#include "ctx.hpp"
+
+namespace amg {
+
+template <int NB> struct Solver {
+    Ctx &c;
+    hipStream_t s;
+    explicit Solver(Ctx &cc) : c(cc), s(cc.stream) {}
+
+    // ---------------- launch helpers ----------------
+    template <typename T, int NV, class GX, class EP, class FIN>
+    void spmv(const DCsr &A, const T *vals, GX gx, EP ep, FIN fin, const int *stop) {
+        const int g = grid_rows(A.n, Geo<NB>::RPB);
+        Reducer<(NV > 0 ? NV : 1), NB> red{c.partial, c.counter};
+        hipLaunchKernelGGL((spmv_kernel<T, NB, NV, GX, EP, FIN>), dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci,
+                           vals, gx, ep, red, fin, stop);
+    }
+
+    template <int NV, class OP, class FIN> void elem(int n, OP op, FIN fin, const int *stop) {
+        const int g = grid_rows((long)n * NB, kBlock);
+        Reducer<(NV > 0 ? NV : 1), NB> red{c.partial, c.counter};
+        hipLaunchKernelGGL((elem_kernel<NB, NV, OP, FIN>), dim3(g), dim3(kBlock), 0, s, n, op, red, fin, stop);
+    }
+
+    template <typename T> void dense_apply(int n, const double *inv, const T *b, T *x, const int *stop) {
+        const int waves = std::max(1, std::min(n, 1024));
+        const int g = ceil_div(waves * 64, kBlock);
+        hipLaunchKernelGGL((dense_apply_kernel<T, NB>), dim3(g), dim3(kBlock), 0, s, n, inv, b, x, stop);
+    }
+
+    void read_sc(const CgScal *d) {
+        AMG_HIP(hipMemcpyAsync(c.hsc, d, sizeof(CgScal), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipStreamSynchronize(s));
+    }
+
+    void read_rs() {
+        AMG_HIP(hipMemcpyAsync(c.rsh, c.rsd, sizeof(RefScal), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipStreamSynchronize(s));
+    }
+
+    template <typename T> CgWs<T> &inws(int l) {
+        if constexpr (std::is_same_v<T, double>) return c.ws[l].in64;
+        else return c.ws[l].in32;
+    }
+
+    // ---------------- V-cycle (AMG preconditioner for A_j) ----------------
+    // z = V_j b: one l1-Jacobi sweep from zero, residual, restriction with
+    // S^T, recursion, prolongation with S, one l1-Jacobi sweep; the coarsest
+    // level is solved with the dense inverse.  With sc the last kernel also
+    // forms r.z for the CG (b is the CG residual) and the CG's beta.
+    template <typename T> void vcycle(int j, const T *b, T *z, CgScal *sc, const int *stop) {
+        const int Lc = c.L - 1;
+        const T *bl = b;
+        for (int l = j; l < Lc; ++l) {
+            Level &Lv = c.lev[l];
+            VcWs<T> &v = vcws<T>(c.ws[l]);
+            spmv<T, 0>(Lv.A, avals<T>(Lv.A), GDinvB<T, NB>{dl1inv<T>(Lv), bl},
+                       EPre<T, NB>{dl1inv<T>(Lv), bl, v.x, v.r}, NoFin{}, stop);
+            T *bn = vcws<T>(c.ws[l + 1]).b;
+            spmv<T, 0>(Lv.St, avals<T>(Lv.St), GPlain<T, NB>{v.r}, EStore<T, NB>{bn}, NoFin{}, stop);
+            bl = bn;
+        }
+        T *xc = (j == Lc) ? z : vcws<T>(c.ws[Lc]).x;
+        dense_apply<T>(c.nAinv, c.Ainv, bl, xc, stop);
+        for (int l = Lc - 1; l >= j; --l) {
+            Level &Lv = c.lev[l];
+            VcWs<T> &v = vcws<T>(c.ws[l]);
+            const T *e = (l + 1 == Lc) ? vcws<T>(c.ws[Lc]).x : vcws<T>(c.ws[l + 1]).x2;
+            spmv<T, 0>(Lv.S, avals<T>(Lv.S), GPlain<T, NB>{e}, EAdd<T, NB>{v.x}, NoFin{}, stop);
+            const T *bb = (l == j) ? b : v.b;
+            T *out = (l == j) ? z : v.x2;
+            if (l == j && sc)
+                spmv<T, 1>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x},
+                           EPost<T, NB, true>{dl1inv<T>(Lv), bb, v.x, out}, FinBeta<NB>{sc, 0}, stop);
+            else
+                spmv<T, 0>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x},
+                           EPost<T, NB, false>{dl1inv<T>(Lv), bb, v.x, out}, NoFin{}, stop);
+        }
+        AMG_HIP(hipGetLastError());
+    }
+
+    // ---------------- conjugate gradients ----------------
+    // JAC: Jacobi preconditioner (mass matrices), else the V-cycle from level j.
+    // Returns the largest iteration count over the columns.
+    template <typename T, bool JAC>
+    int cg(int j, const DCsr &A, const T *vals, const double *mdinv, CgWs<T> &w, const T *b, T *x, double rtol,
+           int maxit, int nlive) {
+        const int n = A.n;
+        T *pold = w.p0, *pnew = w.p1;
+        const int *stop = &w.sc->all_conv;
+        const T *dinv = nullptr;
+        if constexpr (JAC) dinv = mdinv;
+        elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, pold, w.z, dinv}, FinInit<NB, JAC>{w.sc, rtol, nlive},
+                          nullptr);
+        if constexpr (!JAC) vcycle<T>(j, w.r, w.z, w.sc, stop);
+        int it = 0;
+        int next = std::max(1, w.pred);
+        const int every = std::max(1, c.o.check_every);
+        while (true) {
+            spmv<T, 1>(A, vals, GZBP<T, NB>{w.z, pold, w.sc}, ECgQ<T, NB>{w.z, pold, pnew, w.q, w.sc},
+                       FinAlpha<NB>{w.sc, 0}, stop);
+            elem<JAC ? 2 : 1>(n, OpUpd<T, NB, JAC>{x, w.r, w.z, pnew, w.q, dinv, w.sc}, FinUpd<NB, JAC>{w.sc},
+                              stop);
+            if constexpr (!JAC) vcycle<T>(j, w.r, w.z, w.sc, stop);
+            std::swap(pold, pnew);
+            ++it;
+            if (it >= next || it >= maxit) {
+                read_sc(w.sc);
+                if (c.hsc->all_conv) break;
+                if (it >= maxit) {
+                    w.pred = it;
+                    fail(AMG_ERR_NOCONV,
+                         std::string(JAC ? "mass" : "inner") + " CG did not converge at level " + std::to_string(j));
+                }
+                next = it + every;
+            }
+        }
+        int mx = 0;
+        for (int col = 0; col < NB; ++col) {
+            if (c.hsc->s[col].bad)
+                fail(AMG_ERR_NOCONV,
+                     std::string(JAC ? "mass" : "inner") + " CG breakdown at level " + std::to_string(j));
+            mx = std::max(mx, c.hsc->s[col].iters);
+        }
+        w.pred = mx;
+        return mx;
+    }
+
+    // ---------------- solves with A_j ----------------
+    void solve_A(int j, const double *f, double *x, double rtol) {
+        if (j == c.L - 1) {
+            dense_apply<double>(c.nAinv, c.Ainv, f, x, nullptr);
+            AMG_HIP(hipGetLastError());
+            return;
+        }
+        if (c.o.inner_precision == 32) {
+            solve_A_mixed(j, f, x, rtol);
+            return;
+        }
+        Level &L = c.lev[j];
+        const int it = cg<double, false>(j, L.A, L.A.v, nullptr, c.ws[j].in64, f, x, rtol, c.o.inner_maxit, NB);
+        c.st.inner_solves++;
+        c.st.inner_iters += it;
+        c.st.inner_max = std::max<long>(c.st.inner_max, it);
+    }
+
+    // FP64 iterative refinement around the float32 CG:
+    //   s = ||r||, d = CG32(fp32(r / s)), x += s d, r = f - A x (FP64),
+    // until ||r|| <= rtol ||f|| per column.
+    void solve_A_mixed(int j, const double *f, double *x, double rtol) {
+        Level &L = c.lev[j];
+        LevelWs &w = c.ws[j];
+        const int n = L.n;
+        elem<1>(n, OpCopyNorm<NB>{f, w.rr, x}, FinRefInit<NB>{c.rsd, rtol, NB}, nullptr);
+        read_rs();
+        int steps = 0;
+        while (c.rsh->nlive > 0) {
+            if (steps >= c.o.refine_maxit) fail(AMG_ERR_NOCONV, "refinement did not converge");
+            elem<0>(n, OpCastScale<NB>{w.b32, w.rr, c.rsd}, NoFin{}, nullptr);
+            const int it = cg<float, false>(j, L.A, L.A.v32, nullptr, w.in32, w.b32, w.d32, c.o.inner32_rtol,
+                                            c.o.inner_maxit, NB);
+            c.st.inner_iters += it;
+            c.st.inner_max = std::max<long>(c.st.inner_max, it);
+            elem<0>(n, OpRefAdd<NB>{x, w.d32, c.rsd}, NoFin{}, nullptr);
+            spmv<double, 1>(L.A, L.A.v, GPlain<double, NB>{x}, EResid<NB>{f, w.rr}, FinRefine<NB>{c.rsd}, nullptr);
+            read_rs();
+            ++steps;
+            c.st.refine++;
+            if (c.rsh->stagnated) fail(AMG_ERR_NOCONV, "refinement stagnated at level " + std::to_string(j));
+        }
+        c.st.inner_solves++;
+    }
+
+    void mass_solve(int j, const double *b, double *x) {
+        Level &L = c.lev[j];
+        const int it =
+            cg<double, true>(j, L.M, L.M.v, L.mdinv, c.ws[j].mass, b, x, c.o.mass_rtol, c.o.mass_maxit, NB);
+        c.st.mass_iters += it;
+    }
+
+    // y = M_which x at level j (0: M_u, 1: M_y = DMD, 2: M_yu = DM, 3: M_yu^T = MD);
+    // with dotx, dots[c] = dotx_c . y_c (device)
+    void mass_apply(int j, int which, const double *x, double *y, const double *dotx, double *dots) {
+        Level &L = c.lev[j];
+        const uint8_t *mk = (j == 0 && c.has_mask) ? c.mask0 : nullptr;
+        const uint8_t *gm = (which == 1 || which == 3) ? mk : nullptr;
+        const uint8_t *em = (which == 1 || which == 2) ? mk : nullptr;
+        if (dotx)
+            spmv<double, 1>(L.M, L.M.v, GLin<NB>{x, gm, nullptr, 0.0},
+                            ELin<NB>{y, em, 1.0, nullptr, 0.0, nullptr, 0.0, dotx}, FinStore<NB>{dots}, nullptr);
+        else
+            spmv<double, 0>(L.M, L.M.v, GLin<NB>{x, gm, nullptr, 0.0},
+                            ELin<NB>{y, em, 1.0, nullptr, 0.0, nullptr, 0.0, nullptr}, NoFin{}, nullptr);
+        AMG_HIP(hipGetLastError());
+    }
+
+    // y = K_j u = A_j^{-1} M_yu u
+    void state_solve(int j, const double *u, double *y, double rtol) {
+        LevelWs &w = c.ws[j];
+        mass_apply(j, 2, u, w.hf, nullptr, nullptr);
+        solve_A(j, w.hf, y, rtol);
+    }
+
+    // z = K_j^T w = M_yu^T A_j^{-1} w
+    void adjoint_solve(int j, const double *wv, double *z, double rtol) {
+        LevelWs &w = c.ws[j];
+        solve_A(j, wv, w.ht, rtol);
+        mass_apply(j, 3, w.ht, z, nullptr, nullptr);
+    }
+
+    // Hu = K^T M_y K u + beta M_u u, formed as M (D t + beta u) with
+    // t = A^{-1} M_y A^{-1} M_yu u; with rminus, Hu = rminus - H u.
+    void hessian_apply(int j, const double *u, double *Hu, double rtol, const double *rminus) {
+        Level &L = c.lev[j];
+        LevelWs &w = c.ws[j];
+        const uint8_t *mk = (j == 0 && c.has_mask) ? c.mask0 : nullptr;
+        mass_apply(j, 2, u, w.hf, nullptr, nullptr);
+        solve_A(j, w.hf, w.hy, rtol);
+        mass_apply(j, 1, w.hy, w.hw, nullptr, nullptr);
+        solve_A(j, w.hw, w.ht, rtol);
+        spmv<double, 0>(L.M, L.M.v, GLin<NB>{w.ht, mk, u, c.o.beta},
+                        ELin<NB>{Hu, nullptr, rminus ? -1.0 : 1.0, rminus, 1.0, nullptr, 0.0, nullptr}, NoFin{},
+                        nullptr);
+        AMG_HIP(hipGetLastError());
+    }
+
+    // ---------------- multilevel preconditioner (practical form) ----------------
+    // C_l(r) = S_l (B_{l+1} q - beta^{-1} M_{l+1}^{-1} q) + beta^{-1} M_l^{-1} r (+ zprev),
+    // q = S_l^T r
+    void Cop(int l, const double *r, double *out, const double *zprev) {
+        Level &Lv = c.lev[l];
+        LevelWs &w1 = c.ws[l + 1];
+        LevelWs &w0 = c.ws[l];
+        spmv<double, 0>(Lv.St, Lv.St.v, GPlain<double, NB>{r}, EStore<double, NB>{w1.ml_in}, NoFin{}, nullptr);
+        mass_solve(l + 1, w1.ml_in, w1.ml_mup);
+        Bop(l + 1, w1.ml_in, w1.ml_out);
+        mass_solve(l, r, w0.ml_mself);
+        const double ib = 1.0 / c.o.beta;
+        spmv<double, 0>(Lv.S, Lv.S.v, GLin<NB>{w1.ml_out, nullptr, w1.ml_mup, -ib},
+                        ELin<NB>{out, nullptr, 1.0, w0.ml_mself, ib, zprev, 1.0, nullptr}, NoFin{}, nullptr);
+        AMG_HIP(hipGetLastError());
+    }
+
+    // B_{ell-1} = H_{ell-1}^{-1} (dense); B_l = 2 C_l - C_l H_l C_l as the two
+    // calls of Algorithm MLAS (0 < l < ell-1); B_0 = C_0
+    void Bop(int l, const double *r, double *z) {
+        if (l == c.ell - 1) {
+            dense_apply<double>(c.nH, c.Hinv, r, z, nullptr);
+            AMG_HIP(hipGetLastError());
+            return;
+        }
+        if (l == 0) {
+            Cop(0, r, z, nullptr);
+            return;
+        }
+        LevelWs &w = c.ws[l];
+        Cop(l, r, w.ml_z1, nullptr);
+        hessian_apply(l, w.ml_z1, w.ml_t, c.o.precond_inner_rtol, r);  // t = r - H_l z1
+        Cop(l, w.ml_t, z, w.ml_z1);                                     // z = z1 + C_l t
+    }
+
+    void precond(const double *r, double *z) {
+        if (c.o.precond) Bop(0, r, z);
+        else elem<0>(c.N, OpAxpby<NB>{z, r, nullptr, 1.0, 0.0}, NoFin{}, nullptr);
+    }
+
+    // ---------------- outer CG on H_0 (Section 5.3) ----------------
+    int outer(const double *b, double *x, bool have_x0, double rtol, int nlive, int *iters_out) {
+        const int n = c.N;
+        CgWs<double> &w = c.outer;
+        for (;;) {
+            if (have_x0) {
+                hessian_apply(0, x, w.r, c.o.inner_rtol, b);  // r = b - H x0
+            } else {
+                elem<0>(n, OpAxpby<NB>{w.r, b, nullptr, 1.0, 0.0}, NoFin{}, nullptr);
+                elem<0>(n, OpAxpby<NB>{x, b, nullptr, 0.0, 0.0}, NoFin{}, nullptr);
+            }
+            elem<2>(n, OpDot<NB>{b, b, w.r, w.r}, FinOuterInit<NB>{w.sc, rtol, nlive}, nullptr);
+            precond(w.r, w.z);
+            elem<1>(n, OpDot<NB>{w.r, w.z, nullptr, nullptr}, FinRho<NB>{w.sc}, nullptr);
+            elem<0>(n, OpAxpby<NB>{w.p0, w.z, nullptr, 1.0, 0.0}, NoFin{}, nullptr);
+            read_sc(w.sc);
+            int it = 0;
+            bool indefinite = c.hsc->indefinite;
+            bool done = c.hsc->all_conv;
+            while (!done && !indefinite) {
+                if (it >= c.o.outer_maxit) {
+                    *iters_out = it;
+                    return AMG_ERR_NOCONV;
+                }
+                hessian_apply(0, w.p0, w.q, c.o.inner_rtol, nullptr);
+                elem<1>(n, OpDot<NB>{w.p0, w.q, nullptr, nullptr}, FinAlpha<NB>{w.sc, 1}, nullptr);
+                elem<1>(n, OpUpd<double, NB, false>{x, w.r, nullptr, w.p0, w.q, nullptr, w.sc},
+                        FinUpd<NB, false>{w.sc}, nullptr);
+                ++it;
+                read_sc(w.sc);
+                if (c.hsc->indefinite) {
+                    indefinite = true;
+                    break;
+                }
+                if (c.hsc->all_conv) break;
+                precond(w.r, w.z);
+                elem<1>(n, OpDot<NB>{w.r, w.z, nullptr, nullptr}, FinBeta<NB>{w.sc, 1}, nullptr);
+                elem<0>(n, OpPUpd<NB>{w.p0, w.z, w.sc}, NoFin{}, nullptr);
+            }
+            if (!indefinite) {
+                *iters_out = it;
+                return AMG_OK;
+            }
+            if (!(c.o.auto_levels && c.ell > 1)) {
+                *iters_out = it;
+                return AMG_ERR_INDEFINITE;
+            }
+            form_dense_hessian(c, c.ell - 1);
+        }
+    }
+};
+
+}  // namespace amg

@@ -1,0 +1,228 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+the same seeded inputs.
+
+Integer setup outputs (roots, aggregates, every sparsity pattern) must be
+bit-exact; setup values are formed in the same order on both sides and must be
+bit-identical too; dense coarse data within 1e-12; solve-phase FP64 results
+within the tolerances stated per test (the reduced solve to 1e-8 relative,
+the target of the method)."""
+import numpy as np
+import pytest
+
+import inputs
+from oracle import dense as odense
+from oracle import sa as osa
+from oracle import solve as osolve
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+ORACLE_KEYS = ("hess_levels", "max_coarse", "inner_rtol", "mass_rtol", "precond_inner_rtol", "precond",
+               "inner32_rtol")
+
+
+def make(name, n, nb_max=1, **opts):
+    _need_gpu()
+    import paper_2001_11533_amd as amg
+    p = inputs.config(name, n=n)
+    rp, ci, va, vm = amg.assemble_p1(p.mesh.coords, p.mesh.elems, p.kappa)
+    beta = opts.pop("beta", p.beta)
+    g = amg.HessianSolver((rp, ci, va), (rp, ci, vm), p.dirichlet, beta=beta, nb_max=nb_max, **opts)
+    oo = osa.Opts(beta=beta, **{k: v for k, v in opts.items() if k in ORACLE_KEYS})
+    h, A, M = osolve.build_problem(p, oo)
+    mixed = opts.get("inner_precision", 64) == 32
+    return p, g, osolve.Oracle(h, mixed=mixed)
+
+
+def cuda(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def rel(a, b):
+    a = a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+SETUP_CASES = [("c1", None, {}), ("c2", 64, {}), ("c3", 16, {}), ("c3", 20, {"max_coarse": 50}),
+               ("c2", 48, {"max_coarse": 10})]
+
+
+@pytest.mark.parametrize("name,n,opts", SETUP_CASES)
+def test_setup_bit_exact(name, n, opts):
+    p, g, o = make(name, n, **opts)
+    h = o.h
+    L, ell = g.levels()
+    assert L == h.L and ell == h.ell
+    for j in range(L):
+        lev = h.levels[j]
+        nj, nnzA, nnzS, nnzM = g.level_size(j)
+        assert nj == lev.n and nnzA == lev.A.nnz and nnzM == lev.M.nnz
+        for which, ref in ((0, lev.A), (3, lev.M)):
+            rp, ci, v = g.csr(j, which)
+            assert np.array_equal(rp, ref.rowptr) and np.array_equal(ci, ref.col), (j, which)
+            assert np.array_equal(v.view(np.uint64), ref.val.view(np.uint64)), (j, which, np.abs(v - ref.val).max())
+        if j < L - 1:
+            agg, root = g.aggregates(j)
+            assert np.array_equal(root.astype(bool), lev.root)
+            assert np.array_equal(agg, lev.agg)
+            for which, ref in ((1, lev.S), (2, lev.St)):
+                rp, ci, v = g.csr(j, which)
+                assert np.array_equal(rp, ref.rowptr) and np.array_equal(ci, ref.col), (j, which)
+                assert np.array_equal(v.view(np.uint64), ref.val.view(np.uint64)), (j, which)
+    Ainv = g.dense(0)
+    ref = np.linalg.inv(h.levels[-1].A.dense())
+    assert np.max(np.abs(Ainv - ref)) <= 1e-12 * np.max(np.abs(ref))
+    H = g.dense(1)
+    assert np.max(np.abs(H - h.H_dense)) <= 1e-12 * np.max(np.abs(h.H_dense))
+    Hinv = g.dense(2)
+    assert np.max(np.abs(Hinv @ H - np.eye(H.shape[0]))) < 1e-9
+
+
+def test_mass_operators():
+    p, g, o = make("c2", 32, nb_max=4)
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((p.mesh.nverts, 3))
+    fns = [osa.mass_u, osa.mass_y, osa.mass_yu, osa.mass_yu_t]
+    for which, f in enumerate(fns):
+        y = g.mass_apply(cuda(x), which)
+        assert rel(y, f(o.h, 0, x)) < 1e-14, which
+    q = g.mass_quad(cuda(x), 1).numpy()
+    ref = np.einsum("ic,ic->c", x, osa.mass_y(o.h, 0, x))
+    assert np.max(np.abs(q - ref) / np.abs(ref)) < 1e-13
+
+
+TIGHT = dict(inner_rtol=1e-13, mass_rtol=1e-14, precond_inner_rtol=1e-13)
+
+
+@pytest.mark.parametrize("name,n,mc", [("c1", None, 200), ("c2", 40, 20), ("c3", 12, 40)])
+def test_state_adjoint_hessian(name, n, mc):
+    p, g, o = make(name, n, max_coarse=mc, **TIGHT)
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal(p.mesh.nverts)
+    assert rel(g.state_solve(cuda(u)), o.state_solve(0, u)) < 1e-11
+    assert rel(g.adjoint_solve(cuda(u)), o.adjoint_solve(0, u)) < 1e-11
+    assert rel(g.hessian_apply(cuda(u)), o.hessian_apply(0, u)) < 1e-11
+    L, _ = g.levels()
+    if L > 2:
+        u1 = rng.standard_normal(g.level_size(1)[0])
+        assert rel(g.hessian_apply(cuda(u1), level=1), o.hessian_apply(1, u1)) < 1e-11
+
+
+@pytest.mark.parametrize("name,n,mc", [("c2", 40, 20), ("c3", 12, 40)])
+def test_precond_apply(name, n, mc):
+    p, g, o = make(name, n, max_coarse=mc, **TIGHT)
+    assert g.levels()[1] >= 3
+    rng = np.random.default_rng(9)
+    r = rng.standard_normal(p.mesh.nverts)
+    assert rel(g.precond_apply(cuda(r)), o.precond(r)) < 1e-10
+
+
+@pytest.mark.parametrize("name,n,mc", [("c1", None, 200), ("c2", 64, 200), ("c3", 16, 200)])
+def test_reduced_solve(name, n, mc):
+    p, g, o = make(name, n, max_coarse=mc)
+    yd = p.yd[:, 0]
+    u, info = g.reduced_solve(cuda(yd), rtol=1e-8)
+    uo, it = o.reduced_solve(yd, rtol=1e-12)
+    assert info[0]["rel_resid"] <= 1e-8
+    assert rel(u, uo) < 1e-8, (rel(u, uo), info[0])
+    assert abs(info[0]["outer_iters"] - it) <= 3
+
+
+def test_reduced_solve_tiny_against_dense():
+    p, g, o = make("c1", 10, max_coarse=20)
+    yd = p.yd[:, 0]
+    u, info = g.reduced_solve(cuda(yd), rtol=1e-11)
+    H = odense.hessian_practical(o.h)
+    ref = np.linalg.solve(H, odense.rhs_practical(o.h, yd))
+    assert rel(u, ref) < 1e-9
+
+
+def test_mixed_precision_solve():
+    p, g, o = make("c3", 16, inner_precision=32)
+    o64 = osolve.Oracle(o.h)
+    yd = p.yd[:, 0]
+    u, info = g.reduced_solve(cuda(yd), rtol=1e-8)
+    uo, _ = o64.reduced_solve(yd, rtol=1e-12)
+    assert info[0]["refine_steps"] > 0
+    assert rel(u, uo) < 1e-8
+
+
+def test_batched_matches_single_columns():
+    p, g, o = make("c2", 48, nb_max=4)
+    yd = np.stack([inputs.yd_bumps(p.mesh, s) for s in (2, 3, 4)], axis=1)   # nb = 3 (padded to 4)
+    U, infos = g.reduced_solve(cuda(yd), rtol=1e-10)
+    for k in range(3):
+        uk, _ = g.reduced_solve(cuda(yd[:, k]), rtol=1e-10)
+        assert rel(U[:, k], uk.cpu().numpy()) < 1e-8
+        uo, _ = o.reduced_solve(yd[:, k], rtol=1e-12)
+        assert rel(U[:, k], uo) < 1e-8
+
+
+def test_unpreconditioned_matches_preconditioned():
+    p, g, o = make("c2", 32, precond=0)
+    yd = p.yd[:, 0]
+    u0, i0 = g.reduced_solve(cuda(yd), rtol=1e-10)
+    p2, g2, _ = make("c2", 32)
+    u1, i1 = g2.reduced_solve(cuda(yd), rtol=1e-10)
+    assert rel(u0, u1.cpu().numpy()) < 1e-8
+    assert i0[0]["outer_iters"] >= i1[0]["outer_iters"]
+
+
+def test_gradient_autograd_and_objective():
+    from paper_2001_11533_amd import reduced_functional
+    p, g, o = make("c2", 32, nb_max=2, **TIGHT)
+    rng = np.random.default_rng(4)
+    U = rng.standard_normal((p.mesh.nverts, 2))
+    yd = np.repeat(p.yd, 2, axis=1)
+    u = cuda(U).requires_grad_(True)
+    J = reduced_functional(u, cuda(yd), g)
+    J.sum().backward()
+    for k in range(2):
+        gref = o.gradient(U[:, k], yd[:, k])
+        assert rel(u.grad[:, k], gref) < 1e-10
+        assert abs(float(J[k]) - o.objective(U[:, k], yd[:, k])) <= 1e-11 * abs(o.objective(U[:, k], yd[:, k]))
+    Jl, gl = g.objective(cuda(U), cuda(yd))
+    assert rel(gl, u.grad.detach().cpu().numpy()) < 1e-11
+    # exact quadratic: central difference along a direction
+    d = rng.standard_normal(p.mesh.nverts)
+    d /= np.linalg.norm(d)
+    h = 1e-2
+    Jp, _ = g.objective(cuda(U[:, 0] + h * d), cuda(yd[:, 0]), grad=False)
+    Jm, _ = g.objective(cuda(U[:, 0] - h * d), cuda(yd[:, 0]), grad=False)
+    fd = (float(Jp[0]) - float(Jm[0])) / (2 * h)
+    gd = float(u.grad[:, 0].cpu().numpy() @ d)
+    assert abs(fd - gd) <= 1e-8 * abs(gd) + 1e-12
+
+
+def test_error_paths():
+    _need_gpu()
+    import paper_2001_11533_amd as amg
+    from paper_2001_11533_amd import AmgError
+    p = inputs.config("c1", n=12)
+    rp, ci, va, vm = amg.assemble_p1(p.mesh.coords, p.mesh.elems, p.kappa)
+    bad = va.copy()
+    bad[np.nonzero(ci == 1)[0][0]] += 1e-3          # breaks exact symmetry
+    with pytest.raises(AmgError) as e:
+        amg.HessianSolver((rp, ci, bad), (rp, ci, vm), p.dirichlet, beta=1e-2)
+    assert e.value.code == -2
+    neg = va.copy()
+    d = np.nonzero(ci == np.repeat(np.arange(len(rp) - 1), np.diff(rp)))[0]
+    interior = np.nonzero(p.dirichlet == 0)[0][0]
+    neg[d[interior]] = -neg[d[interior]]
+    with pytest.raises(AmgError) as e:
+        amg.HessianSolver((rp, ci, neg), (rp, ci, vm), p.dirichlet, beta=1e-2, max_coarse=10)
+    assert e.value.code == -3
+    g = amg.HessianSolver((rp, ci, va), (rp, ci, vm), p.dirichlet, beta=1e-2, max_coarse=10, inner_maxit=1)
+    with pytest.raises(AmgError) as e:
+        g.state_solve(cuda(np.ones(p.mesh.nverts)))
+    assert e.value.code == -4
+    with pytest.raises(AmgError) as e:
+        g.state_solve(cuda(np.ones((p.mesh.nverts, 2))))    # nb above nb_max
+    assert e.value.code == -1

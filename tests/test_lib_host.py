@@ -1,0 +1,90 @@
+"""Host-side checks of the HIP library (no GPU): the shared object loads and
+exports every function the C header declares, the host P1 assembler agrees
+with the oracle's assembly, and argument validation returns error codes."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import inputs
+from oracle import fem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "amghess.h")
+
+
+def _lib():
+    from paper_2001_11533_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("library not built")
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    h = C.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(h, n), n
+    assert set(names) == set(L.SIGNATURES), set(names) ^ set(L.SIGNATURES)
+
+
+def test_opts_defaults():
+    L = _lib()
+    o = L.Opts()
+    assert L.lib().amg_opts_default(C.byref(o)) == 0
+    assert o.max_coarse == 200 and o.inner_rtol == 1e-10 and o.nu == 1 and o.precond == 1
+    assert L.lib().amg_opts_default(None) == -1
+
+
+@pytest.mark.parametrize("kind", ["2d", "2dj", "3d"])
+def test_host_assembler_matches_oracle(kind):
+    from paper_2001_11533_amd.solver import assemble_p1
+    _lib()
+    m = {"2d": lambda: inputs.mesh2d(9), "2dj": lambda: inputs.mesh2d(12, jitter=0.2),
+         "3d": lambda: inputs.mesh3d(5)}[kind]()
+    kappa = inputs.kappa_lognormal(m, 1.0)
+    rp, ci, va, vm = assemble_p1(m.coords, m.elems, kappa)
+    A, M = fem.assemble(m.coords, m.elems, kappa)
+    assert np.array_equal(rp, A.rowptr) and np.array_equal(ci, A.col)
+    # same formulas in the same operation order: equal to the last bit
+    assert np.array_equal(va, A.val)
+    assert np.array_equal(vm, M.val)
+
+
+def test_assembler_rejects_bad_mesh():
+    L = _lib()
+    elems = np.array([[0, 1, 5]], dtype=np.int32)
+    nnz = C.c_int32()
+    assert L.lib().amg_p1_pattern(2, 3, 1, elems.ctypes.data, C.byref(nnz)) == -1   # vertex out of range
+    assert L.lib().amg_p1_pattern(4, 3, 1, elems.ctypes.data, C.byref(nnz)) == -1   # bad dimension
+
+
+def test_setup_argument_validation_without_gpu():
+    L = _lib()
+    h = C.c_void_p()
+    assert L.lib().amg_setup(None, None, None, None, None, C.byref(h)) == -1
+    a = L.Csr(4, 3, 4, 1, 1, 1)   # not square
+    assert L.lib().amg_setup(C.byref(a), C.byref(a), None, None, None, C.byref(h)) == -1
+    assert b"sizes" in L.lib().amg_last_error(None)
+    a = L.Csr(4, 4, 4, 1, 1, 1)
+    o = L.Opts()
+    L.lib().amg_opts_default(C.byref(o))
+    o.beta = 0.0
+    assert L.lib().amg_setup(C.byref(a), C.byref(a), None, C.byref(o), None, C.byref(h)) == -1
+    o.beta = 1.0
+    o.nb_max = 17
+    assert L.lib().amg_setup(C.byref(a), C.byref(a), None, C.byref(o), None, C.byref(h)) == -1
+    assert not h.value
+    # calls on a null context
+    assert L.lib().state_solve(None, 0, None, None, 1, None) == -1
+    assert L.lib().amg_destroy(None) == 0
