@@ -1,0 +1,197 @@
+"""Benchmark of the reduced-Hessian solve on one MI355X.
+
+Workload: the 3D unit cube, 64^3 grid split into 6 Kuhn tetrahedra per cube
+(274,625 nodes, 1,572,864 P1 elements), log-normal kappa (16 seeded Fourier
+modes, variance 1), beta = 1e-3, the manufactured desired state of the paper's
+eq. test-state; inner V-cycles and CG in float32 inside FP64 refinement,
+outer Hessian CG, refinement residuals and dense coarse factors in FP64.
+
+One step = the whole hot path on that input, resident in HBM when the timed
+region starts: the smoothed-aggregation setup on the GPU (strength graph,
+aggregation, prolongator smoothing, Galerkin products, dense coarse factors)
+followed by the reduced solve to relative residual 1e-8 (right-hand side
+K^T M_y y_d, outer CG preconditioned with the multilevel Hessian
+preconditioner).  The JSON line also reports the plain FP64 path, the batched
+(16 desired states) path, the V-cycle and dominant-kernel bandwidth, and the
+CPU oracle timed on a bounded sample on this host.
+
+usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(p, gpu_outer_iters: int):
+    """The oracle, untuned, on a bounded sample of the same workload: its full
+    setup (hierarchy from the assembled matrices), its right-hand side and one
+    outer iteration (one Hessian action and one preconditioner action), scaled
+    to a whole step with the outer-iteration count of the GPU solve."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import fem, sa, solve
+
+    with threadpool_limits(limits=1):
+        A, M = fem.assemble(p.mesh.coords, p.mesh.elems, p.kappa)
+        bc = p.dirichlet.astype(bool)
+        t0 = time.perf_counter()
+        A0 = fem.dirichlet_stiffness(A, bc)
+        h = sa.build(A0, M, bc, sa.Opts(beta=p.beta))
+        t_setup = time.perf_counter() - t0
+        o = solve.Oracle(h)
+        t0 = time.perf_counter()
+        b = o.rhs(p.yd[:, 0])
+        t_rhs = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        o.hessian_apply(0, b)
+        o.precond(b)
+        t_iter = time.perf_counter() - t0
+    est = t_setup + t_rhs + gpu_outer_iters * t_iter + t_iter  # + the initial preconditioner/Hessian work
+    return {"value": est, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle (NumPy/SciPy, FP64, 1 thread) on the 64^3 workload: full setup {t_setup:.1f} s, "
+                       f"rhs {t_rhs:.1f} s, one outer iteration {t_iter:.1f} s measured; step = setup + rhs + "
+                       f"({gpu_outer_iters} + 1) outer iterations")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the reduced-Hessian solve of this library is a single-GPU "
+              "path (see the sharding notes in the design document); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import inputs
+    import paper_2001_11533_amd as amg
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    p = inputs.config("c3")
+    N = p.mesh.nverts
+    log(f"[bench] workload 64^3: N={N} elements={p.mesh.nelems}")
+    rp, ci, va, vm = amg.assemble_p1(p.mesh.coords, p.mesh.elems, p.kappa)
+    A = tuple(torch.as_tensor(x).to(dev) for x in (rp, ci, va))
+    M = tuple(torch.as_tensor(x).to(dev) for x in (rp, ci, vm))
+    mask = torch.as_tensor(p.dirichlet).to(dev)
+    yd = torch.as_tensor(p.yd[:, 0].copy()).to(dev)
+    torch.cuda.synchronize()
+
+    def step(prec, ydv, nb_max=1):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        s = amg.HessianSolver(A, M, mask, beta=p.beta, inner_precision=prec, nb_max=nb_max)
+        ev[1].record()
+        u, info = s.reduced_solve(ydv, rtol=1e-8)
+        ev[2].record()
+        return s, u, info, ev
+
+    # ---- the headline step: FP32 inner / FP64 outer ----
+    for _ in range(args.warmup):
+        s, u, info, ev = step(32, yd)
+        s.close()
+    torch.cuda.synchronize()
+    setup_ms, solve_ms = [], []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        s, u, info, ev = step(32, yd)
+        if k < args.steps - 1:
+            s.close()
+        torch.cuda.synchronize()
+        setup_ms.append(ev[0].elapsed_time(ev[1]))
+        solve_ms.append(ev[1].elapsed_time(ev[2]))
+        log(f"[bench] step {k}: setup {setup_ms[-1]:.1f} ms solve {solve_ms[-1]:.1f} ms outer {info[0]['outer_iters']}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1000.0 * wall / args.steps
+    u32 = u.clone()
+    info32 = info[0]
+    L, ell = s.levels()
+    sizes = [s.level_size(j) for j in range(L)]
+
+    # dominant kernel (level-0 float32 l1-Jacobi sweep) and the whole V-cycle, HIP events on the library's stream
+    kern_ms, kern_bytes = s.time_kernel(1, prec=32, nb=1, reps=200)
+    vc_ms, vc_bytes = s.time_kernel(2, prec=32, nb=1, reps=50)
+    vc64_ms = vc64_bytes = None
+    s.close()
+
+    # ---- plain FP64 path on the same input ----
+    s64, u64, info64, ev = step(64, yd)
+    torch.cuda.synchronize()
+    fp64_setup_ms, fp64_solve_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+    err_mixed_vs_fp64 = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
+    vc64_ms, vc64_bytes = s64.time_kernel(2, prec=64, nb=1, reps=50)
+    s64.close()
+    log(f"[bench] fp64: setup {fp64_setup_ms:.1f} ms solve {fp64_solve_ms:.1f} ms; mixed vs fp64 {err_mixed_vs_fp64:.2e}")
+
+    # ---- 16 desired states as one block solve vs one at a time ----
+    yd16 = torch.as_tensor(inputs.config("c3", nb=16).yd).to(dev).contiguous()
+    sb, ub, infob, ev = step(32, yd16, nb_max=16)
+    torch.cuda.synchronize()
+    batch_solve_ms = ev[1].elapsed_time(ev[2])
+    sb.close()
+    log(f"[bench] batch16 solve {batch_solve_ms:.1f} ms ({batch_solve_ms / 16:.1f} ms per state)")
+
+    # ---- CPU oracle on a bounded sample ----
+    cpu = cpu_baseline(p, info32["outer_iters"])
+    log(f"[bench] cpu baseline {cpu['value']:.1f} s")
+
+    achieved = kern_bytes / (kern_ms * 1e-3) / 1e9
+    res = {
+        "metric": "reduced-Hessian solve time to 1e-8 (setup + solve), 3D 64^3 P1, FP32 inner / FP64 outer",
+        "value": ms_step / 1000.0,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "3D unit cube 64^3 Kuhn tets, P1, N=274625, log-normal kappa var 1, beta=1e-3, "
+                               "eq. test-state y_d, nb=1", "N": N, "levels": sizes, "ell": ell},
+        "setup_ms": float(np.median(setup_ms)),
+        "solve_ms": float(np.median(solve_ms)),
+        "outer_iters": info32["outer_iters"],
+        "inner_solves": info32["inner_solves"],
+        "inner_iters_total": info32["inner_iters_total"],
+        "refine_steps": info32["refine_steps"],
+        "rel_resid": info32["rel_resid"],
+        "fp64": {"setup_ms": fp64_setup_ms, "solve_ms": fp64_solve_ms, "outer_iters": info64[0]["outer_iters"]},
+        "err_mixed_vs_fp64": err_mixed_vs_fp64,
+        "batch16": {"solve_ms": batch_solve_ms, "ms_per_state": batch_solve_ms / 16,
+                    "outer_iters": max(i["outer_iters"] for i in infob)},
+        "vcycle": {"f32_ms": vc_ms, "f32_GBps_alg": vc_bytes / (vc_ms * 1e-3) / 1e9,
+                   "f64_ms": vc64_ms, "f64_GBps_alg": vc64_bytes / (vc64_ms * 1e-3) / 1e9},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "level-0 float32 l1-Jacobi sweep (CSR SpMV + smoother epilogue)",
+                     "ms": kern_ms, "bytes": kern_bytes},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

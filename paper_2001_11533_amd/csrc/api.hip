@@ -207,10 +207,8 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
     int rc = guarded(nullptr, [&]() {
         c.lev.reserve(o.max_levels + 1);
         c.partial = c.arena.alloc<double>((size_t)2 * 16 * kMaxGrid);
-        c.counter = c.arena.alloc<unsigned>(16);
         c.dscratch = c.arena.alloc<double>(64);
         c.iscratch = c.arena.alloc<int>(64);
-        AMG_HIP(hipMemsetAsync(c.counter, 0, 16 * sizeof(unsigned), c.stream));
         AMG_HIP(hipHostMalloc((void **)&c.hsc, sizeof(CgScal), hipHostMallocDefault));
         AMG_HIP(hipHostMalloc((void **)&c.hscr, 64 * sizeof(double), hipHostMallocDefault));
         AMG_HIP(hipHostMalloc((void **)&c.hiscr, 64 * sizeof(int), hipHostMallocDefault));

@@ -69,7 +69,6 @@ struct Ctx {
     int nH = 0;
     // reductions (one stream: a single partial buffer and ticket suffice)
     double *partial = nullptr;
-    unsigned *counter = nullptr;
     double *dscratch = nullptr;  // small device scalars [64]
     int *iscratch = nullptr;     // small device ints [64]
     // host mirrors

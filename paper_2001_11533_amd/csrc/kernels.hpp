@@ -12,9 +12,11 @@
 // right-hand sides while the x gathers are NB-contiguous.
 //
 // Reductions are deterministic: each workgroup reduces its contribution in a
-// fixed LDS tree, writes one partial per (quantity, column), and the last
-// workgroup to finish (atomic ticket) sums the partials in a fixed order and
-// runs a small "finalize" step on thread 0 (CG scalars, convergence flags).
+// fixed LDS tree and writes one partial per (quantity, column); a one-workgroup
+// kernel launched next sums the partials in a fixed order and runs a small
+// "finalize" step on thread 0 (CG scalars, convergence flags).  Issuing a
+// device-scope fence per workgroup instead (a "last workgroup" ticket) makes
+// every workgroup write back its XCD's L2 and costs far more than the launch.
 #pragma once
 
 #include "common.hpp"
@@ -54,7 +56,6 @@ template <int NB> struct Geo {
 
 template <int NV, int NB> struct Reducer {
     double *partial;    // [NV*NB][gridDim.x]
-    unsigned *counter;  // zero between launches
 };
 
 constexpr int pow2floor(int x) {
@@ -63,13 +64,14 @@ constexpr int pow2floor(int x) {
     return p;
 }
 
-// Block reduction of acc[NV] over threads of equal column (t % NB), then the
-// grid-level ticket.  Returns true in the last workgroup, with the totals in
-// tot (LDS, valid for every thread of that workgroup).
+// Block reduction of acc[NV] over threads of equal column (t % NB) in a
+// fixed LDS tree; thread t < NV*NB then writes partial (t / NB, t % NB) of
+// this workgroup.  The totals are formed by fin_kernel, launched next on the
+// same stream (a kernel boundary orders the partials; no device-scope fence
+// is issued by the workgroups).
 template <int NV, int NB>
-__device__ bool grid_reduce(const double (&acc)[NV], Reducer<NV, NB> r, double (&tot)[NV][NB]) {
+__device__ void block_partials(const double (&acc)[NV], Reducer<NV, NB> r) {
     __shared__ double red[NV][kBlock];
-    __shared__ int last;
     const int t = threadIdx.x;
 #pragma unroll
     for (int v = 0; v < NV; ++v) red[v][t] = acc[v];
@@ -81,32 +83,35 @@ __device__ bool grid_reduce(const double (&acc)[NV], Reducer<NV, NB> r, double (
         }
         __syncthreads();
     }
-    const int nblk = gridDim.x;
-    if (t < NV * NB) r.partial[(size_t)t * nblk + blockIdx.x] = red[t / NB][t % NB];
-    __threadfence();
-    __syncthreads();
-    if (t == 0) last = (atomicAdd(r.counter, 1u) == (unsigned)nblk - 1u);
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
+    if (t < NV * NB) r.partial[(size_t)t * gridDim.x + blockIdx.x] = red[t / NB][t % NB];
+}
+
+// One workgroup: sums the nblk partials of each (quantity, column) in a fixed
+// order and runs the finalize step on thread 0.
+template <int NV, int NB, class FIN>
+__global__ __launch_bounds__(kBlock) void fin_kernel(const double *__restrict__ partial, int nblk, FIN fin,
+                                                     const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    __shared__ double red[kBlock];
+    __shared__ double tot[NV][NB];
     constexpr int Q = NV * NB;
     constexpr int LPS = pow2floor(kBlock / Q);
+    const int t = threadIdx.x;
     const int q = t / LPS, sub = t % LPS;
     double s = 0.0;
     if (q < Q) {
-        const volatile double *pp = r.partial + (size_t)q * nblk;
+        const double *pp = partial + (size_t)q * nblk;
         for (int b = sub; b < nblk; b += LPS) s += pp[b];
     }
-    red[0][t] = s;
+    red[t] = s;
     __syncthreads();
     for (int w = LPS / 2; w >= 1; w >>= 1) {
-        if (q < Q && sub < w) red[0][t] += red[0][t + w];
+        if (q < Q && sub < w) red[t] += red[t + w];
         __syncthreads();
     }
-    if (q < Q && sub == 0) tot[q / NB][q % NB] = red[0][t];
+    if (q < Q && sub == 0) tot[q / NB][q % NB] = red[t];
     __syncthreads();
-    if (t == 0) *r.counter = 0u;
-    return true;
+    if (t == 0) fin(tot);
 }
 
 struct NoFin {
@@ -116,11 +121,11 @@ struct NoFin {
 // ---------------------------------------------------------------------------
 // CSR SpMV / SpMM with a gather functor (how x_k is formed) and an epilogue
 // functor (what is written for row i); optional fused reductions.
-template <typename T, int NB, int NV, class GX, class EP, class FIN>
+template <typename T, int NB, int NV, class GX, class EP>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__restrict__ rp,
                                                       const int *__restrict__ ci,
                                                       const T *__restrict__ av, GX gx, EP ep,
-                                                      Reducer<(NV > 0 ? NV : 1), NB> red, FIN fin,
+                                                      Reducer<(NV > 0 ? NV : 1), NB> red,
                                                       const int *__restrict__ stop) {
     if (stop && *stop) return;
     using Gm = Geo<NB>;
@@ -147,18 +152,13 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__re
         for (int off = NB; off < Gm::LPR; off <<= 1) sum += __shfl_xor(sum, off);
         if (row < r1 && g == 0) ep(row, c, sum, acc);
     }
-    if constexpr (NV > 0) {
-        __shared__ double tot[NV][NB];
-        if (grid_reduce<NV, NB>(acc, red, tot)) {
-            if (t == 0) fin(tot);
-        }
-    }
+    if constexpr (NV > 0) block_partials<NV, NB>(acc, red);
 }
 
 // Elementwise kernel over n rows x NB columns with fused reductions.
-template <int NB, int NV, class OP, class FIN>
+template <int NB, int NV, class OP>
 __global__ __launch_bounds__(kBlock) void elem_kernel(int n, OP op, Reducer<(NV > 0 ? NV : 1), NB> red,
-                                                      FIN fin, const int *__restrict__ stop) {
+                                                      const int *__restrict__ stop) {
     if (stop && *stop) return;
     const int t = threadIdx.x, c = t % NB;
     const int nblk = gridDim.x, b = xcd_block(blockIdx.x, nblk);
@@ -172,12 +172,7 @@ __global__ __launch_bounds__(kBlock) void elem_kernel(int n, OP op, Reducer<(NV 
 #pragma unroll
     for (int v = 0; v < NVA; ++v) acc[v] = 0.0;
     for (long e = e0 + t; e < e1; e += kBlock) op((int)(e / NB), c, acc);
-    if constexpr (NV > 0) {
-        __shared__ double tot[NV][NB];
-        if (grid_reduce<NV, NB>(acc, red, tot)) {
-            if (t == 0) fin(tot);
-        }
-    }
+    if constexpr (NV > 0) block_partials<NV, NB>(acc, red);
 }
 
 // ---------------------------------------------------------------------------

@@ -393,20 +393,21 @@ __global__ void k_t_place(int n, const int *rp, const int *ci, const double *v, 
         }
 }
 
-__global__ void k_row_sort(int m, const int *rp, int *ci, double *v) {
-    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < m; r += gridDim.x * blockDim.x) {
+// rows of the transpose: rank sort by column index, one wavefront per row
+// (the keys of a row are distinct row indices of the source matrix)
+__global__ __launch_bounds__(kBlock) void k_row_sort(int m, const int *rp, const int *ci_in, const double *v_in,
+                                                     int *ci_out, double *v_out) {
+    const int lane = threadIdx.x % 64;
+    const int w = (blockIdx.x * kBlock + threadIdx.x) / 64;
+    const int nw = gridDim.x * kBlock / 64;
+    for (int r = w; r < m; r += nw) {
         const int s = rp[r], e = rp[r + 1];
-        for (int a = s + 1; a < e; ++a) {
-            const int key = ci[a];
-            const double kv = v[a];
-            int b = a - 1;
-            while (b >= s && ci[b] > key) {
-                ci[b + 1] = ci[b];
-                v[b + 1] = v[b];
-                --b;
-            }
-            ci[b + 1] = key;
-            v[b + 1] = kv;
+        for (int a = s + lane; a < e; a += 64) {
+            const int key = ci_in[a];
+            int rank = 0;
+            for (int b = s; b < e; ++b) rank += ci_in[b] < key;
+            ci_out[s + rank] = key;
+            v_out[s + rank] = v_in[a];
         }
     }
 }
@@ -746,14 +747,19 @@ struct Setup {
         T.rp = c.arena.alloc<int>(T.n + 1);
         T.ci = c.arena.alloc<int>(T.nnz);
         T.v = c.arena.alloc<double>(T.nnz);
+        int *tci = c.arena.alloc<int>(T.nnz);
+        double *tv = c.arena.alloc<double>(T.nnz);
         hipLaunchKernelGGL(k_t_count, dim3(gsz(A.n)), dim3(kBlock), 0, s, A.n, A.rp, A.ci, cnt);
         scan(cnt, T.rp, T.n);
-        hipLaunchKernelGGL(k_t_place, dim3(gsz(A.n)), dim3(kBlock), 0, s, A.n, A.rp, A.ci, A.v, T.rp, fill,
-                           T.ci, T.v);
-        hipLaunchKernelGGL(k_row_sort, dim3(gsz(T.n)), dim3(kBlock), 0, s, T.n, T.rp, T.ci, T.v);
+        hipLaunchKernelGGL(k_t_place, dim3(gsz(A.n)), dim3(kBlock), 0, s, A.n, A.rp, A.ci, A.v, T.rp, fill, tci,
+                           tv);
+        const int waves_g = std::min(4096, std::max(1, ceil_div(T.n, 4)));
+        hipLaunchKernelGGL(k_row_sort, dim3(waves_g), dim3(kBlock), 0, s, T.n, T.rp, tci, tv, T.ci, T.v);
         check_kernels();
         c.arena.release(cnt);
         c.arena.release(fill);
+        c.arena.release(tci);
+        c.arena.release(tv);
         return T;
     }
 

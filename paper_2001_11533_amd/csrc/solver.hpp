@@ -21,18 +21,25 @@ template <int NB> struct Solver {
     explicit Solver(Ctx &cc) : c(cc), s(cc.stream) {}
 
     // ---------------- launch helpers ----------------
+    template <int NV, class FIN> void finish(int nblk, FIN fin, const int *stop) {
+        if constexpr (NV > 0)
+            hipLaunchKernelGGL((fin_kernel<NV, NB, FIN>), dim3(1), dim3(kBlock), 0, s, c.partial, nblk, fin, stop);
+    }
+
     template <typename T, int NV, class GX, class EP, class FIN>
     void spmv(const DCsr &A, const T *vals, GX gx, EP ep, FIN fin, const int *stop) {
-        const int g = grid_rows(A.n, Geo<NB>::RPB);
-        Reducer<(NV > 0 ? NV : 1), NB> red{c.partial, c.counter};
-        hipLaunchKernelGGL((spmv_kernel<T, NB, NV, GX, EP, FIN>), dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci,
-                           vals, gx, ep, red, fin, stop);
+        const int g = grid_rows(A.n, Geo<NB>::RPB, NV > 0 ? kMaxGrid : kMaxGridPlain);
+        Reducer<(NV > 0 ? NV : 1), NB> red{c.partial};
+        hipLaunchKernelGGL((spmv_kernel<T, NB, NV, GX, EP>), dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci, vals,
+                           gx, ep, red, stop);
+        finish<NV>(g, fin, stop);
     }
 
     template <int NV, class OP, class FIN> void elem(int n, OP op, FIN fin, const int *stop) {
-        const int g = grid_rows((long)n * NB, kBlock);
-        Reducer<(NV > 0 ? NV : 1), NB> red{c.partial, c.counter};
-        hipLaunchKernelGGL((elem_kernel<NB, NV, OP, FIN>), dim3(g), dim3(kBlock), 0, s, n, op, red, fin, stop);
+        const int g = grid_rows((long)n * NB, kBlock, NV > 0 ? kMaxGrid : kMaxGridPlain);
+        Reducer<(NV > 0 ? NV : 1), NB> red{c.partial};
+        hipLaunchKernelGGL((elem_kernel<NB, NV, OP>), dim3(g), dim3(kBlock), 0, s, n, op, red, stop);
+        finish<NV>(g, fin, stop);
     }
 
     template <typename T> void dense_apply(int n, const double *inv, const T *b, T *x, const int *stop) {

@@ -49,10 +49,20 @@ def default_opts(**kw) -> Opts:
     return o
 
 
+def _to_dev(x, dtype, device):
+    if isinstance(x, torch.Tensor):
+        if x.dtype != dtype:
+            raise TypeError(f"expected {dtype}")
+        return x.to(device).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.int32 if dtype == torch.int32 else
+                                                np.float64 if dtype == torch.float64 else np.uint8)).to(device)
+
+
 def _dev_csr(rowptr, col, val, device):
-    rp = torch.as_tensor(np.asarray(rowptr, dtype=np.int32)).to(device)
-    ci = torch.as_tensor(np.asarray(col, dtype=np.int32)).to(device)
-    v = torch.as_tensor(np.asarray(val, dtype=np.float64)).to(device)
+    """CSR arrays (numpy, or tensors already resident on the device) as an amg_csr."""
+    rp = _to_dev(rowptr, torch.int32, device)
+    ci = _to_dev(col, torch.int32, device)
+    v = _to_dev(val, torch.float64, device)
     n = rp.numel() - 1
     return Csr(n, n, ci.numel(), rp.data_ptr(), ci.data_ptr(), v.data_ptr()), (rp, ci, v)
 
@@ -84,7 +94,7 @@ class HessianSolver:
         Mc, self._M = _dev_csr(*M, self.device)
         self.N = Ac.nrows
         if dirichlet is not None:
-            self._mask = torch.as_tensor(np.asarray(dirichlet, dtype=np.uint8)).to(self.device)
+            self._mask = _to_dev(dirichlet, torch.uint8, self.device)
             mptr = self._mask.data_ptr()
         else:
             self._mask, mptr = None, None
