@@ -89,6 +89,7 @@ typedef struct {
     int32_t nb_max;         /* widest batch used with this context (1..16) */
     int32_t precond;        /* 1: multilevel preconditioner, 0: plain outer CG */
     int32_t check_every;    /* inner CG: host convergence poll period after the predicted count (1) */
+    int32_t use_graphs;     /* 1: replay CG iterations from captured HIP graphs (default), 0: launch eagerly */
 } amg_opts;
 
 typedef struct {

@@ -33,7 +33,8 @@ class Opts(C.Structure):
                 ("inner_rtol", C.c_double), ("mass_rtol", C.c_double), ("precond_inner_rtol", C.c_double),
                 ("inner_maxit", C.c_int32), ("mass_maxit", C.c_int32), ("outer_maxit", C.c_int32),
                 ("inner_precision", C.c_int32), ("inner32_rtol", C.c_double), ("refine_maxit", C.c_int32),
-                ("nb_max", C.c_int32), ("precond", C.c_int32), ("check_every", C.c_int32)]
+                ("nb_max", C.c_int32), ("precond", C.c_int32), ("check_every", C.c_int32),
+                ("use_graphs", C.c_int32)]
 
 
 class Info(C.Structure):

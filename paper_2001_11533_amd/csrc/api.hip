@@ -38,6 +38,7 @@ template <class F> int guarded(Ctx *c, F &&f) {
 }
 
 void alloc_cg(Arena &a, CgWs<double> &w, size_t m) {
+    w.x = a.alloc<double>(m);
     w.r = a.alloc<double>(m);
     w.z = a.alloc<double>(m);
     w.p0 = a.alloc<double>(m);
@@ -46,6 +47,7 @@ void alloc_cg(Arena &a, CgWs<double> &w, size_t m) {
     w.sc = a.alloc<CgScal>(1);
 }
 void alloc_cg(Arena &a, CgWs<float> &w, size_t m) {
+    w.x = a.alloc<float>(m);
     w.r = a.alloc<float>(m);
     w.z = a.alloc<float>(m);
     w.p0 = a.alloc<float>(m);
@@ -169,6 +171,7 @@ int amg_opts_default(amg_opts *o) {
     o->nb_max = 1;
     o->precond = 1;
     o->check_every = 1;
+    o->use_graphs = 1;
     return AMG_OK;
 }
 
@@ -194,7 +197,7 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
     if (!(o.beta > 0.0) || o.nb_max < 1 || o.nb_max > 16 || o.max_levels < 1 || o.max_coarse < 1 ||
         o.dense_max < 1 || o.dense_max > 4096 || (o.inner_precision != 32 && o.inner_precision != 64) ||
         o.nu != 1 || o.inner_maxit < 1 || o.mass_maxit < 1 || o.outer_maxit < 1 || o.hess_levels < 0 ||
-        !(o.theta0 >= 0.0) || o.refine_maxit < 1) {
+        !(o.theta0 >= 0.0) || o.refine_maxit < 1 || o.use_graphs < 0 || o.use_graphs > 1) {
         g_setup_err = "invalid options (beta > 0, 1 <= nb_max <= 16, dense_max <= 4096, nu = 1, precision 32/64)";
         return AMG_ERR_ARG;
     }
@@ -213,6 +216,9 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
         AMG_HIP(hipHostMalloc((void **)&c.hscr, 64 * sizeof(double), hipHostMallocDefault));
         AMG_HIP(hipHostMalloc((void **)&c.hiscr, 64 * sizeof(int), hipHostMallocDefault));
         AMG_HIP(hipHostMalloc((void **)&c.rsh, sizeof(RefScal), hipHostMallocDefault));
+        AMG_HIP(hipHostMalloc((void **)&c.hflag, 2 * sizeof(int), hipHostMallocDefault));
+        AMG_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+        for (auto &e : c.poll_ev) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         build_hierarchy(c, *A, *M, dirichlet);
         form_dense_hessian(c, o.hess_levels > 0 ? o.hess_levels : c.L);
         alloc_workspaces(c);
@@ -236,6 +242,11 @@ int amg_destroy(amg_ctx *ctx) {
     if (c.hscr) (void)hipHostFree(c.hscr);
     if (c.hiscr) (void)hipHostFree(c.hiscr);
     if (c.rsh) (void)hipHostFree(c.rsh);
+    if (c.hflag) (void)hipHostFree(c.hflag);
+    for (auto g : c.graphs) (void)hipGraphExecDestroy(g);
+    for (auto e : c.poll_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
     delete ctx;
     return AMG_OK;
 }

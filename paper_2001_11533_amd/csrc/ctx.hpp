@@ -24,9 +24,11 @@ struct Level {
 };
 
 template <typename T> struct CgWs {
-    T *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
+    T *x = nullptr, *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
     CgScal *sc = nullptr;
     int pred = 0;  // iteration count of the previous solve (poll schedule)
+    // captured graphs: first preconditioner application, iteration p0->p1, iteration p1->p0
+    hipGraphExec_t g0 = nullptr, ga = nullptr, gb = nullptr;
 };
 
 template <typename T> struct VcWs {
@@ -55,6 +57,10 @@ struct Stats {
 
 struct Ctx {
     hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
+    std::vector<hipGraphExec_t> graphs; // every instantiated graph (freed with the context)
+    hipEvent_t poll_ev[2] = {nullptr, nullptr};
+    int *hflag = nullptr;               // pinned [2]: convergence flags in flight
     amg_opts o{};
     Arena arena;
     int N = 0;

@@ -48,11 +48,33 @@ __device__ __forceinline__ int xcd_block(int b, int nblk) {
     return (b % kXcd) * per + b / kXcd;
 }
 
-template <int NB> struct Geo {
-    static constexpr int LPR = NB >= 8 ? NB : 8;
-    static constexpr int G = LPR / NB;
-    static constexpr int RPB = kBlock / LPR;
+// Lanes per row: NB columns x G lanes per (row, column), G a power of two
+// chosen per matrix from its mean row length; LPR = NB G <= 64.
+struct Geo {
+    int lg;   // log2 G
+    int llpr; // log2 LPR
+    __host__ __device__ int lpr() const { return 1 << llpr; }
+    __host__ __device__ int rpb() const { return kBlock >> llpr; }
 };
+
+inline int ilog2(int x) {
+    int l = 0;
+    while ((1 << (l + 1)) <= x) ++l;
+    return l;
+}
+
+// G = next power of two >= (mean entries per row) / 2, at most 64 / NB
+inline Geo make_geo(long nnz, long rows, int NB) {
+    const double m = rows > 0 ? (double)nnz / (double)rows : 1.0;
+    int g = 1;
+    while (g < 64 && g < m / 2.0) g <<= 1;
+    while (g * NB > 64) g >>= 1;
+    if (g < 1) g = 1;
+    Geo geo;
+    geo.lg = ilog2(g);
+    geo.llpr = ilog2(g * NB);
+    return geo;
+}
 
 template <int NV, int NB> struct Reducer {
     double *partial;    // [NV*NB][gridDim.x]
@@ -124,15 +146,15 @@ struct NoFin {
 template <typename T, int NB, int NV, class GX, class EP>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__restrict__ rp,
                                                       const int *__restrict__ ci,
-                                                      const T *__restrict__ av, GX gx, EP ep,
+                                                      const T *__restrict__ av, GX gx, EP ep, Geo geo,
                                                       Reducer<(NV > 0 ? NV : 1), NB> red,
                                                       const int *__restrict__ stop) {
     if (stop && *stop) return;
-    using Gm = Geo<NB>;
     const int t = threadIdx.x;
-    const int lane = t % Gm::LPR, c = lane % NB, g = lane / NB, rl = t / Gm::LPR;
+    const int LPR = geo.lpr(), RPB = geo.rpb(), G = 1 << geo.lg;
+    const int lane = t & (LPR - 1), c = lane % NB, g = lane / NB, rl = t >> geo.llpr;
     const int nblk = gridDim.x, b = xcd_block(blockIdx.x, nblk);
-    const int span = ceil_div_dev(nrows, nblk * Gm::RPB) * Gm::RPB;
+    const int span = ceil_div_dev(nrows, nblk * RPB) * RPB;
     const int r0 = b * span;
     const int r1 = min(nrows, r0 + span);
     gx.prep(c);
@@ -141,15 +163,14 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__re
     double acc[NVA];
 #pragma unroll
     for (int v = 0; v < NVA; ++v) acc[v] = 0.0;
-    for (int base = r0; base < r1; base += Gm::RPB) {
+    for (int base = r0; base < r1; base += RPB) {
         const int row = base + rl;
         T sum = T(0);
         if (row < r1) {
             const int p1 = rp[row + 1];
-            for (int p = rp[row] + g; p < p1; p += Gm::G) sum += av[p] * gx(ci[p], c);
+            for (int p = rp[row] + g; p < p1; p += G) sum += av[p] * gx(ci[p], c);
         }
-#pragma unroll
-        for (int off = NB; off < Gm::LPR; off <<= 1) sum += __shfl_xor(sum, off);
+        for (int off = NB; off < LPR; off <<= 1) sum += __shfl_xor(sum, off);
         if (row < r1 && g == 0) ep(row, c, sum, acc);
     }
     if constexpr (NV > 0) block_partials<NV, NB>(acc, red);

@@ -28,10 +28,11 @@ template <int NB> struct Solver {
 
     template <typename T, int NV, class GX, class EP, class FIN>
     void spmv(const DCsr &A, const T *vals, GX gx, EP ep, FIN fin, const int *stop) {
-        const int g = grid_rows(A.n, Geo<NB>::RPB, NV > 0 ? kMaxGrid : kMaxGridPlain);
+        const Geo geo = make_geo(A.nnz, A.n, NB);
+        const int g = grid_rows(A.n, geo.rpb(), NV > 0 ? kMaxGrid : kMaxGridPlain);
         Reducer<(NV > 0 ? NV : 1), NB> red{c.partial};
         hipLaunchKernelGGL((spmv_kernel<T, NB, NV, GX, EP>), dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci, vals,
-                           gx, ep, red, stop);
+                           gx, ep, geo, red, stop);
         finish<NV>(g, fin, stop);
     }
 
@@ -99,41 +100,110 @@ template <int NB> struct Solver {
         AMG_HIP(hipGetLastError());
     }
 
+    // ---------------- graph capture ----------------
+    // Records the launches of body() on the private capture stream and
+    // instantiates them; the graph is replayed on the context's stream.
+    template <class F> hipGraphExec_t capture(F &&body) {
+        const hipStream_t saved = s;
+        s = c.cap_stream;
+        AMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipGraph_t g = nullptr;
+        try {
+            body();
+        } catch (...) {
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            s = saved;
+            throw;
+        }
+        AMG_HIP(hipStreamEndCapture(s, &g));
+        s = saved;
+        hipGraphExec_t e = nullptr;
+        const hipError_t rc = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        AMG_HIP(rc);
+        c.graphs.push_back(e);
+        return e;
+    }
+
+    void launch(hipGraphExec_t g) { AMG_HIP(hipGraphLaunch(g, s)); }
+
+    void post_flag(const CgScal *sc, int slot) {
+        AMG_HIP(hipMemcpyAsync(&c.hflag[slot], &sc->all_conv, sizeof(int), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipEventRecord(c.poll_ev[slot], s));
+    }
+
+    bool wait_flag(int slot) {
+        AMG_HIP(hipEventSynchronize(c.poll_ev[slot]));
+        return c.hflag[slot] != 0;
+    }
+
     // ---------------- conjugate gradients ----------------
     // JAC: Jacobi preconditioner (mass matrices), else the V-cycle from level j.
-    // Returns the largest iteration count over the columns.
+    // One CG iteration (p_new = z + beta p_old, q = A p_new, alpha; x, r update
+    // and the convergence test; z = B r and beta) is a fixed sequence of
+    // launches on fixed buffers, captured once per workspace in two graphs
+    // (even and odd iterations swap p_old and p_new).  The host launches the
+    // iterations it expects from the previous solve at this level, then keeps
+    // one iteration in flight while it reads the convergence flag of the one
+    // before; iterations after convergence return at once in every kernel.
+    // Returns the largest iteration count over the columns; x_out gets x.
+    template <typename T, bool JAC>
+    void cg_iter(int j, const DCsr &A, const T *vals, const T *dinv, CgWs<T> &w, T *pold, T *pnew) {
+        const int n = A.n;
+        const int *stop = &w.sc->all_conv;
+        spmv<T, 1>(A, vals, GZBP<T, NB>{w.z, pold, w.sc}, ECgQ<T, NB>{w.z, pold, pnew, w.q, w.sc},
+                   FinAlpha<NB>{w.sc, 0}, stop);
+        elem<JAC ? 2 : 1>(n, OpUpd<T, NB, JAC>{w.x, w.r, w.z, pnew, w.q, dinv, w.sc}, FinUpd<NB, JAC>{w.sc}, stop);
+        if constexpr (!JAC) vcycle<T>(j, w.r, w.z, w.sc, stop);
+    }
+
     template <typename T, bool JAC>
     int cg(int j, const DCsr &A, const T *vals, const double *mdinv, CgWs<T> &w, const T *b, T *x, double rtol,
            int maxit, int nlive) {
         const int n = A.n;
-        T *pold = w.p0, *pnew = w.p1;
         const int *stop = &w.sc->all_conv;
         const T *dinv = nullptr;
         if constexpr (JAC) dinv = mdinv;
-        elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, pold, w.z, dinv}, FinInit<NB, JAC>{w.sc, rtol, nlive},
+        elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, w.x, w.p0, w.z, dinv}, FinInit<NB, JAC>{w.sc, rtol, nlive},
                           nullptr);
-        if constexpr (!JAC) vcycle<T>(j, w.r, w.z, w.sc, stop);
+        const bool graphs = c.o.use_graphs != 0;
+        if (graphs && !w.ga) {
+            if constexpr (!JAC) w.g0 = capture([&] { vcycle<T>(j, w.r, w.z, w.sc, stop); });
+            w.ga = capture([&] { cg_iter<T, JAC>(j, A, vals, dinv, w, w.p0, w.p1); });
+            w.gb = capture([&] { cg_iter<T, JAC>(j, A, vals, dinv, w, w.p1, w.p0); });
+        }
+        if constexpr (!JAC) {
+            if (graphs) launch(w.g0);
+            else vcycle<T>(j, w.r, w.z, w.sc, stop);
+        }
         int it = 0;
-        int next = std::max(1, w.pred);
-        const int every = std::max(1, c.o.check_every);
-        while (true) {
-            spmv<T, 1>(A, vals, GZBP<T, NB>{w.z, pold, w.sc}, ECgQ<T, NB>{w.z, pold, pnew, w.q, w.sc},
-                       FinAlpha<NB>{w.sc, 0}, stop);
-            elem<JAC ? 2 : 1>(n, OpUpd<T, NB, JAC>{x, w.r, w.z, pnew, w.q, dinv, w.sc}, FinUpd<NB, JAC>{w.sc},
-                              stop);
-            if constexpr (!JAC) vcycle<T>(j, w.r, w.z, w.sc, stop);
-            std::swap(pold, pnew);
+        auto step = [&]() {
+            if (graphs) launch((it & 1) ? w.gb : w.ga);
+            else if (it & 1) cg_iter<T, JAC>(j, A, vals, dinv, w, w.p1, w.p0);
+            else cg_iter<T, JAC>(j, A, vals, dinv, w, w.p0, w.p1);
             ++it;
-            if (it >= next || it >= maxit) {
-                read_sc(w.sc);
-                if (c.hsc->all_conv) break;
-                if (it >= maxit) {
-                    w.pred = it;
-                    fail(AMG_ERR_NOCONV,
-                         std::string(JAC ? "mass" : "inner") + " CG did not converge at level " + std::to_string(j));
-                }
-                next = it + every;
+        };
+        const int first = std::min(std::max(1, w.pred - 1), maxit);
+        while (it < first) step();
+        post_flag(w.sc, 0);
+        int cur = 0;
+        bool done = false;
+        while (!done) {
+            if (it >= maxit) {
+                done = wait_flag(cur);
+                break;
             }
+            step();
+            post_flag(w.sc, cur ^ 1);
+            done = wait_flag(cur);
+            cur ^= 1;
+        }
+        read_sc(w.sc);
+        if (!c.hsc->all_conv) {
+            w.pred = it;
+            fail(AMG_ERR_NOCONV, std::string(JAC ? "mass" : "inner") + " CG did not converge at level " +
+                                     std::to_string(j));
         }
         int mx = 0;
         for (int col = 0; col < NB; ++col) {
@@ -143,6 +213,7 @@ template <int NB> struct Solver {
             mx = std::max(mx, c.hsc->s[col].iters);
         }
         w.pred = mx;
+        AMG_HIP(hipMemcpyAsync(x, w.x, sizeof(T) * (size_t)n * NB, hipMemcpyDeviceToDevice, s));
         return mx;
     }
 
