@@ -90,6 +90,12 @@ typedef struct {
     int32_t precond;        /* 1: multilevel preconditioner, 0: plain outer CG */
     int32_t check_every;    /* inner CG: host convergence poll period after the predicted count (1) */
     int32_t use_graphs;     /* 1: replay CG iterations from captured HIP graphs (default), 0: launch eagerly */
+    double coarse_hess_rtol;/* coarsest Hessian level above dense_max: unpreconditioned CG to this
+                               relative residual (1e-4, Section 5.2); at or below dense_max it is
+                               inverted exactly (Section 3.2) */
+    int32_t dense_solve_max;/* coarse levels j >= 1 (below the coarsest) with at most this many rows
+                               solve A_j and M_j exactly with dense inverses instead of CG (2048;
+                               0 = always iterative) */
 } amg_opts;
 
 typedef struct {
@@ -134,6 +140,9 @@ int amg_p1_assemble(int dim, int32_t nv, const double *coords, int32_t ne, const
  *   A, M: the assembled stiffness and mass matrices (device CSR, same pattern not
  *         required), N x N, exactly symmetric.
  *   dirichlet: device uint8 [N] (1 = Dirichlet node) or NULL (none).
+ *   The coarsest AMG level must have at most opts.dense_max rows (else
+ *   DENSE_TOO_LARGE); the coarsest Hessian level may be larger (see
+ *   coarse_hess_rtol).
  *   opts: NULL for defaults.  stream: a hipStream_t or NULL (default stream).
  * Errors: ARG, NOT_SYMMETRIC, NOT_SPD, DENSE_TOO_LARGE, CAPACITY, OOM, HIP.
  * On error *out is NULL and nothing is leaked. */
@@ -200,9 +209,13 @@ const char *amg_last_error(amg_ctx *ctx);
 
 /* Average device time of `reps` back-to-back launches of one kernel on the context's
  * stream, measured with HIP events: which = 0: level-0 CSR SpMV (q = A_0 p), 1: the
- * level-0 fused l1-Jacobi post-smoothing sweep, 2: a whole V-cycle from level 0.
- * prec: 64 or 32; nb as above.  *ms_avg receives milliseconds per launch and
- * *bytes the algorithmic bytes one launch moves. */
+ * level-0 first l1-Jacobi sweep fused with the residual (x = D^{-1} b, r = b - A_0 x,
+ * the V-cycle's first kernel), 2: a whole V-cycle from level 0.  The kernels see
+ * zero vectors.  prec: 64 or 32 (32 needs inner_precision 32); nb as above.
+ * *ms_avg receives milliseconds per launch and *bytes the algorithmic bytes one
+ * launch moves (row pointers, column indices and values once, every vector it
+ * reads or gathers once, every vector it writes once).
+ * Errors: ARG. */
 int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double *ms_avg,
                     double *bytes);
 

@@ -32,6 +32,9 @@ operation order (readings recorded with the design notes):
              matrices coincide: M_{j+1} = S_j^T M_j S_j
   stop       level j is the coarsest when n_j <= max_coarse, when
              j + 1 = max_levels, or when n_{j+1} > 0.9 n_j
+  small      on coarse levels (j >= 1) with n_j <= dense_solve_max the
+             A_j- and M_j-solves are exact (dense Cholesky) instead of
+             iterative; they return what the iterative solves approximate
 """
 from __future__ import annotations
 
@@ -231,6 +234,7 @@ class Opts:
     max_levels: int = 10
     max_coarse: int = 200
     dense_max: int = 4096
+    dense_solve_max: int = 2048     # coarse levels j >= 1 this small: exact dense A_j and M_j solves
     theta0: float = 0.08
     agg_seed: int = 0x200111533
     nu: int = 1
@@ -240,6 +244,7 @@ class Opts:
     inner_maxit: int = 500
     mass_maxit: int = 500
     outer_maxit: int = 200
+    coarse_hess_rtol: float = 1e-4
     inner32_rtol: float = 1e-6
     refine_maxit: int = 6
     precond: int = 1                # 0: unpreconditioned outer CG
@@ -258,6 +263,8 @@ class Level:
     strong: np.ndarray | None = None
     omega: float = 0.0
     rho: float = 0.0
+    chol_A: tuple | None = None     # dense factors on small coarse levels
+    chol_M: tuple | None = None
 
     @property
     def n(self) -> int:
@@ -306,6 +313,11 @@ def build(A0: CSR, M: CSR, dirichlet: np.ndarray, opts: Opts) -> Hierarchy:
         levels.append(Level(Ac, Mc, np.zeros(nc, dtype=bool), l1_diag(Ac)))
         j += 1
     h = Hierarchy(levels, opts)
+    for j in range(1, len(levels) - 1):
+        lev = levels[j]
+        if lev.n <= opts.dense_solve_max:
+            lev.chol_A = sla.cho_factor(lev.A.dense(), lower=True)
+            lev.chol_M = sla.cho_factor(lev.M.dense(), lower=True)
     last = levels[-1]
     if last.n > opts.dense_max:
         raise RuntimeError("coarsest level too large for the dense factor")
@@ -360,12 +372,17 @@ def dense_level_matrices(h: Hierarchy, j: int):
 def set_hessian_levels(h: Hierarchy, ell: int) -> None:
     """Form the dense practical-form Hessian H = X^T M_y X + beta M_u with
     X = A^{-1} M_yu at level ell-1 (the coarsest Hessian level, solved exactly
-    as the theory of Section 3.2 assumes), symmetrise it and factor it."""
+    as the theory of Section 3.2 assumes), symmetrise it and factor it.  Above
+    dense_max rows no dense matrix is formed: that level is then solved by
+    unpreconditioned CG to a loose tolerance, the practice of Section 5.2."""
     ell = max(1, min(ell, h.L))
     c = ell - 1
     n = h.levels[c].n
+    h.ell = ell
     if n > h.opts.dense_max:
-        raise RuntimeError("coarsest Hessian level too large for the dense factor")
+        h.H_dense = None
+        h.chol_H = None
+        return
     A, My, Mu, Myu = dense_level_matrices(h, c)
     X = sla.cho_solve(sla.cho_factor(A, lower=True), Myu)
     H = X.T @ (My @ X) + h.opts.beta * Mu

@@ -54,6 +54,7 @@ class Counters:
     mass_iters: int = 0
     outer_iters: int = 0
     refine_steps: int = 0
+    coarse_cg_iters: int = 0
     history: list = field(default_factory=list)
 
 
@@ -144,6 +145,8 @@ class Oracle:
         h = self.h
         if j == h.L - 1:
             return sla.cho_solve(h.chol_A, f)
+        if h.levels[j].chol_A is not None:
+            return sla.cho_solve(h.levels[j].chol_A, f)
         if self.mixed:
             return self._solve_A_mixed(j, f, rtol)
         A = h.levels[j].A
@@ -209,6 +212,8 @@ class Oracle:
         raise NoConvergence("refinement did not converge")
 
     def mass_solve(self, j: int, r: np.ndarray) -> np.ndarray:
+        if self.h.levels[j].chol_M is not None:
+            return sla.cho_solve(self.h.levels[j].chol_M, r)
         M = self.h.levels[j].M
         d = M.diag()
         x, it = pcg(M.matvec, lambda v: v / d, r, self.o.mass_rtol, self.o.mass_maxit)
@@ -244,7 +249,14 @@ class Oracle:
     def B(self, j: int, r: np.ndarray) -> np.ndarray:
         h = self.h
         if j == h.ell - 1:
-            return sla.cho_solve(h.chol_H, r)
+            if h.chol_H is not None:
+                return sla.cho_solve(h.chol_H, r)
+            # Section 5.2: the coarsest Hessian solve by unpreconditioned CG
+            # to a loose relative residual (1e-4)
+            x, it = pcg(lambda v: self.hessian_apply(j, v, self.o.precond_inner_rtol), lambda v: v.copy(), r,
+                        self.o.coarse_hess_rtol, self.o.outer_maxit)
+            self.cnt.coarse_cg_iters += it
+            return x
         z = self.C(j, r)
         if j > 0:
             z = z + self.C(j, r - self.hessian_apply(j, z, self.o.precond_inner_rtol))

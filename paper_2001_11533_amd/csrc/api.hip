@@ -37,24 +37,30 @@ template <class F> int guarded(Ctx *c, F &&f) {
     }
 }
 
-void alloc_cg(Arena &a, CgWs<double> &w, size_t m) {
-    w.x = a.alloc<double>(m);
-    w.r = a.alloc<double>(m);
-    w.z = a.alloc<double>(m);
-    w.p0 = a.alloc<double>(m);
-    w.p1 = a.alloc<double>(m);
-    w.q = a.alloc<double>(m);
-    w.sc = a.alloc<CgScal>(1);
+// a mailbox from the pinned pool, its device view stored in the device-side struct
+Mail *take_mail(Ctx &c, Mail **dev_slot) {
+    if (c.nmail >= 64) fail(AMG_ERR_OOM, "mailbox pool exhausted");
+    Mail *h = &c.mails[c.nmail++];
+    std::memset(h, 0, sizeof(Mail));
+    void *d = nullptr;
+    AMG_HIP(hipHostGetDevicePointer(&d, h, 0));
+    AMG_HIP(hipMemcpy(dev_slot, &d, sizeof(void *), hipMemcpyHostToDevice));
+    return h;
 }
-void alloc_cg(Arena &a, CgWs<float> &w, size_t m) {
-    w.x = a.alloc<float>(m);
-    w.r = a.alloc<float>(m);
-    w.z = a.alloc<float>(m);
-    w.p0 = a.alloc<float>(m);
-    w.p1 = a.alloc<float>(m);
-    w.q = a.alloc<float>(m);
+
+template <typename T> void alloc_cg(Ctx &c, CgWs<T> &w, size_t m) {
+    Arena &a = c.arena;
+    w.x = a.alloc<T>(m);
+    w.r = a.alloc<T>(m);
+    w.z = a.alloc<T>(m);
+    w.p0 = a.alloc<T>(m);
+    w.p1 = a.alloc<T>(m);
+    w.q = a.alloc<T>(m);
     w.sc = a.alloc<CgScal>(1);
+    AMG_HIP(hipMemset(w.sc, 0, sizeof(CgScal)));
+    w.hmail = take_mail(c, &w.sc->mail);
 }
+
 template <typename T> void alloc_vc(Arena &a, VcWs<T> &v, size_t m) {
     v.b = a.alloc<T>(m);
     v.x = a.alloc<T>(m);
@@ -64,17 +70,19 @@ template <typename T> void alloc_vc(Arena &a, VcWs<T> &v, size_t m) {
 
 void alloc_workspaces(Ctx &c) {
     Arena &a = c.arena;
+    AMG_HIP(hipStreamSynchronize(c.stream));
     const int nbp = c.nbp;
     c.ws.assign(c.L, LevelWs{});
     const bool mixed = c.o.inner_precision == 32;
     for (int l = 0; l < c.L; ++l) {
         LevelWs &w = c.ws[l];
         const size_t m = (size_t)c.lev[l].n * nbp;
-        alloc_cg(a, w.in64, m);
-        alloc_cg(a, w.mass, m);
+        alloc_cg(c, w.in64, m);
+        alloc_cg(c, w.mass, m);
+        alloc_cg(c, w.hcg, m);
         alloc_vc(a, w.vc64, m);
         if (mixed) {
-            alloc_cg(a, w.in32, m);
+            alloc_cg(c, w.in32, m);
             alloc_vc(a, w.vc32, m);
             w.rr = a.alloc<double>(m);
             w.b32 = a.alloc<float>(m);
@@ -92,13 +100,15 @@ void alloc_workspaces(Ctx &c) {
         w.ml_t = a.alloc<double>(m);
     }
     const size_t m0 = (size_t)c.N * nbp;
-    alloc_cg(a, c.outer, m0);
+    alloc_cg(c, c.outer, m0);
     c.ox = a.alloc<double>(m0);
     c.ob = a.alloc<double>(m0);
     c.obq = a.alloc<double>(m0);
     c.pk_in = a.alloc<double>(m0);
     c.pk_out = a.alloc<double>(m0);
     c.rsd = a.alloc<RefScal>(1);
+    AMG_HIP(hipMemset(c.rsd, 0, sizeof(RefScal)));
+    c.rmail = take_mail(c, &c.rsd->mail);
 }
 
 void fill_info(Ctx &c, amg_info *info, int n, double ms, int outer_it) {
@@ -172,6 +182,8 @@ int amg_opts_default(amg_opts *o) {
     o->precond = 1;
     o->check_every = 1;
     o->use_graphs = 1;
+    o->coarse_hess_rtol = 1e-4;
+    o->dense_solve_max = 2048;
     return AMG_OK;
 }
 
@@ -197,7 +209,8 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
     if (!(o.beta > 0.0) || o.nb_max < 1 || o.nb_max > 16 || o.max_levels < 1 || o.max_coarse < 1 ||
         o.dense_max < 1 || o.dense_max > 4096 || (o.inner_precision != 32 && o.inner_precision != 64) ||
         o.nu != 1 || o.inner_maxit < 1 || o.mass_maxit < 1 || o.outer_maxit < 1 || o.hess_levels < 0 ||
-        !(o.theta0 >= 0.0) || o.refine_maxit < 1 || o.use_graphs < 0 || o.use_graphs > 1) {
+        !(o.theta0 >= 0.0) || o.refine_maxit < 1 || o.use_graphs < 0 || o.use_graphs > 1 ||
+        !(o.coarse_hess_rtol > 0.0) || o.dense_solve_max < 0 || o.dense_solve_max > 4096) {
         g_setup_err = "invalid options (beta > 0, 1 <= nb_max <= 16, dense_max <= 4096, nu = 1, precision 32/64)";
         return AMG_ERR_ARG;
     }
@@ -209,14 +222,13 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
     c.nbp = pad_nb(o.nb_max);
     int rc = guarded(nullptr, [&]() {
         c.lev.reserve(o.max_levels + 1);
-        c.partial = c.arena.alloc<double>((size_t)2 * 16 * kMaxGrid);
+        for (auto &p : c.part) p = c.arena.alloc<double>((size_t)2 * 16 * kMaxGrid);
         c.dscratch = c.arena.alloc<double>(64);
         c.iscratch = c.arena.alloc<int>(64);
         AMG_HIP(hipHostMalloc((void **)&c.hsc, sizeof(CgScal), hipHostMallocDefault));
         AMG_HIP(hipHostMalloc((void **)&c.hscr, 64 * sizeof(double), hipHostMallocDefault));
         AMG_HIP(hipHostMalloc((void **)&c.hiscr, 64 * sizeof(int), hipHostMallocDefault));
-        AMG_HIP(hipHostMalloc((void **)&c.rsh, sizeof(RefScal), hipHostMallocDefault));
-        AMG_HIP(hipHostMalloc((void **)&c.hflag, 2 * sizeof(int), hipHostMallocDefault));
+        AMG_HIP(hipHostMalloc((void **)&c.mails, 64 * sizeof(Mail), hipHostMallocDefault));
         AMG_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
         for (auto &e : c.poll_ev) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         build_hierarchy(c, *A, *M, dirichlet);
@@ -241,8 +253,7 @@ int amg_destroy(amg_ctx *ctx) {
     if (c.hsc) (void)hipHostFree(c.hsc);
     if (c.hscr) (void)hipHostFree(c.hscr);
     if (c.hiscr) (void)hipHostFree(c.hiscr);
-    if (c.rsh) (void)hipHostFree(c.rsh);
-    if (c.hflag) (void)hipHostFree(c.hflag);
+    if (c.mails) (void)hipHostFree(c.mails);
     for (auto g : c.graphs) (void)hipGraphExecDestroy(g);
     for (auto e : c.poll_ev)
         if (e) (void)hipEventDestroy(e);
@@ -546,10 +557,10 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                         S.template spmv<T, 0>(L0.A, avals<T>(L0.A), GPlain<T, NB>{v.x}, EStore<T, NB>{v.r}, NoFin{},
                                               nullptr);
                     else if (which == 1)
-                        S.template spmv<T, 0>(L0.A, avals<T>(L0.A), GPlain<T, NB>{v.x},
-                                              EPost<T, NB, false>{dl1inv<T>(L0), v.b, v.x, v.x2}, NoFin{}, nullptr);
+                        S.template spmv<T, 0>(L0.A, avals<T>(L0.A), GDinvB<T, NB>{dl1inv<T>(L0), v.b},
+                                              EPre<T, NB>{dl1inv<T>(L0), v.b, v.x, v.r}, NoFin{}, nullptr);
                     else
-                        S.template vcycle<T>(0, v.b, v.x2, nullptr, nullptr);
+                        S.template vcycle<T>(0, v.b, v.x2, false, nullptr);
                 };
                 // defined inputs
                 AMG_HIP(hipMemsetAsync(v.x, 0, sizeof(T) * n * NB, c.stream));
@@ -570,7 +581,8 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
             *ms_avg = ms / reps;
             if (bytes) {
                 if (which == 0) *bytes = spmv_b;
-                else if (which == 1) *bytes = spmv_b + sz * n * nbd /*b*/ + sz * n /*dinv*/;
+                else if (which == 1)  // gathers dinv and b once each, writes x and r
+                    *bytes = 4.0 * (n + 1) + (4.0 + sz) * L0.A.nnz + sz * n + 3.0 * sz * n * nbd;
                 else {
                     double tot = 0.0;
                     for (int l = 0; l < c.L - 1; ++l) {

@@ -71,8 +71,9 @@ struct DCsr {
 };
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
-constexpr int kMaxGrid = 1024;       // workgroups at most for kernels with reductions
-constexpr int kMaxGridPlain = 8192;  // and for kernels without
+constexpr int kMaxGrid = 16384;        // workgroups at most for kernels with reductions
+constexpr int kMaxGridPlain = 1 << 20; // and for kernels without
+constexpr int kFinBlock = 1024;        // threads of a finalize kernel
 constexpr int kXcd = 8;          // XCDs of an MI355X
 
 inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }

@@ -21,11 +21,14 @@ struct Level {
     uint8_t *root = nullptr;
     const uint8_t *mask = nullptr;  // Dirichlet flags, level 0 only
     double omega = 0.0, rho = 0.0;
+    double *Ainv = nullptr;     // small coarse levels: dense inverses of A_j and M_j
+    double *Minv = nullptr;
 };
 
 template <typename T> struct CgWs {
     T *x = nullptr, *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
     CgScal *sc = nullptr;
+    Mail *hmail = nullptr;  // host view of the mailbox the finalize kernels write
     int pred = 0;  // iteration count of the previous solve (poll schedule)
     // captured graphs: first preconditioner application, iteration p0->p1, iteration p1->p0
     hipGraphExec_t g0 = nullptr, ga = nullptr, gb = nullptr;
@@ -36,7 +39,7 @@ template <typename T> struct VcWs {
 };
 
 struct LevelWs {
-    CgWs<double> in64, mass;
+    CgWs<double> in64, mass, hcg;  // inner A-solves, mass solves, coarsest-Hessian CG
     CgWs<float> in32;
     VcWs<double> vc64;
     VcWs<float> vc32;
@@ -51,7 +54,7 @@ struct LevelWs {
 };
 
 struct Stats {
-    long inner_solves = 0, inner_iters = 0, inner_max = 0, mass_iters = 0, refine = 0;
+    long inner_solves = 0, inner_iters = 0, inner_max = 0, mass_iters = 0, refine = 0, coarse_cg = 0;
     void reset() { *this = Stats(); }
 };
 
@@ -60,7 +63,6 @@ struct Ctx {
     hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
     std::vector<hipGraphExec_t> graphs; // every instantiated graph (freed with the context)
     hipEvent_t poll_ev[2] = {nullptr, nullptr};
-    int *hflag = nullptr;               // pinned [2]: convergence flags in flight
     amg_opts o{};
     Arena arena;
     int N = 0;
@@ -74,7 +76,8 @@ struct Ctx {
     double *Hdense = nullptr, *Hinv = nullptr;  // practical-form Hessian at level ell-1
     int nH = 0;
     // reductions (one stream: a single partial buffer and ticket suffice)
-    double *partial = nullptr;
+    double *part[3] = {nullptr, nullptr, nullptr};  // reduction partials [2*16*kMaxGrid] each
+    int pgrid[3] = {0, 0, 0};                       // workgroups that wrote each buffer
     double *dscratch = nullptr;  // small device scalars [64]
     int *iscratch = nullptr;     // small device ints [64]
     // host mirrors
@@ -87,7 +90,9 @@ struct Ctx {
     double *pk_in = nullptr, *pk_out = nullptr;  // packing buffers [N x nbp]
     // refinement per-column data (device) and its pinned host mirror
     RefScal *rsd = nullptr;
-    RefScal *rsh = nullptr;
+    Mail *rmail = nullptr;              // host view of the refinement mailbox
+    Mail *mails = nullptr;              // pinned pool of mailboxes
+    int nmail = 0;
     Stats st;
     std::string err;
     bool has_mask = false;

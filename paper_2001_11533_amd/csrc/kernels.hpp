@@ -33,13 +33,42 @@ struct ColScal {
     int conv, iters, bad, pad;
 };
 
+// What the host needs to steer a CG, written by the finalize kernels into
+// pinned host memory (read after an event, no copy kernels).
+struct Mail {
+    int all_conv;
+    int bad;
+    int iters;       // largest iteration count over the columns
+    int indefinite;
+    int nlive;       // refinement: columns still refining
+    int stagnated;
+    int pad[2];
+};
+
 struct CgScal {
     ColScal s[16];
     int all_conv;
     int nb;          // live columns; columns >= nb are padding and stay frozen
     int indefinite;  // outer CG: p.q <= 0 or r.z <= 0 met on a live column
     int pad;
+    Mail *mail;      // host-mapped mailbox of this CG
+    void *xptr;      // where the CG accumulates its solution (set at start)
 };
+
+__device__ __forceinline__ void publish(CgScal *sc, int NBc) {
+    int all = 1, bad = 0, it = 0;
+    for (int c = 0; c < NBc; ++c) {
+        all &= sc->s[c].conv;
+        bad |= sc->s[c].bad;
+        it = max(it, sc->s[c].iters);
+    }
+    sc->all_conv = all;
+    Mail *m = sc->mail;
+    m->iters = it;
+    m->bad = bad;
+    m->indefinite = sc->indefinite;
+    m->all_conv = all;
+}
 
 __device__ __forceinline__ int xcd_block(int b, int nblk) {
     // Workgroups are dispatched round-robin over the XCDs; give each XCD a
@@ -63,11 +92,15 @@ inline int ilog2(int x) {
     return l;
 }
 
-// G = next power of two >= (mean entries per row) / 2, at most 64 / NB
+// entries a lane loads together (wide batches: one lane per column walks the row)
+template <int NB> constexpr int spmv_unroll() { return NB >= 8 ? 16 : 4; }
+
+// G = next power of two >= (mean entries per row) / U, at most 64 / NB
 inline Geo make_geo(long nnz, long rows, int NB) {
     const double m = rows > 0 ? (double)nnz / (double)rows : 1.0;
+    const double u = NB >= 8 ? 16.0 : 4.0;
     int g = 1;
-    while (g < 64 && g < m / 2.0) g <<= 1;
+    while (g < 64 && g < m / u) g <<= 1;
     while (g * NB > 64) g >>= 1;
     if (g < 1) g = 1;
     Geo geo;
@@ -108,16 +141,13 @@ __device__ void block_partials(const double (&acc)[NV], Reducer<NV, NB> r) {
     if (t < NV * NB) r.partial[(size_t)t * gridDim.x + blockIdx.x] = red[t / NB][t % NB];
 }
 
-// One workgroup: sums the nblk partials of each (quantity, column) in a fixed
-// order and runs the finalize step on thread 0.
-template <int NV, int NB, class FIN>
-__global__ __launch_bounds__(kBlock) void fin_kernel(const double *__restrict__ partial, int nblk, FIN fin,
-                                                     const int *__restrict__ stop) {
-    if (stop && *stop) return;
-    __shared__ double red[kBlock];
-    __shared__ double tot[NV][NB];
+// Sums the nblk partials of each (quantity, column) in a fixed order with
+// all threads of the workgroup; every thread sees the totals in tot.
+template <int NV, int NB, int BS = kBlock>
+__device__ void sum_partials(const double *__restrict__ partial, int nblk, double (&tot)[NV][NB]) {
+    __shared__ double red[BS];
     constexpr int Q = NV * NB;
-    constexpr int LPS = pow2floor(kBlock / Q);
+    constexpr int LPS = pow2floor(BS / Q);
     const int t = threadIdx.x;
     const int q = t / LPS, sub = t % LPS;
     double s = 0.0;
@@ -133,7 +163,28 @@ __global__ __launch_bounds__(kBlock) void fin_kernel(const double *__restrict__ 
     }
     if (q < Q && sub == 0) tot[q / NB][q % NB] = red[t];
     __syncthreads();
-    if (t == 0) fin(tot);
+}
+
+// One workgroup: totals of the partials, then the finalize step on thread 0.
+template <int NV, int NB, class FIN>
+__global__ __launch_bounds__(kFinBlock) void fin_kernel(const double *__restrict__ partial, int nblk, FIN fin,
+                                                        const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    __shared__ double tot[NV][NB];
+    sum_partials<NV, NB, kFinBlock>(partial, nblk, tot);
+    if (threadIdx.x == 0) fin(tot);
+}
+
+// The same with two partial buffers (one quantity each).
+template <int NB, class FIN>
+__global__ __launch_bounds__(kFinBlock) void fin2_kernel(const double *__restrict__ pa, int na,
+                                                         const double *__restrict__ pb, int nb, FIN fin,
+                                                         const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    __shared__ double ta[1][NB], tb[1][NB];
+    sum_partials<1, NB, kFinBlock>(pa, na, ta);
+    sum_partials<1, NB, kFinBlock>(pb, nb, tb);
+    if (threadIdx.x == 0) fin(ta, tb);
 }
 
 struct NoFin {
@@ -143,7 +194,9 @@ struct NoFin {
 // ---------------------------------------------------------------------------
 // CSR SpMV / SpMM with a gather functor (how x_k is formed) and an epilogue
 // functor (what is written for row i); optional fused reductions.
-template <typename T, int NB, int NV, class GX, class EP>
+// FINE = 1 marks launches on the finest level (a separate instantiation, so that
+// profiles separate the fine-level kernels from the coarse-level ones).
+template <typename T, int NB, int NV, class GX, class EP, int FINE>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__restrict__ rp,
                                                       const int *__restrict__ ci,
                                                       const T *__restrict__ av, GX gx, EP ep, Geo geo,
@@ -163,21 +216,38 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__re
     double acc[NVA];
 #pragma unroll
     for (int v = 0; v < NVA; ++v) acc[v] = 0.0;
+    constexpr int U = spmv_unroll<NB>();  // entries per lane issued together
     for (int base = r0; base < r1; base += RPB) {
         const int row = base + rl;
+        const bool live = row < r1;
+        typename EP::P pr{};
+        if (live && g == 0) pr = ep.load(row, c);
         T sum = T(0);
-        if (row < r1) {
+        if (live) {
             const int p1 = rp[row + 1];
-            for (int p = rp[row] + g; p < p1; p += G) sum += av[p] * gx(ci[p], c);
+            for (int p = rp[row] + g; p < p1; p += U * G) {
+                int kk[U];
+                T aa[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int q = p + u * G;
+                    const bool ok = q < p1;
+                    kk[u] = ok ? ci[q] : -1;
+                    aa[u] = ok ? av[q] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (kk[u] >= 0) sum += aa[u] * gx(kk[u], c);
+            }
         }
         for (int off = NB; off < LPR; off <<= 1) sum += __shfl_xor(sum, off);
-        if (row < r1 && g == 0) ep(row, c, sum, acc);
+        if (live && g == 0) ep(row, c, sum, pr, acc);
     }
     if constexpr (NV > 0) block_partials<NV, NB>(acc, red);
 }
 
 // Elementwise kernel over n rows x NB columns with fused reductions.
-template <int NB, int NV, class OP>
+template <int NB, int NV, class OP, int FINE>
 __global__ __launch_bounds__(kBlock) void elem_kernel(int n, OP op, Reducer<(NV > 0 ? NV : 1), NB> red,
                                                       const int *__restrict__ stop) {
     if (stop && *stop) return;
@@ -194,6 +264,82 @@ __global__ __launch_bounds__(kBlock) void elem_kernel(int n, OP op, Reducer<(NV 
     for (int v = 0; v < NVA; ++v) acc[v] = 0.0;
     for (long e = e0 + t; e < e1; e += kBlock) op((int)(e / NB), c, acc);
     if constexpr (NV > 0) block_partials<NV, NB>(acc, red);
+}
+
+// CG update: every workgroup first sums the p.q partials of the preceding
+// operator kernel (same fixed order in all workgroups, so all agree on alpha),
+// then x += alpha p, r -= alpha q (Jacobi: z = dinv r) on the live columns,
+// with the partials of r.r (and r.z).  Workgroup 0 records alpha and flags a
+// non-positive p.q (breakdown, or indefiniteness for the outer CG).
+template <typename T, int NB, bool JAC, int FINE>
+__global__ __launch_bounds__(kBlock) void cg_update_kernel(int n, T *__restrict__ x, T *__restrict__ r,
+                                                           T *__restrict__ z, const T *__restrict__ p,
+                                                           const T *__restrict__ q, const T *__restrict__ dinv,
+                                                           CgScal *sc, const double *__restrict__ part_pq,
+                                                           int nblk_pq, int outer,
+                                                           Reducer<JAC ? 2 : 1, NB> red,
+                                                           const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    if (!x) x = static_cast<T *>(sc->xptr);
+    __shared__ double pq[1][NB];
+    __shared__ double sh_a[NB];
+    __shared__ int sh_live[NB];
+    const int t = threadIdx.x;
+    if (nblk_pq > 0) sum_partials<1, NB>(part_pq, nblk_pq, pq);
+    if (nblk_pq == 0) {
+        // alpha was formed by a finalize kernel (many partials)
+        if (t < NB) {
+            sh_a[t] = sc->s[t].alpha;
+            sh_live[t] = !sc->s[t].conv;
+        }
+    } else if (t < NB) {
+        ColScal &s = sc->s[t];
+        const double v = pq[0][t];
+        double a = 0.0;
+        int live = !s.conv;
+        if (live) {
+            if (v > 0.0) {
+                a = s.rho / v;
+            } else {
+                live = 0;
+                if (blockIdx.x == 0) {
+                    s.bad = 1;
+                    if (outer) sc->indefinite = 1;
+                }
+            }
+        }
+        sh_a[t] = a;
+        sh_live[t] = live;
+        if (blockIdx.x == 0) {
+            s.alpha = a;
+            s.pq = v;
+        }
+    }
+    __syncthreads();
+    const int c = t % NB;
+    const T a = (T)sh_a[c];
+    const int live = sh_live[c];
+    const int nblk = gridDim.x, b = xcd_block(blockIdx.x, nblk);
+    const long total = (long)n * NB;
+    const long span = (long)ceil_div_dev_l(total, (long)nblk * kBlock) * kBlock;
+    const long e0 = (long)b * span;
+    const long e1 = total < e0 + span ? total : e0 + span;
+    double acc[JAC ? 2 : 1] = {};
+    if (live) {
+        for (long e = e0 + t; e < e1; e += kBlock) {
+            const size_t o = (size_t)e;
+            x[o] += a * p[o];
+            const T rv = r[o] - a * q[o];
+            r[o] = rv;
+            acc[0] += (double)rv * (double)rv;
+            if constexpr (JAC) {
+                const T zz = dinv[e / NB] * rv;
+                z[o] = zz;
+                acc[1] += (double)rv * (double)zz;
+            }
+        }
+    }
+    block_partials<JAC ? 2 : 1, NB>(acc, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -238,20 +384,29 @@ template <int NB> struct GLin {
 };
 
 // ---------------------------------------------------------------------------
-// epilogues
+// epilogues: load(i, c) fetches the row's own operands before the entry loop
+// (so their latency overlaps the gathers); operator() then writes the row.
+struct NoPre {};
+
 template <typename T, int NB> struct EStore {  // y_i = sum
     T *y;
+    using P = NoPre;
     __device__ void prep(int) {}
-    template <int NV> __device__ void operator()(int i, int c, T s, double (&)[NV]) const {
+    __device__ P load(int, int) const { return {}; }
+    template <int NV> __device__ void operator()(int i, int c, T s, const P &, double (&)[NV]) const {
         y[(size_t)i * NB + c] = s;
     }
 };
 
 template <typename T, int NB> struct EAdd {  // y_i += sum
     T *y;
+    struct P {
+        T y0;
+    };
     __device__ void prep(int) {}
-    template <int NV> __device__ void operator()(int i, int c, T s, double (&)[NV]) const {
-        y[(size_t)i * NB + c] += s;
+    __device__ P load(int i, int c) const { return {y[(size_t)i * NB + c]}; }
+    template <int NV> __device__ void operator()(int i, int c, T s, const P &pr, double (&)[NV]) const {
+        y[(size_t)i * NB + c] = pr.y0 + s;
     }
 };
 
@@ -261,12 +416,15 @@ template <typename T, int NB> struct EPre {
     const T *b;
     T *x;
     T *r;
+    struct P {
+        T b, d;
+    };
     __device__ void prep(int) {}
-    template <int NV> __device__ void operator()(int i, int c, T s, double (&)[NV]) const {
+    __device__ P load(int i, int c) const { return {b[(size_t)i * NB + c], dinv[i]}; }
+    template <int NV> __device__ void operator()(int i, int c, T s, const P &pr, double (&)[NV]) const {
         const size_t o = (size_t)i * NB + c;
-        const T bi = b[o];
-        x[o] = dinv[i] * bi;
-        r[o] = bi - s;
+        x[o] = pr.d * pr.b;
+        r[o] = pr.b - s;
     }
 };
 
@@ -276,13 +434,18 @@ template <typename T, int NB, bool DOT> struct EPost {
     const T *b;
     const T *x;
     T *out;
+    struct P {
+        T b, x, d;
+    };
     __device__ void prep(int) {}
-    template <int NV> __device__ void operator()(int i, int c, T s, double (&acc)[NV]) const {
+    __device__ P load(int i, int c) const {
         const size_t o = (size_t)i * NB + c;
-        const T bi = b[o];
-        const T v = x[o] + dinv[i] * (bi - s);
-        out[o] = v;
-        if constexpr (DOT) acc[0] += (double)bi * (double)v;
+        return {b[o], x[o], dinv[i]};
+    }
+    template <int NV> __device__ void operator()(int i, int c, T s, const P &pr, double (&acc)[NV]) const {
+        const T v = pr.x + pr.d * (pr.b - s);
+        out[(size_t)i * NB + c] = v;
+        if constexpr (DOT) acc[0] += (double)pr.b * (double)v;
     }
 };
 
@@ -294,10 +457,17 @@ template <typename T, int NB> struct ECgQ {
     T *q;
     const CgScal *sc;
     T beta;
+    struct P {
+        T z, po;
+    };
     __device__ void prep(int c) { beta = (T)sc->s[c].beta; }
-    template <int NV> __device__ void operator()(int i, int c, T s, double (&acc)[NV]) const {
+    __device__ P load(int i, int c) const {
         const size_t o = (size_t)i * NB + c;
-        const T pi = z[o] + beta * pold[o];
+        return {z[o], pold[o]};
+    }
+    template <int NV> __device__ void operator()(int i, int c, T s, const P &pr, double (&acc)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        const T pi = pr.z + beta * pr.po;
         p[o] = pi;
         q[o] = s;
         acc[0] += (double)pi * (double)s;
@@ -314,16 +484,21 @@ template <int NB> struct ELin {
     const double *w;
     double s3;
     const double *dotx;  // acc[0] += dotx_i * out_i when not null
+    struct P {
+        double y0, w0, dx;
+        int keep;
+    };
     __device__ void prep(int) {}
-    template <int NV> __device__ void operator()(int i, int c, double s, double (&acc)[NV]) const {
+    __device__ P load(int i, int c) const {
         const size_t o = (size_t)i * NB + c;
-        double v = (mask && mask[i]) ? 0.0 : s1 * s;
-        if (y) v += s2 * y[o];
-        if (w) v += s3 * w[o];
-        out[o] = v;
-        if constexpr (NV > 0) {
-            if (dotx) acc[0] += dotx[o] * v;
-        }
+        return {y ? y[o] : 0.0, w ? w[o] : 0.0, dotx ? dotx[o] : 0.0, !(mask && mask[i])};
+    }
+    template <int NV> __device__ void operator()(int i, int c, double s, const P &pr, double (&acc)[NV]) const {
+        double v = pr.keep ? s1 * s : 0.0;
+        if (y) v += s2 * pr.y0;
+        if (w) v += s3 * pr.w0;
+        out[(size_t)i * NB + c] = v;
+        if (dotx) acc[0] += pr.dx * v;
     }
 };
 
@@ -331,11 +506,14 @@ template <int NB> struct ELin {
 template <int NB> struct EResid {
     const double *f;
     double *r;
+    struct P {
+        double f;
+    };
     __device__ void prep(int) {}
-    template <int NV> __device__ void operator()(int i, int c, double s, double (&acc)[NV]) const {
-        const size_t o = (size_t)i * NB + c;
-        const double v = f[o] - s;
-        r[o] = v;
+    __device__ P load(int i, int c) const { return {f[(size_t)i * NB + c]}; }
+    template <int NV> __device__ void operator()(int i, int c, double s, const P &pr, double (&acc)[NV]) const {
+        const double v = pr.f - s;
+        r[(size_t)i * NB + c] = v;
         acc[0] += v * v;
     }
 };
@@ -364,7 +542,7 @@ template <int NB> struct FinAlpha {  // alpha = rho / p.q on live columns
         }
         int all = 1;
         for (int c = 0; c < NB; ++c) all &= sc->s[c].conv;
-        sc->all_conv = all;
+        publish(sc, NB);
     }
 };
 
@@ -377,7 +555,7 @@ template <int NB, bool JAC> struct FinUpd {  // convergence test on r.r (and Jac
             if (!s.conv) {
                 s.iters += 1;
                 s.rr = tot[0][c];
-                if (s.rr <= s.tol2) s.conv = 1;
+                if (s.rr <= s.tol2 || s.bad) s.conv = 1;
                 if constexpr (JAC) {
                     const double rz = tot[1][c];
                     s.rz = rz;
@@ -387,7 +565,64 @@ template <int NB, bool JAC> struct FinUpd {  // convergence test on r.r (and Jac
             }
             all &= s.conv;
         }
-        sc->all_conv = all;
+        publish(sc, NB);
+    }
+};
+
+// Inner V-cycle CG, once per iteration after the preconditioner: convergence
+// test on r.r (partials of the update kernel), then beta from r.z (partials of
+// the V-cycle's last kernel).
+template <int NB> struct FinUB {
+    CgScal *sc;
+    __device__ void operator()(double (&rr)[1][NB], double (&rz)[1][NB]) const {
+        int all = 1;
+        for (int c = 0; c < NB; ++c) {
+            ColScal &s = sc->s[c];
+            if (!s.conv) {
+                s.iters += 1;
+                s.rr = rr[0][c];
+                if (s.bad || s.rr <= s.tol2) {
+                    s.conv = 1;
+                    s.beta = 0.0;
+                } else {
+                    const double v = rz[0][c];
+                    if (!(v > 0.0)) {
+                        s.bad = 1;
+                        s.conv = 1;
+                    } else {
+                        s.rz = v;
+                        s.beta = v / s.rho;
+                        s.rho = v;
+                    }
+                }
+            }
+            all &= s.conv;
+        }
+        publish(sc, NB);
+    }
+};
+
+// Inner V-cycle CG start: rho = r.z of the first preconditioner application.
+template <int NB> struct FinRho0 {
+    CgScal *sc;
+    __device__ void operator()(double (&tot)[1][NB]) const {
+        int all = 1;
+        for (int c = 0; c < NB; ++c) {
+            ColScal &s = sc->s[c];
+            s.beta = 0.0;
+            if (!s.conv) {
+                const double v = tot[0][c];
+                if (!(v > 0.0)) {
+                    s.bad = 1;
+                    s.conv = 1;
+                } else {
+                    s.rho = v;
+                    s.rz = v;
+                }
+            }
+            all &= s.conv;
+        }
+        publish(sc, NB);
     }
 };
 
@@ -415,7 +650,7 @@ template <int NB> struct FinBeta {  // beta = r.z / rho after the preconditioner
         }
         int all = 1;
         for (int c = 0; c < NB; ++c) all &= sc->s[c].conv;
-        sc->all_conv = all;
+        publish(sc, NB);
     }
 };
 
@@ -424,7 +659,9 @@ template <int NB, bool JAC> struct FinInit {
     CgScal *sc;
     double rtol;
     int nlive;
+    void *x;
     __device__ void operator()(double (&tot)[JAC ? 2 : 1][NB]) const {
+        sc->xptr = x;
         sc->nb = nlive;
         int all = 1;
         for (int c = 0; c < NB; ++c) {
@@ -444,7 +681,7 @@ template <int NB, bool JAC> struct FinInit {
             }
             all &= s.conv;
         }
-        sc->all_conv = all;
+        publish(sc, NB);
         sc->indefinite = 0;
     }
 };
@@ -553,6 +790,7 @@ struct RefScal {
     int nlive;
     int stagnated;
     double rtol;
+    Mail *mail;     // host-mapped: nlive, stagnated
 };
 
 template <int NB> struct OpCopyNorm {  // r = f, x = 0, acc f.f
@@ -584,6 +822,8 @@ template <int NB> struct FinRefInit {
             nl += rs->live[c];
         }
         rs->nlive = nl;
+        rs->mail->nlive = nl;
+        rs->mail->stagnated = rs->stagnated;
     }
 };
 
@@ -605,6 +845,8 @@ template <int NB> struct FinRefine {
             ++nl;
         }
         rs->nlive = nl;
+        rs->mail->nlive = nl;
+        rs->mail->stagnated = rs->stagnated;
     }
 };
 
@@ -658,7 +900,7 @@ template <int NB> struct FinOuterInit {
             s.conv = (c >= nlive) || !(s.bb > 0.0) || s.rr <= s.tol2;
             all &= s.conv;
         }
-        sc->all_conv = all;
+        publish(sc, NB);
     }
 };
 
@@ -677,6 +919,7 @@ template <int NB> struct FinRho {  // rho = r.z at the start of the outer CG
             s.rho = rz;
             s.rz = rz;
         }
+        publish(sc, NB);
     }
 };
 

@@ -455,10 +455,13 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_count(int n, const int *arp, 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_spgemm_fill(int n, const int *arp, const int *aci,
-                                                        const double *av, const int *brp, const int *bci,
-                                                        const double *bv, const int *crp, int *cci,
-                                                        double *cv, int *ovf) {
+// Fill variant for short rows of B: one lane per output column, summing the
+// products over the stored A[i,k] in ascending k (binary search in row k of B).
+__global__ __launch_bounds__(kBlock) void k_spgemm_fill_search(int n, const int *arp, const int *aci,
+                                                               const double *av, const int *brp,
+                                                               const int *bci, const double *bv,
+                                                               const int *crp, int *cci, double *cv,
+                                                               int *ovf) {
     __shared__ int tab[4][kHS];
     __shared__ int lst[4][kMaxRowOut];
     __shared__ int srt[4][kMaxRowOut];
@@ -526,6 +529,96 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_fill(int n, const int *arp, c
     }
 }
 
+__device__ __forceinline__ int hash_find(const int *tab, int key) {
+    unsigned h = ((unsigned)key * 2654435761u) & (kHS - 1);
+    for (int probe = 0; probe < kHS; ++probe) {
+        const int v = tab[h];
+        if (v == key || v == -1) return v == key ? (int)h : -1;
+        h = (h + 1) & (kHS - 1);
+    }
+    return -1;
+}
+
+// Fill: rebuild the row's hash of output columns, give every column its rank
+// in ascending order (the output position), then accumulate the products in
+// LDS walking the stored A[i,k] in ascending k; for one k the lanes share out
+// the row of B, whose columns are distinct, so every output entry receives its
+// products strictly in ascending k: the same rounded sums as a sequential loop.
+constexpr int kFillWaves = 2;
+__global__ __launch_bounds__(64 * kFillWaves) void k_spgemm_fill(int n, const int *arp, const int *aci,
+                                                                const double *av, const int *brp,
+                                                                const int *bci, const double *bv,
+                                                                const int *crp, int *cci, double *cv,
+                                                                int *ovf) {
+    __shared__ int tab[kFillWaves][kHS];
+    __shared__ int pos[kFillWaves][kHS];
+    __shared__ int lst[kFillWaves][kMaxRowOut];
+    __shared__ double acc[kFillWaves][kMaxRowOut];
+    __shared__ int uc[kFillWaves], uc2[kFillWaves];
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    for (int base = blockIdx.x * kFillWaves; base < n; base += gridDim.x * kFillWaves) {
+        const int row = base + w;
+        for (int s = lane; s < kHS; s += 64) tab[w][s] = -1;
+        if (lane == 0) {
+            uc[w] = 0;
+            uc2[w] = 0;
+        }
+        __syncthreads();
+        if (row < n) {
+            for (int p = arp[row] + lane; p < arp[row + 1]; p += 64) {
+                const int k = aci[p];
+                for (int q = brp[k]; q < brp[k + 1]; ++q) hash_insert(tab[w], bci[q], &uc[w], ovf);
+            }
+        }
+        __syncthreads();
+        const int u = row < n ? uc[w] : 0;
+        const bool ok = row < n && u <= kMaxRowOut;
+        if (ok) {
+            for (int s = lane; s < kHS; s += 64) {
+                const int key = tab[w][s];
+                if (key >= 0) lst[w][atomicAdd(&uc2[w], 1)] = key;
+            }
+        }
+        __syncthreads();
+        if (ok) {
+            const int cs = crp[row];
+            for (int s = lane; s < kHS; s += 64) {
+                const int key = tab[w][s];
+                if (key < 0) continue;
+                int rank = 0;
+                for (int f = 0; f < u; ++f) rank += lst[w][f] < key;
+                pos[w][s] = rank;
+                cci[cs + rank] = key;
+                acc[w][rank] = 0.0;
+            }
+        }
+        __syncthreads();
+        if (ok) {
+            const int a0 = arp[row], a1 = arp[row + 1];
+            for (int p = a0; p < a1; ++p) {
+                const int k = aci[p];
+                const double a = av[p];
+                for (int q = brp[k] + lane; q < brp[k + 1]; q += 64) {
+                    const int slot = hash_find(tab[w], bci[q]);
+                    if (slot < 0) {  // cannot happen: every key was inserted above
+                        atomicOr(ovf, 2);
+                        continue;
+                    }
+                    const int r = pos[w][slot];
+                    const double prod = a * bv[q];
+                    acc[w][r] = acc[w][r] + prod;
+                }
+            }
+        }
+        __syncthreads();
+        if (ok) {
+            const int cs = crp[row];
+            for (int e = lane; e < u; e += 64) cv[cs + e] = acc[w][e];
+        }
+        __syncthreads();
+    }
+}
+
 // lower triangle := upper triangle (symbolically symmetric pattern)
 __global__ void k_mirror(int n, const int *rp, const int *ci, double *v, int *bad) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -567,60 +660,185 @@ __global__ void k_densify(int n, const int *rp, const int *ci, const double *v, 
     }
 }
 
-// right-looking Cholesky of the lower triangle, one workgroup
-__global__ __launch_bounds__(1024) void k_chol(int n, double *D, int *bad) {
+// Tiled right-looking Cholesky of the lower triangle (tiles of kTB): per tile
+// column kb, factor the diagonal tile in LDS, solve the panel below it, then
+// update the trailing lower tiles.  Only the lower triangle is read later.
+constexpr int kTB = 32;
+
+__global__ __launch_bounds__(kBlock) void k_potrf_tile(int n, double *D, int k0, int *bad) {
+    __shared__ double T[kTB][kTB + 1];
     __shared__ double piv;
-    for (int k = 0; k < n; ++k) {
-        if (threadIdx.x == 0) {
-            const double a = D[(size_t)k * n + k];
+    const int tb = min(kTB, n - k0);
+    const int t = threadIdx.x;
+    for (int e = t; e < tb * tb; e += kBlock) T[e / tb][e % tb] = D[(size_t)(k0 + e / tb) * n + k0 + e % tb];
+    __syncthreads();
+    for (int k = 0; k < tb; ++k) {
+        if (t == 0) {
+            const double a = T[k][k];
             if (!(a > 0.0)) {
                 atomicOr(bad, 1);
                 piv = 1.0;
             } else {
                 piv = sqrt(a);
             }
-            D[(size_t)k * n + k] = piv;
+            T[k][k] = piv;
         }
         __syncthreads();
-        const double pk = piv;
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) D[(size_t)i * n + k] /= pk;
+        if (t > k && t < tb) T[t][k] /= piv;
         __syncthreads();
-        const long m = n - k - 1;
-        const long tri = m * (m + 1) / 2;
-        for (long e = threadIdx.x; e < tri; e += blockDim.x) {
-            // e -> (i, j) with k < j <= i < n
-            long ii = (long)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
-            while (ii * (ii + 1) / 2 > e) --ii;
-            while ((ii + 1) * (ii + 2) / 2 <= e) ++ii;
-            const long jj = e - ii * (ii + 1) / 2;
-            const int i = k + 1 + (int)ii, j = k + 1 + (int)jj;
-            D[(size_t)i * n + j] -= D[(size_t)i * n + k] * D[(size_t)j * n + k];
+        for (int e = t; e < tb * tb; e += kBlock) {
+            const int i = e / tb, j = e % tb;
+            if (j > k && j <= i) T[i][j] -= T[i][k] * T[j][k];
         }
         __syncthreads();
+    }
+    for (int e = t; e < tb * tb; e += kBlock) {
+        const int i = e / tb, j = e % tb;
+        if (j <= i) D[(size_t)(k0 + i) * n + k0 + j] = T[i][j];
     }
 }
 
-// inverse from the Cholesky factor: one workgroup per column, y in LDS
-__global__ __launch_bounds__(kBlock) void k_chol_inv(int n, const double *Lf, double *inv) {
-    extern __shared__ double y[];
-    const int j = blockIdx.x;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = i == j ? 1.0 : 0.0;
+// panel: rows below the diagonal tile, X = A_ik L_kk^{-T}, one wavefront per row tile
+__global__ __launch_bounds__(64) void k_trsm_tile(int n, double *D, int k0) {
+    __shared__ double Lk[kTB][kTB + 1];
+    const int tb = min(kTB, n - k0);
+    const int t = threadIdx.x;
+    for (int e = t; e < tb * tb; e += 64) Lk[e / tb][e % tb] = D[(size_t)(k0 + e / tb) * n + k0 + e % tb];
     __syncthreads();
-    for (int k = 0; k < n; ++k) {  // L y = e_j
-        if (threadIdx.x == 0) y[k] = y[k] / Lf[(size_t)k * n + k];
-        __syncthreads();
-        const double yk = y[k];
-        for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) y[i] -= Lf[(size_t)i * n + k] * yk;
-        __syncthreads();
+    const int r = k0 + tb + blockIdx.x * kTB + t;
+    if (t >= kTB || r >= n) return;
+    double x[kTB];
+#pragma unroll
+    for (int j = 0; j < kTB; ++j) x[j] = j < tb ? D[(size_t)r * n + k0 + j] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kTB; ++j) {
+        if (j < tb) {
+            double v = x[j];
+            for (int m = 0; m < j; ++m) v -= x[m] * Lk[j][m];
+            x[j] = v / Lk[j][j];
+        }
     }
-    for (int k = n - 1; k >= 0; --k) {  // L^T x = y
-        if (threadIdx.x == 0) y[k] = y[k] / Lf[(size_t)k * n + k];
-        __syncthreads();
-        const double yk = y[k];
-        for (int i = threadIdx.x; i < k; i += blockDim.x) y[i] -= Lf[(size_t)k * n + i] * yk;
-        __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kTB; ++j)
+        if (j < tb) D[(size_t)r * n + k0 + j] = x[j];
+}
+
+// trailing update A_ij -= L_ik L_jk^T for tile pairs i >= j after tile column k0
+__global__ __launch_bounds__(kBlock) void k_syrk_tile(int n, double *D, int k0) {
+    __shared__ double Li[kTB][kTB + 1], Lj[kTB][kTB + 1];
+    const int tb = min(kTB, n - k0);
+    const int s0 = k0 + tb;  // first trailing row
+    const long p = blockIdx.x;
+    long ti = (long)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > p) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= p) ++ti;
+    const long tj = p - ti * (ti + 1) / 2;
+    const int r0 = s0 + (int)ti * kTB, c0 = s0 + (int)tj * kTB;
+    const int t = threadIdx.x;
+    for (int e = t; e < kTB * kTB; e += kBlock) {
+        const int a = e / kTB, m = e % kTB;
+        Li[a][m] = (r0 + a < n && m < tb) ? D[(size_t)(r0 + a) * n + k0 + m] : 0.0;
+        Lj[a][m] = (c0 + a < n && m < tb) ? D[(size_t)(c0 + a) * n + k0 + m] : 0.0;
     }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) inv[(size_t)j * n + i] = y[i];
+    __syncthreads();
+    for (int e = t; e < kTB * kTB; e += kBlock) {
+        const int a = e / kTB, b = e % kTB;
+        const int i = r0 + a, j = c0 + b;
+        if (i >= n || j >= n || j > i) continue;
+        double acc = 0.0;
+        for (int m = 0; m < tb; ++m) acc += Li[a][m] * Lj[b][m];
+        D[(size_t)i * n + j] -= acc;
+    }
+}
+
+// Lt = L^T for the lower triangle (column k of L becomes a contiguous row)
+__global__ void k_lower_transpose(int n, const double *L, double *Lt) {
+    const long tot = (long)n * n;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / n), j = (int)(e % n);
+        if (j <= i) Lt[(size_t)j * n + i] = L[e];
+    }
+}
+
+// Inverse from the Cholesky factor: R columns of the identity per workgroup,
+// forward solve L y = e_j reading rows of L^T, backward solve L^T x = y
+// reading rows of L (both contiguous), vectors in LDS, one barrier per step.
+// Thread t owns the entries i = t (mod blockDim); the row needed at the next
+// step is loaded before the current step's updates so its latency overlaps.
+constexpr int kInvP = 16;  // entries per thread: n <= kInvP * kBlock = 4096
+__global__ __launch_bounds__(kBlock) void k_chol_inv(int n, int R, const double *Lf, const double *Lt,
+                                                     double *inv) {
+    extern __shared__ double sm[];
+    double *y = sm;          // [R][n]
+    double *w = sm + R * n;  // [R][n]: finished entries
+    const int j0 = blockIdx.x * R;
+    const int t = threadIdx.x, B = blockDim.x;
+    for (int e = t; e < R * n; e += B) {
+        const int q = e / n, i = e % n;
+        y[e] = (j0 + q < n && i == j0 + q) ? 1.0 : 0.0;
+    }
+    double cur[kInvP], nxt[kInvP];
+#pragma unroll
+    for (int m = 0; m < kInvP; ++m) {
+        const int i = t + m * B;
+        cur[m] = i < n ? Lt[i] : 0.0;  // row 0 of L^T
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        if (k + 1 < n) {
+            const double *nr = Lt + (size_t)(k + 1) * n;
+#pragma unroll
+            for (int m = 0; m < kInvP; ++m) {
+                const int i = t + m * B;
+                nxt[m] = i < n ? nr[i] : 0.0;
+            }
+        }
+        const double dk = Lf[(size_t)k * n + k];
+        for (int q = 0; q < R; ++q) {
+            const double yk = y[q * n + k] / dk;
+#pragma unroll
+            for (int m = 0; m < kInvP; ++m) {
+                const int i = t + m * B;
+                if (i > k && i < n) y[q * n + i] -= cur[m] * yk;
+            }
+            if (t == 0) w[q * n + k] = yk;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kInvP; ++m) cur[m] = nxt[m];
+    }
+#pragma unroll
+    for (int m = 0; m < kInvP; ++m) {
+        const int i = t + m * B;
+        cur[m] = i < n ? Lf[(size_t)(n - 1) * n + i] : 0.0;
+    }
+    for (int k = n - 1; k >= 0; --k) {
+        if (k > 0) {
+            const double *pr = Lf + (size_t)(k - 1) * n;
+#pragma unroll
+            for (int m = 0; m < kInvP; ++m) {
+                const int i = t + m * B;
+                nxt[m] = i < n ? pr[i] : 0.0;
+            }
+        }
+        const double dk = Lf[(size_t)k * n + k];
+        for (int q = 0; q < R; ++q) {
+            const double xk = w[q * n + k] / dk;
+#pragma unroll
+            for (int m = 0; m < kInvP; ++m) {
+                const int i = t + m * B;
+                if (i < k) w[q * n + i] -= cur[m] * xk;
+            }
+            if (t == 0) y[q * n + k] = xk;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < kInvP; ++m) cur[m] = nxt[m];
+    }
+    for (int e = t; e < R * n; e += B) {
+        const int q = e / n, i = e % n;
+        if (j0 + q < n) inv[(size_t)(j0 + q) * n + i] = y[e];
+    }
 }
 
 // C = op(A) B, n x n row-major, op(A) = A or A^T; 16x16 LDS tiles
@@ -728,8 +946,14 @@ struct Setup {
         C.nnz = scan(cnt, C.rp, A.n);
         C.ci = c.arena.alloc<int>(C.nnz);
         C.v = c.arena.alloc<double>(C.nnz);
-        hipLaunchKernelGGL(k_spgemm_fill, dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci, A.v, B.rp, B.ci, B.v,
-                           C.rp, C.ci, C.v, c.iscratch + 4);
+        if ((double)B.nnz <= 8.0 * (double)B.n) {  // short rows of B: per-column search
+            hipLaunchKernelGGL(k_spgemm_fill_search, dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci, A.v, B.rp, B.ci,
+                               B.v, C.rp, C.ci, C.v, c.iscratch + 4);
+        } else {
+            const int gf = std::min(8192, std::max(1, ceil_div(A.n, kFillWaves)));
+            hipLaunchKernelGGL(k_spgemm_fill, dim3(gf), dim3(64 * kFillWaves), 0, s, A.n, A.rp, A.ci, A.v, B.rp,
+                               B.ci, B.v, C.rp, C.ci, C.v, c.iscratch + 4);
+        }
         check_kernels();
         c.arena.release(cnt);
         return C;
@@ -907,13 +1131,26 @@ struct Setup {
 
     double *factor_invert(double *D, int n) {
         zero(c.iscratch + 9, sizeof(int));
-        hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), 0, s, n, D, c.iscratch + 9);
+        for (int k0 = 0; k0 < n; k0 += kTB) {
+            hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(kBlock), 0, s, n, D, k0, c.iscratch + 9);
+            const int rest = n - (k0 + kTB);
+            if (rest <= 0) break;
+            const int tiles = ceil_div(rest, kTB);
+            hipLaunchKernelGGL(k_trsm_tile, dim3(tiles), dim3(64), 0, s, n, D, k0);
+            hipLaunchKernelGGL(k_syrk_tile, dim3(tiles * (tiles + 1) / 2), dim3(kBlock), 0, s, n, D, k0);
+        }
         check_kernels();
         if (read_int(c.iscratch + 9)) fail(AMG_ERR_NOT_SPD, "dense Cholesky met a non-positive pivot");
         double *inv = c.arena.alloc<double>((size_t)n * n);
-        hipLaunchKernelGGL(k_chol_inv, dim3(n), dim3(kBlock), sizeof(double) * n, s, n, D, inv);
+        double *Lt = c.arena.alloc<double>((size_t)n * n);
+        hipLaunchKernelGGL(k_lower_transpose, dim3(gsz((long)n * n)), dim3(kBlock), 0, s, n, D, Lt);
+        // LDS: 2 R n doubles within 64 KiB (n <= 4096)
+        const int R = std::max(1, std::min(8, 4096 / n));
+        hipLaunchKernelGGL(k_chol_inv, dim3(ceil_div(n, R)), dim3(kBlock), sizeof(double) * 2 * R * n, s, n, R, D,
+                           Lt, inv);
         check_kernels();
         c.arena.release(D);
+        c.arena.release(Lt);
         return inv;
     }
 };
@@ -992,6 +1229,13 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
         fail(AMG_ERR_DENSE_TOO_LARGE, "coarsest level has " + std::to_string(Lc.n) + " rows");
     c.nAinv = Lc.n;
     c.Ainv = su.dense_inverse(Lc.A, nullptr, false);
+    // small coarse levels above the coarsest: exact dense A_j and M_j solves
+    for (int j = 1; j + 1 < c.L; ++j) {
+        Level &Lv = c.lev[j];
+        if (Lv.n > c.o.dense_solve_max) continue;
+        Lv.Ainv = su.dense_inverse(Lv.A, nullptr, false);
+        Lv.Minv = su.dense_inverse(Lv.M, nullptr, false);
+    }
     AMG_HIP(hipStreamSynchronize(s));
 }
 
@@ -1006,11 +1250,12 @@ void form_dense_hessian(Ctx &c, int ell) {
     const int lv = ell - 1;
     Level &L = c.lev[lv];
     const int n = L.n;
-    if (n > c.o.dense_max)
-        fail(AMG_ERR_DENSE_TOO_LARGE, "Hessian level " + std::to_string(lv) + " has " + std::to_string(n) + " rows");
     if (c.Hdense) c.arena.release(c.Hdense);
     if (c.Hinv) c.arena.release(c.Hinv);
     c.Hdense = c.Hinv = nullptr;
+    c.nH = 0;
+    c.ell = ell;
+    if (n > c.o.dense_max) return;  // solved by loose CG on H (Section 5.2)
     const size_t nn = (size_t)n * n;
     double *Ainv = (lv == c.L - 1) ? c.Ainv : su.dense_inverse(L.A, nullptr, false);
     const uint8_t *mk = lv == 0 ? L.mask : nullptr;

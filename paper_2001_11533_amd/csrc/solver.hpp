@@ -21,26 +21,61 @@ template <int NB> struct Solver {
     explicit Solver(Ctx &cc) : c(cc), s(cc.stream) {}
 
     // ---------------- launch helpers ----------------
-    template <int NV, class FIN> void finish(int nblk, FIN fin, const int *stop) {
-        if constexpr (NV > 0)
-            hipLaunchKernelGGL((fin_kernel<NV, NB, FIN>), dim3(1), dim3(kBlock), 0, s, c.partial, nblk, fin, stop);
+    // Reductions write their partials into one of three buffers (pbuf) so that
+    // a finalize kernel can combine the partials of two earlier kernels.
+    template <int NV, class FIN> void finish(int pbuf, FIN fin, const int *stop) {
+        if constexpr (NV > 0 && !std::is_same_v<FIN, NoFin>)
+            hipLaunchKernelGGL((fin_kernel<NV, NB, FIN>), dim3(1), dim3(kFinBlock), 0, s, c.part[pbuf],
+                               c.pgrid[pbuf], fin, stop);
     }
 
     template <typename T, int NV, class GX, class EP, class FIN>
-    void spmv(const DCsr &A, const T *vals, GX gx, EP ep, FIN fin, const int *stop) {
+    void spmv(const DCsr &A, const T *vals, GX gx, EP ep, FIN fin, const int *stop, int pbuf = 0) {
         const Geo geo = make_geo(A.nnz, A.n, NB);
         const int g = grid_rows(A.n, geo.rpb(), NV > 0 ? kMaxGrid : kMaxGridPlain);
-        Reducer<(NV > 0 ? NV : 1), NB> red{c.partial};
-        hipLaunchKernelGGL((spmv_kernel<T, NB, NV, GX, EP>), dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci, vals,
-                           gx, ep, geo, red, stop);
-        finish<NV>(g, fin, stop);
+        Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
+        if (NV > 0) c.pgrid[pbuf] = g;
+        if (A.n == c.N)
+            hipLaunchKernelGGL((spmv_kernel<T, NB, NV, GX, EP, 1>), dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci,
+                               vals, gx, ep, geo, red, stop);
+        else
+            hipLaunchKernelGGL((spmv_kernel<T, NB, NV, GX, EP, 0>), dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci,
+                               vals, gx, ep, geo, red, stop);
+        finish<NV>(pbuf, fin, stop);
     }
 
-    template <int NV, class OP, class FIN> void elem(int n, OP op, FIN fin, const int *stop) {
+    template <int NV, class OP, class FIN> void elem(int n, OP op, FIN fin, const int *stop, int pbuf = 0) {
         const int g = grid_rows((long)n * NB, kBlock, NV > 0 ? kMaxGrid : kMaxGridPlain);
-        Reducer<(NV > 0 ? NV : 1), NB> red{c.partial};
-        hipLaunchKernelGGL((elem_kernel<NB, NV, OP>), dim3(g), dim3(kBlock), 0, s, n, op, red, stop);
-        finish<NV>(g, fin, stop);
+        Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
+        if (NV > 0) c.pgrid[pbuf] = g;
+        if (n == c.N)
+            hipLaunchKernelGGL((elem_kernel<NB, NV, OP, 1>), dim3(g), dim3(kBlock), 0, s, n, op, red, stop);
+        else
+            hipLaunchKernelGGL((elem_kernel<NB, NV, OP, 0>), dim3(g), dim3(kBlock), 0, s, n, op, red, stop);
+        finish<NV>(pbuf, fin, stop);
+    }
+
+    // x += alpha p, r -= alpha q with alpha from the p.q partials in buffer 0;
+    // r.r (and r.z) partials into buffer 1
+    template <typename T, bool JAC>
+    void cg_update(int n, T *x, T *r, T *z, const T *p, const T *q, const T *dinv, CgScal *sc, int outer,
+                   const int *stop) {
+        const int g = grid_rows((long)n * NB, kBlock, kMaxGrid);
+        Reducer<JAC ? 2 : 1, NB> red{c.part[1]};
+        // alpha: every workgroup sums the p.q partials itself when they are few,
+        // else one finalize kernel forms it first
+        int nblk_pq = c.pgrid[0];
+        if ((long)nblk_pq * NB > 2048) {
+            finish<1>(0, FinAlpha<NB>{sc, outer}, stop);
+            nblk_pq = 0;
+        }
+        c.pgrid[1] = g;
+        if (n == c.N)
+            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 1>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, p, q, dinv,
+                               sc, c.part[0], nblk_pq, outer, red, stop);
+        else
+            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 0>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, p, q, dinv,
+                               sc, c.part[0], nblk_pq, outer, red, stop);
     }
 
     template <typename T> void dense_apply(int n, const double *inv, const T *b, T *x, const int *stop) {
@@ -54,9 +89,9 @@ template <int NB> struct Solver {
         AMG_HIP(hipStreamSynchronize(s));
     }
 
-    void read_rs() {
-        AMG_HIP(hipMemcpyAsync(c.rsh, c.rsd, sizeof(RefScal), hipMemcpyDeviceToHost, s));
-        AMG_HIP(hipStreamSynchronize(s));
+    void wait_mail() {
+        AMG_HIP(hipEventRecord(c.poll_ev[0], s));
+        AMG_HIP(hipEventSynchronize(c.poll_ev[0]));
     }
 
     template <typename T> CgWs<T> &inws(int l) {
@@ -67,9 +102,9 @@ template <int NB> struct Solver {
     // ---------------- V-cycle (AMG preconditioner for A_j) ----------------
     // z = V_j b: one l1-Jacobi sweep from zero, residual, restriction with
     // S^T, recursion, prolongation with S, one l1-Jacobi sweep; the coarsest
-    // level is solved with the dense inverse.  With sc the last kernel also
-    // forms r.z for the CG (b is the CG residual) and the CG's beta.
-    template <typename T> void vcycle(int j, const T *b, T *z, CgScal *sc, const int *stop) {
+    // level is solved with the dense inverse.  With dot the last kernel also
+    // writes the partials of r.z for the CG (b is the CG residual) to buffer 2.
+    template <typename T> void vcycle(int j, const T *b, T *z, bool dot, const int *stop) {
         const int Lc = c.L - 1;
         const T *bl = b;
         for (int l = j; l < Lc; ++l) {
@@ -90,9 +125,9 @@ template <int NB> struct Solver {
             spmv<T, 0>(Lv.S, avals<T>(Lv.S), GPlain<T, NB>{e}, EAdd<T, NB>{v.x}, NoFin{}, stop);
             const T *bb = (l == j) ? b : v.b;
             T *out = (l == j) ? z : v.x2;
-            if (l == j && sc)
+            if (l == j && dot)
                 spmv<T, 1>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x},
-                           EPost<T, NB, true>{dl1inv<T>(Lv), bb, v.x, out}, FinBeta<NB>{sc, 0}, stop);
+                           EPost<T, NB, true>{dl1inv<T>(Lv), bb, v.x, out}, NoFin{}, stop, 2);
             else
                 spmv<T, 0>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x},
                            EPost<T, NB, false>{dl1inv<T>(Lv), bb, v.x, out}, NoFin{}, stop);
@@ -128,14 +163,13 @@ template <int NB> struct Solver {
 
     void launch(hipGraphExec_t g) { AMG_HIP(hipGraphLaunch(g, s)); }
 
-    void post_flag(const CgScal *sc, int slot) {
-        AMG_HIP(hipMemcpyAsync(&c.hflag[slot], &sc->all_conv, sizeof(int), hipMemcpyDeviceToHost, s));
-        AMG_HIP(hipEventRecord(c.poll_ev[slot], s));
-    }
+    // The finalize kernels write each CG's mailbox in pinned host memory; an
+    // event marks how far the stream has run, so no copy is enqueued.
+    void post_flag(int slot) { AMG_HIP(hipEventRecord(c.poll_ev[slot], s)); }
 
-    bool wait_flag(int slot) {
+    template <typename T> bool wait_flag(int slot, const CgWs<T> &w) {
         AMG_HIP(hipEventSynchronize(c.poll_ev[slot]));
-        return c.hflag[slot] != 0;
+        return __atomic_load_n(&w.hmail->all_conv, __ATOMIC_ACQUIRE) != 0;
     }
 
     // ---------------- conjugate gradients ----------------
@@ -152,10 +186,15 @@ template <int NB> struct Solver {
     void cg_iter(int j, const DCsr &A, const T *vals, const T *dinv, CgWs<T> &w, T *pold, T *pnew) {
         const int n = A.n;
         const int *stop = &w.sc->all_conv;
-        spmv<T, 1>(A, vals, GZBP<T, NB>{w.z, pold, w.sc}, ECgQ<T, NB>{w.z, pold, pnew, w.q, w.sc},
-                   FinAlpha<NB>{w.sc, 0}, stop);
-        elem<JAC ? 2 : 1>(n, OpUpd<T, NB, JAC>{w.x, w.r, w.z, pnew, w.q, dinv, w.sc}, FinUpd<NB, JAC>{w.sc}, stop);
-        if constexpr (!JAC) vcycle<T>(j, w.r, w.z, w.sc, stop);
+        spmv<T, 1>(A, vals, GZBP<T, NB>{w.z, pold, w.sc}, ECgQ<T, NB>{w.z, pold, pnew, w.q, w.sc}, NoFin{}, stop, 0);
+        cg_update<T, JAC>(n, nullptr, w.r, w.z, pnew, w.q, dinv, w.sc, 0, stop);
+        if constexpr (JAC) {
+            finish<2>(1, FinUpd<NB, true>{w.sc}, stop);
+        } else {
+            vcycle<T>(j, w.r, w.z, true, stop);
+            hipLaunchKernelGGL((fin2_kernel<NB, FinUB<NB>>), dim3(1), dim3(kFinBlock), 0, s, c.part[1], c.pgrid[1],
+                               c.part[2], c.pgrid[2], FinUB<NB>{w.sc}, stop);
+        }
     }
 
     template <typename T, bool JAC>
@@ -165,17 +204,21 @@ template <int NB> struct Solver {
         const int *stop = &w.sc->all_conv;
         const T *dinv = nullptr;
         if constexpr (JAC) dinv = mdinv;
-        elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, w.x, w.p0, w.z, dinv}, FinInit<NB, JAC>{w.sc, rtol, nlive},
-                          nullptr);
+        elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, w.p0, w.z, dinv},
+                          FinInit<NB, JAC>{w.sc, rtol, nlive, (void *)x}, nullptr);
         const bool graphs = c.o.use_graphs != 0;
+        auto first_precond = [&] {
+            vcycle<T>(j, w.r, w.z, true, stop);
+            finish<1>(2, FinRho0<NB>{w.sc}, stop);
+        };
         if (graphs && !w.ga) {
-            if constexpr (!JAC) w.g0 = capture([&] { vcycle<T>(j, w.r, w.z, w.sc, stop); });
+            if constexpr (!JAC) w.g0 = capture(first_precond);
             w.ga = capture([&] { cg_iter<T, JAC>(j, A, vals, dinv, w, w.p0, w.p1); });
             w.gb = capture([&] { cg_iter<T, JAC>(j, A, vals, dinv, w, w.p1, w.p0); });
         }
         if constexpr (!JAC) {
             if (graphs) launch(w.g0);
-            else vcycle<T>(j, w.r, w.z, w.sc, stop);
+            else first_precond();
         }
         int it = 0;
         auto step = [&]() {
@@ -186,41 +229,37 @@ template <int NB> struct Solver {
         };
         const int first = std::min(std::max(1, w.pred - 1), maxit);
         while (it < first) step();
-        post_flag(w.sc, 0);
+        post_flag(0);
         int cur = 0;
         bool done = false;
         while (!done) {
             if (it >= maxit) {
-                done = wait_flag(cur);
+                done = wait_flag(cur, w);
                 break;
             }
             step();
-            post_flag(w.sc, cur ^ 1);
-            done = wait_flag(cur);
+            post_flag(cur ^ 1);
+            done = wait_flag(cur, w);
             cur ^= 1;
         }
-        read_sc(w.sc);
-        if (!c.hsc->all_conv) {
+        // the last posted event covers every launch: the mailbox is final
+        AMG_HIP(hipEventSynchronize(c.poll_ev[cur]));
+        const Mail &m = *w.hmail;
+        if (!m.all_conv) {
             w.pred = it;
             fail(AMG_ERR_NOCONV, std::string(JAC ? "mass" : "inner") + " CG did not converge at level " +
                                      std::to_string(j));
         }
-        int mx = 0;
-        for (int col = 0; col < NB; ++col) {
-            if (c.hsc->s[col].bad)
-                fail(AMG_ERR_NOCONV,
-                     std::string(JAC ? "mass" : "inner") + " CG breakdown at level " + std::to_string(j));
-            mx = std::max(mx, c.hsc->s[col].iters);
-        }
-        w.pred = mx;
-        AMG_HIP(hipMemcpyAsync(x, w.x, sizeof(T) * (size_t)n * NB, hipMemcpyDeviceToDevice, s));
-        return mx;
+        if (m.bad)
+            fail(AMG_ERR_NOCONV, std::string(JAC ? "mass" : "inner") + " CG breakdown at level " + std::to_string(j));
+        w.pred = m.iters;
+        return m.iters;
     }
 
     // ---------------- solves with A_j ----------------
     void solve_A(int j, const double *f, double *x, double rtol) {
-        if (j == c.L - 1) {
-            dense_apply<double>(c.nAinv, c.Ainv, f, x, nullptr);
+        if (j == c.L - 1 || c.lev[j].Ainv) {
+            dense_apply<double>(c.lev[j].n, j == c.L - 1 ? c.Ainv : c.lev[j].Ainv, f, x, nullptr);
             AMG_HIP(hipGetLastError());
             return;
         }
@@ -243,9 +282,9 @@ template <int NB> struct Solver {
         LevelWs &w = c.ws[j];
         const int n = L.n;
         elem<1>(n, OpCopyNorm<NB>{f, w.rr, x}, FinRefInit<NB>{c.rsd, rtol, NB}, nullptr);
-        read_rs();
+        wait_mail();
         int steps = 0;
-        while (c.rsh->nlive > 0) {
+        while (c.rmail->nlive > 0) {
             if (steps >= c.o.refine_maxit) fail(AMG_ERR_NOCONV, "refinement did not converge");
             elem<0>(n, OpCastScale<NB>{w.b32, w.rr, c.rsd}, NoFin{}, nullptr);
             const int it = cg<float, false>(j, L.A, L.A.v32, nullptr, w.in32, w.b32, w.d32, c.o.inner32_rtol,
@@ -254,16 +293,21 @@ template <int NB> struct Solver {
             c.st.inner_max = std::max<long>(c.st.inner_max, it);
             elem<0>(n, OpRefAdd<NB>{x, w.d32, c.rsd}, NoFin{}, nullptr);
             spmv<double, 1>(L.A, L.A.v, GPlain<double, NB>{x}, EResid<NB>{f, w.rr}, FinRefine<NB>{c.rsd}, nullptr);
-            read_rs();
+            wait_mail();
             ++steps;
             c.st.refine++;
-            if (c.rsh->stagnated) fail(AMG_ERR_NOCONV, "refinement stagnated at level " + std::to_string(j));
+            if (c.rmail->stagnated) fail(AMG_ERR_NOCONV, "refinement stagnated at level " + std::to_string(j));
         }
         c.st.inner_solves++;
     }
 
     void mass_solve(int j, const double *b, double *x) {
         Level &L = c.lev[j];
+        if (L.Minv) {
+            dense_apply<double>(L.n, L.Minv, b, x, nullptr);
+            AMG_HIP(hipGetLastError());
+            return;
+        }
         const int it =
             cg<double, true>(j, L.M, L.M.v, L.mdinv, c.ws[j].mass, b, x, c.o.mass_rtol, c.o.mass_maxit, NB);
         c.st.mass_iters += it;
@@ -336,8 +380,12 @@ template <int NB> struct Solver {
     // calls of Algorithm MLAS (0 < l < ell-1); B_0 = C_0
     void Bop(int l, const double *r, double *z) {
         if (l == c.ell - 1) {
-            dense_apply<double>(c.nH, c.Hinv, r, z, nullptr);
-            AMG_HIP(hipGetLastError());
+            if (c.Hinv) {
+                dense_apply<double>(c.nH, c.Hinv, r, z, nullptr);
+                AMG_HIP(hipGetLastError());
+            } else {
+                hess_cg(l, r, z);
+            }
             return;
         }
         if (l == 0) {
@@ -348,6 +396,33 @@ template <int NB> struct Solver {
         Cop(l, r, w.ml_z1, nullptr);
         hessian_apply(l, w.ml_z1, w.ml_t, c.o.precond_inner_rtol, r);  // t = r - H_l z1
         Cop(l, w.ml_t, z, w.ml_z1);                                     // z = z1 + C_l t
+    }
+
+    // Coarsest Hessian level too large to invert densely: unpreconditioned CG
+    // on H_l to coarse_hess_rtol from x = 0 (Section 5.2).
+    void hess_cg(int l, const double *b, double *x) {
+        const int n = c.lev[l].n;
+        CgWs<double> &w = c.ws[l].hcg;
+        elem<0>(n, OpAxpby<NB>{w.r, b, nullptr, 1.0, 0.0}, NoFin{}, nullptr);
+        elem<0>(n, OpAxpby<NB>{x, b, nullptr, 0.0, 0.0}, NoFin{}, nullptr);
+        elem<0>(n, OpAxpby<NB>{w.p0, b, nullptr, 1.0, 0.0}, NoFin{}, nullptr);
+        elem<2>(n, OpDot<NB>{b, b, w.r, w.r}, FinOuterInit<NB>{w.sc, c.o.coarse_hess_rtol, NB}, nullptr);
+        elem<1>(n, OpDot<NB>{w.r, w.r, nullptr, nullptr}, FinRho<NB>{w.sc}, nullptr);
+        read_sc(w.sc);
+        for (int it = 0; !c.hsc->all_conv; ++it) {
+            if (it >= c.o.outer_maxit) fail(AMG_ERR_NOCONV, "coarsest-level Hessian CG did not converge");
+            hessian_apply(l, w.p0, w.q, c.o.precond_inner_rtol, nullptr);
+            elem<1>(n, OpDot<NB>{w.p0, w.q, nullptr, nullptr}, NoFin{}, nullptr, 0);
+            cg_update<double, false>(n, x, w.r, nullptr, w.p0, w.q, nullptr, w.sc, 0, nullptr);
+            finish<1>(1, FinUpd<NB, false>{w.sc}, nullptr);
+            read_sc(w.sc);
+            for (int col = 0; col < NB; ++col)
+                if (c.hsc->s[col].bad) fail(AMG_ERR_NOCONV, "coarsest-level Hessian CG breakdown");
+            if (c.hsc->all_conv) break;
+            elem<1>(n, OpDot<NB>{w.r, w.r, nullptr, nullptr}, FinBeta<NB>{w.sc, 0}, nullptr);
+            elem<0>(n, OpPUpd<NB>{w.p0, w.r, w.sc}, NoFin{}, nullptr);
+        }
+        c.st.coarse_cg += 1;
     }
 
     void precond(const double *r, double *z) {
@@ -380,9 +455,9 @@ template <int NB> struct Solver {
                     return AMG_ERR_NOCONV;
                 }
                 hessian_apply(0, w.p0, w.q, c.o.inner_rtol, nullptr);
-                elem<1>(n, OpDot<NB>{w.p0, w.q, nullptr, nullptr}, FinAlpha<NB>{w.sc, 1}, nullptr);
-                elem<1>(n, OpUpd<double, NB, false>{x, w.r, nullptr, w.p0, w.q, nullptr, w.sc},
-                        FinUpd<NB, false>{w.sc}, nullptr);
+                elem<1>(n, OpDot<NB>{w.p0, w.q, nullptr, nullptr}, NoFin{}, nullptr, 0);
+                cg_update<double, false>(n, x, w.r, nullptr, w.p0, w.q, nullptr, w.sc, 1, nullptr);
+                finish<1>(1, FinUpd<NB, false>{w.sc}, nullptr);
                 ++it;
                 read_sc(w.sc);
                 if (c.hsc->indefinite) {

@@ -24,7 +24,7 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-ORACLE_KEYS = ("hess_levels", "max_coarse", "inner_rtol", "mass_rtol", "precond_inner_rtol", "precond",
+ORACLE_KEYS = ("hess_levels", "max_coarse", "inner_rtol", "mass_rtol", "precond_inner_rtol", "precond", "dense_max", "dense_solve_max",
                "inner32_rtol")
 
 
@@ -246,3 +246,15 @@ def test_graph_replay_matches_eager_launches():
     ua, _ = gg.reduced_solve(cuda(pg.yd[:, 0]))
     ub, _ = ge.reduced_solve(cuda(pg.yd[:, 0]))
     assert torch.equal(ua, ub)
+
+
+def test_coarsest_hessian_by_loose_cg():
+    # coarsest Hessian level above dense_max: unpreconditioned CG to 1e-4 on it
+    # (the practice of Section 5.2), on both sides
+    p, g, o = make("c2", 16, max_coarse=30, dense_max=30, hess_levels=2, beta=1e-3)
+    assert g.levels()[1] == 2 and o.h.chol_H is None
+    assert g.dense(1).size == 0
+    yd = p.yd[:, 0]
+    u, info = g.reduced_solve(cuda(yd), rtol=1e-10)
+    uo, it = o.reduced_solve(yd, rtol=1e-12)
+    assert rel(u, uo) < 1e-8

@@ -220,3 +220,31 @@ def test_indefinite_fallback_drops_levels():
     H = dense.hessian_practical(h)
     ref = np.linalg.solve(H, dense.rhs_practical(h, yd))
     assert np.linalg.norm(u - ref) <= 1e-6 * np.linalg.norm(ref)
+
+
+def test_coarsest_hessian_by_loose_cg():
+    # Section 5.2 solves the coarsest Hessian level by unpreconditioned CG to
+    # 1e-4 instead of exactly; forcing that path (dense_max below the coarsest
+    # Hessian level) must leave the solution of H_0 u = b unchanged
+    p, h = build("c2", 16, max_coarse=30, dense_max=30, hess_levels=2, beta=1e-3)
+    assert h.levels[h.ell - 1].n > 30 and h.chol_H is None
+    o = solve.Oracle(h)
+    yd = p.yd[:, 0]
+    u, it = o.reduced_solve(yd, rtol=1e-10)
+    assert o.cnt.coarse_cg_iters > 0
+    H = dense.hessian_practical(h)
+    ref = np.linalg.solve(H, dense.rhs_practical(h, yd))
+    assert np.linalg.norm(u - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_exact_small_coarse_solves_do_not_change_the_solution():
+    # exact dense A_j / M_j solves on small coarse levels return what the
+    # iterative inner solves approximate: same outer solution to tolerance
+    p, h1 = build("c2", 32, max_coarse=20)
+    assert any(lev.chol_A is not None for lev in h1.levels[1:-1])
+    p, h0 = build("c2", 32, max_coarse=20, dense_solve_max=0)
+    assert all(lev.chol_A is None for lev in h0.levels)
+    yd = p.yd[:, 0]
+    u1, _ = solve.Oracle(h1).reduced_solve(yd, rtol=1e-11)
+    u0, _ = solve.Oracle(h0).reduced_solve(yd, rtol=1e-11)
+    assert np.linalg.norm(u1 - u0) <= 1e-9 * np.linalg.norm(u0)
