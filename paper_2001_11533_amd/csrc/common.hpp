@@ -29,33 +29,46 @@ struct Error {
     } while (0)
 
 // Every device allocation of a context goes through one arena so that a
-// failure anywhere in setup releases everything.
+// failure anywhere in setup releases everything.  A released block is kept
+// and handed out again to a later request of at most its size (and at least
+// half of it): all work of a context runs in order on its one stream, so the
+// kernels that used the block are ahead of any that reuse it, and no hipFree
+// (which waits for the whole device) happens before the context ends.
 struct Arena {
-    std::vector<void *> ptrs;
+    struct Blk {
+        void *p;
+        size_t bytes;
+        bool live;
+    };
+    std::vector<Blk> blks;
     size_t bytes = 0;
     template <class T> T *alloc(size_t n) {
         if (n == 0) n = 1;
+        const size_t want = (n * sizeof(T) + 255) & ~(size_t)255;
+        Blk *best = nullptr;
+        for (auto &b : blks)
+            if (!b.live && b.bytes >= want && b.bytes <= 2 * want && (!best || b.bytes < best->bytes)) best = &b;
+        if (best) {
+            best->live = true;
+            return static_cast<T *>(best->p);
+        }
         void *p = nullptr;
-        hipError_t e = hipMalloc(&p, n * sizeof(T));
+        hipError_t e = hipMalloc(&p, want);
         if (e != hipSuccess) {
             (void)hipGetLastError();
-            fail(AMG_ERR_OOM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed");
+            fail(AMG_ERR_OOM, "hipMalloc of " + std::to_string(want) + " bytes failed");
         }
-        ptrs.push_back(p);
-        bytes += n * sizeof(T);
+        blks.push_back({p, want, true});
+        bytes += want;
         return static_cast<T *>(p);
     }
     void release(void *p) {
-        for (auto &q : ptrs)
-            if (q == p) {
-                (void)hipFree(q);
-                q = nullptr;
-            }
+        for (auto &b : blks)
+            if (b.p == p) b.live = false;
     }
     void free_all() {
-        for (void *p : ptrs)
-            if (p) (void)hipFree(p);
-        ptrs.clear();
+        for (auto &b : blks) (void)hipFree(b.p);
+        blks.clear();
         bytes = 0;
     }
 };
@@ -76,7 +89,7 @@ constexpr int kMaxGridPlain = 1 << 20; // and for kernels without
 constexpr int kFinBlock = 1024;        // threads of a finalize kernel
 constexpr int kXcd = 8;          // XCDs of an MI355X
 
-inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+__host__ __device__ inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
 
 // Grid for a row-blocked kernel: a multiple of 8 so that the XCD-aware remap
 // (see xcd_block) is a permutation.

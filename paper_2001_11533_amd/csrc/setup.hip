@@ -23,6 +23,7 @@
 //              copied from the upper one
 #include <algorithm>
 #include <cmath>
+#include <initializer_list>
 
 #include "ctx.hpp"
 
@@ -395,234 +396,269 @@ __global__ void k_t_place(int n, const int *rp, const int *ci, const double *v, 
 
 // rows of the transpose: rank sort by column index, one wavefront per row
 // (the keys of a row are distinct row indices of the source matrix)
+constexpr int kSortLds = 1024;  // keys of a row staged in LDS (longer rows read them from memory)
 __global__ __launch_bounds__(kBlock) void k_row_sort(int m, const int *rp, const int *ci_in, const double *v_in,
                                                      int *ci_out, double *v_out) {
-    const int lane = threadIdx.x % 64;
+    __shared__ int keys[kBlock / 64][kSortLds];
+    const int lane = threadIdx.x % 64, wl = threadIdx.x / 64;
     const int w = (blockIdx.x * kBlock + threadIdx.x) / 64;
     const int nw = gridDim.x * kBlock / 64;
     for (int r = w; r < m; r += nw) {
-        const int s = rp[r], e = rp[r + 1];
-        for (int a = s + lane; a < e; a += 64) {
-            const int key = ci_in[a];
-            int rank = 0;
-            for (int b = s; b < e; ++b) rank += ci_in[b] < key;
-            ci_out[s + rank] = key;
-            v_out[s + rank] = v_in[a];
+        const int s = rp[r], e = rp[r + 1], len = e - s;
+        if (len <= kSortLds) {
+            for (int a = lane; a < len; a += 64) keys[wl][a] = ci_in[s + a];
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            for (int a = lane; a < len; a += 64) {
+                const int key = keys[wl][a];
+                int rank = 0;
+                for (int b = 0; b < len; ++b) rank += keys[wl][b] < key;
+                ci_out[s + rank] = key;
+                v_out[s + rank] = v_in[s + a];
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        } else {
+            for (int a = s + lane; a < e; a += 64) {
+                const int key = ci_in[a];
+                int rank = 0;
+                for (int b = s; b < e; ++b) rank += ci_in[b] < key;
+                ci_out[s + rank] = key;
+                v_out[s + rank] = v_in[a];
+            }
         }
     }
 }
 
 // ---- sparse product C = A B, one wavefront per row of A, LDS hash of the
 // output columns; values summed over the stored A[i,k] in ascending k ----
-__device__ __forceinline__ int hash_insert(int *tab, int key, int *ucount, int *ovf) {
-    unsigned h = ((unsigned)key * 2654435761u) & (kHS - 1);
-    for (int probe = 0; probe < kHS; ++probe) {
+
+template <int HS> __device__ __forceinline__ void hs_insert(int *tab, int key, int *ucount, int *ovf) {
+    unsigned h = ((unsigned)key * 2654435761u) & (HS - 1);
+    for (int probe = 0; probe < HS; ++probe) {
         const int old = atomicCAS(&tab[h], -1, key);
         if (old == -1) {
             atomicAdd(ucount, 1);
-            return 1;
+            return;
         }
-        if (old == key) return 0;
-        h = (h + 1) & (kHS - 1);
+        if (old == key) return;
+        h = (h + 1) & (HS - 1);
     }
     atomicOr(ovf, 1);
-    return 0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_spgemm_count(int n, const int *arp, const int *aci,
-                                                         const int *brp, const int *bci, int *cnt,
-                                                         int *ovf) {
-    __shared__ int tab[4][kHS];
-    __shared__ int uc[4];
-    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int base = blockIdx.x * 4; base < n; base += gridDim.x * 4) {
-        const int row = base + w;
-        for (int s = lane; s < kHS; s += 64) tab[w][s] = -1;
-        if (lane == 0) uc[w] = 0;
-        __syncthreads();
-        if (row < n) {
-            for (int p = arp[row] + lane; p < arp[row + 1]; p += 64) {
-                const int k = aci[p];
-                for (int q = brp[k]; q < brp[k + 1]; ++q) hash_insert(tab[w], bci[q], &uc[w], ovf);
-            }
-        }
-        __syncthreads();
-        if (row < n && lane == 0) {
-            cnt[row] = uc[w];
-            if (uc[w] > kMaxRowOut) atomicOr(ovf, 1);
-        }
-        __syncthreads();
-    }
-}
-
-// Fill variant for short rows of B: one lane per output column, summing the
-// products over the stored A[i,k] in ascending k (binary search in row k of B).
-__global__ __launch_bounds__(kBlock) void k_spgemm_fill_search(int n, const int *arp, const int *aci,
-                                                               const double *av, const int *brp,
-                                                               const int *bci, const double *bv,
-                                                               const int *crp, int *cci, double *cv,
-                                                               int *ovf) {
-    __shared__ int tab[4][kHS];
-    __shared__ int lst[4][kMaxRowOut];
-    __shared__ int srt[4][kMaxRowOut];
-    __shared__ int uc[4], uc2[4];
-    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int base = blockIdx.x * 4; base < n; base += gridDim.x * 4) {
-        const int row = base + w;
-        for (int s = lane; s < kHS; s += 64) tab[w][s] = -1;
-        if (lane == 0) {
-            uc[w] = 0;
-            uc2[w] = 0;
-        }
-        __syncthreads();
-        if (row < n) {
-            for (int p = arp[row] + lane; p < arp[row + 1]; p += 64) {
-                const int k = aci[p];
-                for (int q = brp[k]; q < brp[k + 1]; ++q) hash_insert(tab[w], bci[q], &uc[w], ovf);
-            }
-        }
-        __syncthreads();
-        const int u = row < n ? uc[w] : 0;
-        const bool ok = u <= kMaxRowOut;
-        if (row < n && ok) {
-            for (int s = lane; s < kHS; s += 64) {
-                const int key = tab[w][s];
-                if (key >= 0) lst[w][atomicAdd(&uc2[w], 1)] = key;
-            }
-        }
-        __syncthreads();
-        if (row < n && ok) {
-            for (int e = lane; e < u; e += 64) {
-                const int key = lst[w][e];
-                int rank = 0;
-                for (int f = 0; f < u; ++f) rank += lst[w][f] < key;
-                srt[w][rank] = key;
-            }
-        }
-        __syncthreads();
-        if (row < n && ok) {
-            const int cs = crp[row];
-            const int a0 = arp[row], a1 = arp[row + 1];
-            for (int e = lane; e < u; e += 64) {
-                const int J = srt[w][e];
-                double acc = 0.0;
-                for (int p = a0; p < a1; ++p) {
-                    const int k = aci[p];
-                    int lo = brp[k], hi = brp[k + 1] - 1;
-                    while (lo <= hi) {
-                        const int mid = (lo + hi) >> 1;
-                        const int cm = bci[mid];
-                        if (cm == J) {
-                            const double prod = av[p] * bv[mid];
-                            acc = acc + prod;
-                            break;
-                        }
-                        if (cm < J) lo = mid + 1;
-                        else hi = mid - 1;
-                    }
-                }
-                cci[cs + e] = J;
-                cv[cs + e] = acc;
-            }
-        }
-        __syncthreads();
-    }
-}
-
-__device__ __forceinline__ int hash_find(const int *tab, int key) {
-    unsigned h = ((unsigned)key * 2654435761u) & (kHS - 1);
-    for (int probe = 0; probe < kHS; ++probe) {
+template <int HS> __device__ __forceinline__ int hs_find(const int *tab, int key) {
+    unsigned h = ((unsigned)key * 2654435761u) & (HS - 1);
+    for (int probe = 0; probe < HS; ++probe) {
         const int v = tab[h];
-        if (v == key || v == -1) return v == key ? (int)h : -1;
-        h = (h + 1) & (kHS - 1);
+        if (v == key) return (int)h;
+        if (v == -1) return -1;
+        h = (h + 1) & (HS - 1);
     }
     return -1;
 }
 
-// Fill: rebuild the row's hash of output columns, give every column its rank
-// in ascending order (the output position), then accumulate the products in
-// LDS walking the stored A[i,k] in ascending k; for one k the lanes share out
-// the row of B, whose columns are distinct, so every output entry receives its
-// products strictly in ascending k: the same rounded sums as a sequential loop.
-constexpr int kFillWaves = 2;
-__global__ __launch_bounds__(64 * kFillWaves) void k_spgemm_fill(int n, const int *arp, const int *aci,
-                                                                const double *av, const int *brp,
-                                                                const int *bci, const double *bv,
-                                                                const int *crp, int *cci, double *cv,
-                                                                int *ovf) {
-    __shared__ int tab[kFillWaves][kHS];
-    __shared__ int pos[kFillWaves][kHS];
-    __shared__ int lst[kFillWaves][kMaxRowOut];
-    __shared__ double acc[kFillWaves][kMaxRowOut];
-    __shared__ int uc[kFillWaves], uc2[kFillWaves];
-    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-    for (int base = blockIdx.x * kFillWaves; base < n; base += gridDim.x * kFillWaves) {
-        const int row = base + w;
-        for (int s = lane; s < kHS; s += 64) tab[w][s] = -1;
-        if (lane == 0) {
-            uc[w] = 0;
-            uc2[w] = 0;
+// Insert the columns of B[qb:qe) into the hash, loading them 8 at a time
+// before the inserts so that their latencies overlap.
+template <int HS>
+__device__ __forceinline__ void hs_insert_row(int *tab, const int *bci, int qb, int qe, int *ucount, int *ovf) {
+    for (int q0 = qb; q0 < qe; q0 += 8) {
+        int key[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) key[i] = q0 + i < qe ? bci[q0 + i] : -1;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (key[i] >= 0) hs_insert<HS>(tab, key[i], ucount, ovf);
+    }
+}
+
+// Symbolic pass, W wavefronts per row of A sharing one LDS hash: output
+// columns per row; maxes[0] and maxes[1] receive the largest output row and
+// the longest row of B that is referenced.
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_spgemm_count(int n, const int *arp, const int *aci, const int *brp,
+                                                         const int *bci, int *cnt, int *ovf, int *maxes) {
+    constexpr int NT = 64 * W;
+    __shared__ int tab[kHS];
+    __shared__ int uc;
+    __shared__ int red[2][W];
+    const int t = threadIdx.x;
+    int umax = 0, bmax = 0;
+    for (int row = blockIdx.x; row < n; row += gridDim.x) {
+        for (int s = t; s < kHS; s += NT) tab[s] = -1;
+        if (t == 0) uc = 0;
+        __syncthreads();
+        for (int p = arp[row] + t; p < arp[row + 1]; p += NT) {
+            const int k = aci[p];
+            const int qb = brp[k], qe = brp[k + 1];
+            bmax = max(bmax, qe - qb);
+            hs_insert_row<kHS>(tab, bci, qb, qe, &uc, ovf);
         }
         __syncthreads();
-        if (row < n) {
-            for (int p = arp[row] + lane; p < arp[row + 1]; p += 64) {
-                const int k = aci[p];
-                for (int q = brp[k]; q < brp[k + 1]; ++q) hash_insert(tab[w], bci[q], &uc[w], ovf);
+        if (t == 0) {
+            cnt[row] = uc;
+            umax = max(umax, uc);
+            if (uc > kMaxRowOut) atomicOr(ovf, 1);
+        }
+        __syncthreads();
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        umax = max(umax, __shfl_xor(umax, off));
+        bmax = max(bmax, __shfl_xor(bmax, off));
+    }
+    if (t % 64 == 0) {
+        red[0][t / 64] = umax;
+        red[1][t / 64] = bmax;
+    }
+    __syncthreads();
+    if (t == 0) {
+        for (int w = 1; w < W; ++w) {
+            umax = max(umax, red[0][w]);
+            bmax = max(bmax, red[1][w]);
+        }
+        atomicMax(&maxes[0], umax);
+        atomicMax(&maxes[1], bmax);
+    }
+}
+
+// Numeric pass, W wavefronts per row of A with an LDS hash of HS slots
+// (HS / 2 >= the row's output count): rebuild the row's output columns, give
+// each its rank in ascending order (its output position), then accumulate the
+// products in LDS over the stored A[i,k] in ascending k.  The entries of the
+// A row and the extents of the rows of B they select are staged in LDS.  The
+// NT = 64 W threads form G groups of NT / G; one step hands G consecutive k
+// to the groups (every row of B is at most NT / G long when G > 1), the
+// groups then add their products one group after another with a barrier in
+// between, and the loads of the next step are issued before those additions.
+// For one k the products go to distinct outputs (the columns of row k of B
+// are distinct), so every output entry receives its products strictly in
+// ascending k: the rounded sums of a sequential loop.
+template <int HS, int W>
+__global__ __launch_bounds__(64 * W) void k_spgemm_fill(int n, int G, const int *arp, const int *aci,
+                                                        const double *av, const int *brp, const int *bci,
+                                                        const double *bv, const int *crp, int *cci, double *cv,
+                                                        int *ovf) {
+    constexpr int NT = 64 * W;
+    __shared__ int tab[HS];
+    __shared__ int pos[HS];
+    __shared__ int lst[HS / 2];
+    __shared__ double acc[HS / 2];
+    __shared__ int sqb[NT], sqe[NT];
+    __shared__ double sa[NT];
+    __shared__ int uc, uc2;
+    const int t = threadIdx.x;
+    const int gs = NT / G, grp = t / gs, gl = t % gs;
+    for (int row = blockIdx.x; row < n; row += gridDim.x) {
+        for (int s = t; s < HS; s += NT) tab[s] = -1;
+        if (t == 0) {
+            uc = 0;
+            uc2 = 0;
+        }
+        __syncthreads();
+        const int a0 = arp[row], a1 = arp[row + 1];
+        for (int p = a0 + t; p < a1; p += NT) {
+            const int k = aci[p];
+            hs_insert_row<HS>(tab, bci, brp[k], brp[k + 1], &uc, ovf);
+        }
+        __syncthreads();
+        const int u = uc;
+        if (u > HS / 2) {  // the host sized HS from the symbolic pass: cannot happen
+            if (t == 0) atomicOr(ovf, 2);
+            __syncthreads();
+            continue;
+        }
+        for (int s = t; s < HS; s += NT) {
+            const int key = tab[s];
+            if (key >= 0) lst[atomicAdd(&uc2, 1)] = key;
+        }
+        __syncthreads();
+        const int cs = crp[row];
+        for (int s = t; s < HS; s += NT) {
+            const int key = tab[s];
+            if (key < 0) continue;
+            int rank = 0;
+            for (int f = 0; f < u; ++f) rank += lst[f] < key;
+            pos[s] = rank;
+            cci[cs + rank] = key;
+            acc[rank] = 0.0;
+        }
+        for (int p0 = a0; p0 < a1; p0 += NT) {
+            const int cnt = min(NT, a1 - p0);
+            __syncthreads();  // ranks and zeroed sums done / previous chunk's staging no longer read
+            if (t < cnt) {
+                const int k = aci[p0 + t];
+                sa[t] = av[p0 + t];
+                sqb[t] = brp[k];
+                sqe[t] = brp[k + 1];
             }
-        }
-        __syncthreads();
-        const int u = row < n ? uc[w] : 0;
-        const bool ok = row < n && u <= kMaxRowOut;
-        if (ok) {
-            for (int s = lane; s < kHS; s += 64) {
-                const int key = tab[w][s];
-                if (key >= 0) lst[w][atomicAdd(&uc2[w], 1)] = key;
+            __syncthreads();
+            int nkey = -1;
+            double nval = 0.0;
+            if (grp < cnt) {
+                const int q = sqb[grp] + gl;
+                if (q < sqe[grp]) {
+                    nkey = bci[q];
+                    nval = bv[q];
+                }
             }
-        }
-        __syncthreads();
-        if (ok) {
-            const int cs = crp[row];
-            for (int s = lane; s < kHS; s += 64) {
-                const int key = tab[w][s];
-                if (key < 0) continue;
-                int rank = 0;
-                for (int f = 0; f < u; ++f) rank += lst[w][f] < key;
-                pos[w][s] = rank;
-                cci[cs + rank] = key;
-                acc[w][rank] = 0.0;
-            }
-        }
-        __syncthreads();
-        if (ok) {
-            const int a0 = arp[row], a1 = arp[row + 1];
-            for (int p = a0; p < a1; ++p) {
-                const int k = aci[p];
-                const double a = av[p];
-                for (int q = brp[k] + lane; q < brp[k + 1]; q += 64) {
-                    const int slot = hash_find(tab[w], bci[q]);
+            for (int e0 = 0; e0 < cnt; e0 += G) {
+                const int e = e0 + grp;
+                const int key = nkey;
+                const double val = nval;
+                nkey = -1;
+                if (e + G < cnt) {
+                    const int q = sqb[e + G] + gl;
+                    if (q < sqe[e + G]) {
+                        nkey = bci[q];
+                        nval = bv[q];
+                    }
+                }
+                int r = -1;
+                double prod = 0.0;
+                if (key >= 0) {
+                    const int slot = hs_find<HS>(tab, key);
                     if (slot < 0) {  // cannot happen: every key was inserted above
                         atomicOr(ovf, 2);
-                        continue;
+                    } else {
+                        r = pos[slot];
+                        prod = sa[e] * val;
                     }
-                    const int r = pos[w][slot];
-                    const double prod = a * bv[q];
-                    acc[w][r] = acc[w][r] + prod;
+                }
+                for (int g = 0; g < G; ++g) {
+                    if (grp == g) {
+                        if (r >= 0) acc[r] = acc[r] + prod;
+                        if (G == 1 && e < cnt) {  // rows of B longer than NT: the rest of row k
+                            const double a = sa[e];
+                            for (int q = sqb[e] + NT + gl; q < sqe[e]; q += NT) {
+                                const int slot = hs_find<HS>(tab, bci[q]);
+                                if (slot < 0) {
+                                    atomicOr(ovf, 2);
+                                    continue;
+                                }
+                                const int r2 = pos[slot];
+                                const double prod2 = a * bv[q];
+                                acc[r2] = acc[r2] + prod2;
+                            }
+                        }
+                    }
+                    __syncthreads();
                 }
             }
         }
         __syncthreads();
-        if (ok) {
-            const int cs = crp[row];
-            for (int e = lane; e < u; e += 64) cv[cs + e] = acc[w][e];
-        }
+        for (int e = t; e < u; e += NT) cv[cs + e] = acc[e];
         __syncthreads();
     }
 }
 
 // lower triangle := upper triangle (symbolically symmetric pattern)
-__global__ void k_mirror(int n, const int *rp, const int *ci, double *v, int *bad) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+// one wavefront per row, lanes over the row's entries left of the diagonal
+__global__ __launch_bounds__(kBlock) void k_mirror(int n, const int *rp, const int *ci, double *v, int *bad) {
+    const int lane = threadIdx.x % 64;
+    const int w = (blockIdx.x * kBlock + threadIdx.x) / 64;
+    const int nw = gridDim.x * kBlock / 64;
+    for (int i = w; i < n; i += nw) {
+        for (int p = rp[i] + lane; p < rp[i + 1]; p += 64) {
             const int k = ci[p];
             if (k >= i) break;
             int lo = rp[k], hi = rp[k + 1] - 1, found = -1;
@@ -648,11 +684,14 @@ __global__ void k_to_f32(long n, const double *a, float *b) {
 }
 
 // ---- dense kernels (coarsest level) ----
-__global__ void k_densify(int n, const int *rp, const int *ci, const double *v, const uint8_t *rmask,
-                          const uint8_t *cmask, double *D) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(kBlock) void k_densify(int n, const int *rp, const int *ci, const double *v,
+                                                    const uint8_t *rmask, const uint8_t *cmask, double *D) {
+    const int lane = threadIdx.x % 64;
+    const int w = (blockIdx.x * kBlock + threadIdx.x) / 64;
+    const int nw = gridDim.x * kBlock / 64;
+    for (int i = w; i < n; i += nw) {
         const bool rk = !(rmask && rmask[i]);
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        for (int p = rp[i] + lane; p < rp[i + 1]; p += 64) {
             const int k = ci[p];
             const bool ck = !(cmask && cmask[k]);
             D[(size_t)i * n + k] = (rk && ck) ? v[p] : 0.0;
@@ -663,44 +702,52 @@ __global__ void k_densify(int n, const int *rp, const int *ci, const double *v, 
 // Tiled right-looking Cholesky of the lower triangle (tiles of kTB): per tile
 // column kb, factor the diagonal tile in LDS, solve the panel below it, then
 // update the trailing lower tiles.  Only the lower triangle is read later.
+// Every dense kernel below works on a batch of matrices of one order n stored
+// back to back (matrix blockIdx.z at D + blockIdx.z * n * n).
 constexpr int kTB = 32;
 
-__global__ __launch_bounds__(kBlock) void k_potrf_tile(int n, double *D, int k0, int *bad) {
+__device__ __forceinline__ double *bat(double *D, int n) { return D + (size_t)blockIdx.z * n * n; }
+__device__ __forceinline__ const double *bat(const double *D, int n) { return D + (size_t)blockIdx.z * n * n; }
+
+// Diagonal tile, padded with the identity; per column k the scaled column is
+// formed in a separate LDS vector so that one barrier separates it from the
+// trailing update, which in turn ends with the second barrier of the step.
+__global__ __launch_bounds__(kBlock) void k_potrf_tile(int n, double *Db, int k0, int *bad) {
     __shared__ double T[kTB][kTB + 1];
-    __shared__ double piv;
+    __shared__ double col[kTB];
+    double *D = bat(Db, n);
     const int tb = min(kTB, n - k0);
     const int t = threadIdx.x;
-    for (int e = t; e < tb * tb; e += kBlock) T[e / tb][e % tb] = D[(size_t)(k0 + e / tb) * n + k0 + e % tb];
+    for (int e = t; e < kTB * kTB; e += kBlock) {
+        const int i = e / kTB, j = e % kTB;
+        T[i][j] = (i < tb && j < tb) ? D[(size_t)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
+    }
     __syncthreads();
     for (int k = 0; k < tb; ++k) {
-        if (t == 0) {
+        if (t < kTB) {
             const double a = T[k][k];
-            if (!(a > 0.0)) {
-                atomicOr(bad, 1);
-                piv = 1.0;
-            } else {
-                piv = sqrt(a);
-            }
-            T[k][k] = piv;
+            const double piv = a > 0.0 ? sqrt(a) : 1.0;
+            if (t == k && !(a > 0.0)) atomicOr(bad, 1);
+            col[t] = t == k ? piv : t > k ? T[t][k] / piv : 0.0;
         }
         __syncthreads();
-        if (t > k && t < tb) T[t][k] /= piv;
-        __syncthreads();
-        for (int e = t; e < tb * tb; e += kBlock) {
-            const int i = e / tb, j = e % tb;
-            if (j > k && j <= i) T[i][j] -= T[i][k] * T[j][k];
+        for (int e = t; e < kTB * kTB; e += kBlock) {
+            const int i = e / kTB, j = e % kTB;
+            if (j == k && i >= k) T[i][j] = col[i];
+            else if (j > k && j <= i) T[i][j] -= col[i] * col[j];
         }
         __syncthreads();
     }
-    for (int e = t; e < tb * tb; e += kBlock) {
-        const int i = e / tb, j = e % tb;
-        if (j <= i) D[(size_t)(k0 + i) * n + k0 + j] = T[i][j];
+    for (int e = t; e < kTB * kTB; e += kBlock) {
+        const int i = e / kTB, j = e % kTB;
+        if (i < tb && j <= i) D[(size_t)(k0 + i) * n + k0 + j] = T[i][j];
     }
 }
 
 // panel: rows below the diagonal tile, X = A_ik L_kk^{-T}, one wavefront per row tile
-__global__ __launch_bounds__(64) void k_trsm_tile(int n, double *D, int k0) {
+__global__ __launch_bounds__(64) void k_trsm_tile(int n, double *Db, int k0) {
     __shared__ double Lk[kTB][kTB + 1];
+    double *D = bat(Db, n);
     const int tb = min(kTB, n - k0);
     const int t = threadIdx.x;
     for (int e = t; e < tb * tb; e += 64) Lk[e / tb][e % tb] = D[(size_t)(k0 + e / tb) * n + k0 + e % tb];
@@ -724,8 +771,9 @@ __global__ __launch_bounds__(64) void k_trsm_tile(int n, double *D, int k0) {
 }
 
 // trailing update A_ij -= L_ik L_jk^T for tile pairs i >= j after tile column k0
-__global__ __launch_bounds__(kBlock) void k_syrk_tile(int n, double *D, int k0) {
+__global__ __launch_bounds__(kBlock) void k_syrk_tile(int n, double *Db, int k0) {
     __shared__ double Li[kTB][kTB + 1], Lj[kTB][kTB + 1];
+    double *D = bat(Db, n);
     const int tb = min(kTB, n - k0);
     const int s0 = k0 + tb;  // first trailing row
     const long p = blockIdx.x;
@@ -751,94 +799,143 @@ __global__ __launch_bounds__(kBlock) void k_syrk_tile(int n, double *D, int k0) 
     }
 }
 
-// Lt = L^T for the lower triangle (column k of L becomes a contiguous row)
-__global__ void k_lower_transpose(int n, const double *L, double *Lt) {
-    const long tot = (long)n * n;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
-        const int i = (int)(e / n), j = (int)(e % n);
-        if (j <= i) Lt[(size_t)j * n + i] = L[e];
+// ---- inverse from the Cholesky factor: A^{-1} = W^T W with W = L^{-1} ----
+// kTB x kTB tiles in LDS, zero outside the matrix; 256 threads each own a 2x2
+// block of the product tile.
+typedef double Tile[kTB][kTB + 1];
+
+__device__ __forceinline__ void tile_load(Tile &T, const double *D, int n, int r0, int c0) {
+    for (int e = threadIdx.x; e < kTB * kTB; e += kBlock) {
+        const int a = e / kTB, b = e % kTB;
+        T[a][b] = (r0 + a < n && c0 + b < n) ? D[(size_t)(r0 + a) * n + c0 + b] : 0.0;
     }
 }
 
-// Inverse from the Cholesky factor: R columns of the identity per workgroup,
-// forward solve L y = e_j reading rows of L^T, backward solve L^T x = y
-// reading rows of L (both contiguous), vectors in LDS, one barrier per step.
-// Thread t owns the entries i = t (mod blockDim); the row needed at the next
-// step is loaded before the current step's updates so its latency overlaps.
-constexpr int kInvP = 16;  // entries per thread: n <= kInvP * kBlock = 4096
-__global__ __launch_bounds__(kBlock) void k_chol_inv(int n, int R, const double *Lf, const double *Lt,
-                                                     double *inv) {
-    extern __shared__ double sm[];
-    double *y = sm;          // [R][n]
-    double *w = sm + R * n;  // [R][n]: finished entries
-    const int j0 = blockIdx.x * R;
-    const int t = threadIdx.x, B = blockDim.x;
-    for (int e = t; e < R * n; e += B) {
-        const int q = e / n, i = e % n;
-        y[e] = (j0 + q < n && i == j0 + q) ? 1.0 : 0.0;
+// acc += P Q (transP: P^T Q) for the thread's 2x2 block (rows ra, ra+1; columns cb, cb+1)
+template <bool TransP>
+__device__ __forceinline__ void tile_mac(const Tile &P, const Tile &Q, double acc[2][2]) {
+    const int ra = (threadIdx.x / 16) * 2, cb = (threadIdx.x % 16) * 2;
+#pragma unroll 8
+    for (int m = 0; m < kTB; ++m) {
+        const double a0 = TransP ? P[m][ra] : P[ra][m];
+        const double a1 = TransP ? P[m][ra + 1] : P[ra + 1][m];
+        const double b0 = Q[m][cb], b1 = Q[m][cb + 1];
+        acc[0][0] += a0 * b0;
+        acc[0][1] += a0 * b1;
+        acc[1][0] += a1 * b0;
+        acc[1][1] += a1 * b1;
     }
-    double cur[kInvP], nxt[kInvP];
-#pragma unroll
-    for (int m = 0; m < kInvP; ++m) {
-        const int i = t + m * B;
-        cur[m] = i < n ? Lt[i] : 0.0;  // row 0 of L^T
+}
+
+// Lam[z][k] = inverse of the lower-triangular diagonal tile L_kk (padded rows
+// and columns of a ragged last tile act as the identity); one wavefront per
+// tile, lane j < kTB solves L_kk x = e_j by forward substitution.
+__global__ __launch_bounds__(64) void k_trtri_tile(int n, const double *Db, double *Lamb) {
+    __shared__ double T[kTB][kTB + 1];
+    const double *D = bat(Db, n);
+    const int T0 = ceil_div(n, kTB);
+    double *Lam = Lamb + ((size_t)blockIdx.z * T0 + blockIdx.x) * kTB * kTB;
+    const int k0 = blockIdx.x * kTB;
+    for (int e = threadIdx.x; e < kTB * kTB; e += 64) {
+        const int a = e / kTB, b = e % kTB;
+        const bool in = k0 + a < n && k0 + b < n;
+        T[a][b] = b > a ? 0.0 : in ? D[(size_t)(k0 + a) * n + k0 + b] : (a == b ? 1.0 : 0.0);
     }
     __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        if (k + 1 < n) {
-            const double *nr = Lt + (size_t)(k + 1) * n;
+    const int j = threadIdx.x;
+    if (j >= kTB) return;
+    double x[kTB];
 #pragma unroll
-            for (int m = 0; m < kInvP; ++m) {
-                const int i = t + m * B;
-                nxt[m] = i < n ? nr[i] : 0.0;
-            }
-        }
-        const double dk = Lf[(size_t)k * n + k];
-        for (int q = 0; q < R; ++q) {
-            const double yk = y[q * n + k] / dk;
+    for (int i = 0; i < kTB; ++i) {
+        double v = i == j ? 1.0 : 0.0;
 #pragma unroll
-            for (int m = 0; m < kInvP; ++m) {
-                const int i = t + m * B;
-                if (i > k && i < n) y[q * n + i] -= cur[m] * yk;
-            }
-            if (t == 0) w[q * n + k] = yk;
+        for (int m = 0; m < i; ++m) v -= T[i][m] * x[m];
+        x[i] = v / T[i][i];
+    }
+#pragma unroll
+    for (int i = 0; i < kTB; ++i) Lam[i * kTB + j] = x[i];
+}
+
+// Block forward substitution for W = L^{-1}, step k (tile row k): every block
+// (i, c), i > k, c <= k, forms W_kc = Lam_k Acc_kc (W_kk = Lam_k) and updates
+// Acc_ic -= L_ik W_kc; the blocks with i = k + 1 (or the only row of blocks at
+// the last step) store W_kc.  Acc starts at zero and holds, for row k, minus
+// the sum of L_km W_mc over m < k when step k runs.
+__global__ __launch_bounds__(kBlock) void k_trinv_step(int n, int k, const double *Db, const double *Lamb,
+                                                       double *Accb, double *Wb) {
+    __shared__ Tile P, Q, R;
+    const double *D = bat(Db, n);
+    double *Acc = bat(Accb, n), *W = bat(Wb, n);
+    const int T0 = ceil_div(n, kTB);
+    const double *Lam = Lamb + ((size_t)blockIdx.z * T0 + k) * kTB * kTB;
+    const int c = blockIdx.y, i = k + 1 + blockIdx.x;
+    const int t = threadIdx.x, ra = (t / 16) * 2, cb = (t % 16) * 2;
+    for (int e = t; e < kTB * kTB; e += kBlock) P[e / kTB][e % kTB] = Lam[e];
+    if (c < k) tile_load(Q, Acc, n, k * kTB, c * kTB);
+    __syncthreads();
+    if (c < k) {
+        double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        tile_mac<false>(P, Q, acc);
+        R[ra][cb] = acc[0][0];
+        R[ra][cb + 1] = acc[0][1];
+        R[ra + 1][cb] = acc[1][0];
+        R[ra + 1][cb + 1] = acc[1][1];
+    } else {
+        for (int e = t; e < kTB * kTB; e += kBlock) R[e / kTB][e % kTB] = P[e / kTB][e % kTB];
+    }
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        for (int e = t; e < kTB * kTB; e += kBlock) {
+            const int a = e / kTB, b = e % kTB;
+            const int r = k * kTB + a, col = c * kTB + b;
+            if (r < n && col < n) W[(size_t)r * n + col] = R[a][b];
         }
+    }
+    if (i >= T0) return;
+    tile_load(P, D, n, i * kTB, k * kTB);
+    __syncthreads();
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    tile_mac<false>(P, R, acc);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int r = i * kTB + ra + u, col = c * kTB + cb + v;
+            if (r < n && col < n) Acc[(size_t)r * n + col] -= acc[u][v];
+        }
+}
+
+// X = W^T W for lower-triangular W: tile (i, j), i >= j, is the sum over tile
+// rows m >= i of W_mi^T W_mj; it is stored with its mirror X_ji.
+__global__ __launch_bounds__(kBlock) void k_wtw(int n, const double *Wb, double *Xb) {
+    __shared__ Tile P, Q;
+    const double *W = bat(Wb, n);
+    double *X = bat(Xb, n);
+    const int T0 = ceil_div(n, kTB);
+    const long p = blockIdx.x;
+    long ti = (long)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > p) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= p) ++ti;
+    const int i = (int)ti, j = (int)(p - ti * (ti + 1) / 2);
+    const int t = threadIdx.x, ra = (t / 16) * 2, cb = (t % 16) * 2;
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int m = i; m < T0; ++m) {
+        tile_load(P, W, n, m * kTB, i * kTB);
+        tile_load(Q, W, n, m * kTB, j * kTB);
         __syncthreads();
-#pragma unroll
-        for (int m = 0; m < kInvP; ++m) cur[m] = nxt[m];
-    }
-#pragma unroll
-    for (int m = 0; m < kInvP; ++m) {
-        const int i = t + m * B;
-        cur[m] = i < n ? Lf[(size_t)(n - 1) * n + i] : 0.0;
-    }
-    for (int k = n - 1; k >= 0; --k) {
-        if (k > 0) {
-            const double *pr = Lf + (size_t)(k - 1) * n;
-#pragma unroll
-            for (int m = 0; m < kInvP; ++m) {
-                const int i = t + m * B;
-                nxt[m] = i < n ? pr[i] : 0.0;
-            }
-        }
-        const double dk = Lf[(size_t)k * n + k];
-        for (int q = 0; q < R; ++q) {
-            const double xk = w[q * n + k] / dk;
-#pragma unroll
-            for (int m = 0; m < kInvP; ++m) {
-                const int i = t + m * B;
-                if (i < k) w[q * n + i] -= cur[m] * xk;
-            }
-            if (t == 0) y[q * n + k] = xk;
-        }
+        tile_mac<true>(P, Q, acc);
         __syncthreads();
+    }
 #pragma unroll
-        for (int m = 0; m < kInvP; ++m) cur[m] = nxt[m];
-    }
-    for (int e = t; e < R * n; e += B) {
-        const int q = e / n, i = e % n;
-        if (j0 + q < n) inv[(size_t)(j0 + q) * n + i] = y[e];
-    }
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int r = i * kTB + ra + u, col = j * kTB + cb + v;
+            if (r < n && col < n) {
+                X[(size_t)r * n + col] = acc[u][v];
+                X[(size_t)col * n + r] = acc[u][v];
+            }
+        }
 }
 
 // C = op(A) B, n x n row-major, op(A) = A or A^T; 16x16 LDS tiles
@@ -879,6 +976,11 @@ int gsz(long n) {
     return (int)g;
 }
 
+// grid for one wavefront per row
+int gwave(long rows) {
+    return gsz(rows * 64);
+}
+
 struct Setup {
     Ctx &c;
     hipStream_t s;
@@ -891,6 +993,24 @@ struct Setup {
     }
 
     void zero(void *p, size_t bytes) { AMG_HIP(hipMemsetAsync(p, 0, bytes, s)); }
+
+    // Sticky failure flags of checks that need no immediate answer (nothing
+    // downstream indexes memory by the flagged values): set by kernels,
+    // cleared once per phase and read at its end in one transfer.
+    static constexpr int kFlag0 = 16, kFlagN = 32;
+    static constexpr int kFlagFill = 16, kFlagMirror = 17, kFlagChol = 18, kFlagMassDiag = 19, kFlagDiag = 20;
+    void clear_flags() { zero(c.iscratch + kFlag0, kFlagN * sizeof(int)); }
+    void check_flags() {
+        AMG_HIP(hipMemcpyAsync(c.hiscr, c.iscratch + kFlag0, kFlagN * sizeof(int), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipStreamSynchronize(s));
+        const int *f = c.hiscr - kFlag0;
+        for (int j = 0; j < kFlag0 + kFlagN - kFlagDiag; ++j)
+            if (f[kFlagDiag + j]) fail(AMG_ERR_NOT_SPD, "non-positive diagonal at level " + std::to_string(j));
+        if (f[kFlagMassDiag]) fail(AMG_ERR_NOT_SPD, "mass matrix has a non-positive diagonal");
+        if (f[kFlagChol]) fail(AMG_ERR_NOT_SPD, "dense Cholesky met a non-positive pivot");
+        if (f[kFlagMirror]) fail(AMG_ERR_ARG, "coarse matrix pattern is not symmetric");
+        if (f[kFlagFill]) fail(AMG_ERR_CAPACITY, "sparse product: output column lost in the fill");
+    }
 
     // out[0..n] exclusive scan of cnt[0..n-1]; returns the total
     int scan(const int *cnt, int *out, int n) {
@@ -937,22 +1057,43 @@ struct Setup {
         int *cnt = c.arena.alloc<int>(A.n + 1);
         C.rp = c.arena.alloc<int>(A.n + 1);
         zero(c.iscratch + 4, sizeof(int));
-        const int g = std::min(4096, std::max(1, ceil_div(A.n, 4)));
-        hipLaunchKernelGGL(k_spgemm_count, dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci, B.rp, B.ci, cnt,
-                           c.iscratch + 4);
+        zero(c.iscratch + 10, 2 * sizeof(int));
+        // one wavefront per row, or four when the rows are too few to fill the chip
+        const bool wide = A.n < 8192;
+        const int NT = wide ? 256 : 64;
+        const int gr = std::max(1, std::min(A.n, 32768));
+        if (wide)
+            hipLaunchKernelGGL(k_spgemm_count<4>, dim3(gr), dim3(256), 0, s, A.n, A.rp, A.ci, B.rp, B.ci, cnt,
+                               c.iscratch + 4, c.iscratch + 10);
+        else
+            hipLaunchKernelGGL(k_spgemm_count<1>, dim3(gr), dim3(64), 0, s, A.n, A.rp, A.ci, B.rp, B.ci, cnt,
+                               c.iscratch + 4, c.iscratch + 10);
         check_kernels();
-        if (read_int(c.iscratch + 4))
+        AMG_HIP(hipMemcpyAsync(c.hiscr, c.iscratch + 4, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipStreamSynchronize(s));
+        if (c.hiscr[0])
             fail(AMG_ERR_CAPACITY, "sparse product row exceeds " + std::to_string(kMaxRowOut) + " columns");
+        const int umax = c.hiscr[6], bmax = c.hiscr[7];
         C.nnz = scan(cnt, C.rp, A.n);
         C.ci = c.arena.alloc<int>(C.nnz);
         C.v = c.arena.alloc<double>(C.nnz);
-        if ((double)B.nnz <= 8.0 * (double)B.n) {  // short rows of B: per-column search
-            hipLaunchKernelGGL(k_spgemm_fill_search, dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci, A.v, B.rp, B.ci,
-                               B.v, C.rp, C.ci, C.v, c.iscratch + 4);
+        // G rows of B per step when every row of B fits NT / G threads (groups of 8 at least)
+        int G = 1;
+        while (2 * G <= NT / 8 && NT / (2 * G) >= bmax) G *= 2;
+        auto fill = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(gr), dim3(NT), 0, s, A.n, G, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci,
+                               C.v, c.iscratch + kFlagFill);
+        };
+        if (wide) {
+            if (umax <= 128) fill(k_spgemm_fill<256, 4>);
+            else if (umax <= 256) fill(k_spgemm_fill<512, 4>);
+            else if (umax <= 512) fill(k_spgemm_fill<1024, 4>);
+            else fill(k_spgemm_fill<2048, 4>);
         } else {
-            const int gf = std::min(8192, std::max(1, ceil_div(A.n, kFillWaves)));
-            hipLaunchKernelGGL(k_spgemm_fill, dim3(gf), dim3(64 * kFillWaves), 0, s, A.n, A.rp, A.ci, A.v, B.rp,
-                               B.ci, B.v, C.rp, C.ci, C.v, c.iscratch + 4);
+            if (umax <= 128) fill(k_spgemm_fill<256, 1>);
+            else if (umax <= 256) fill(k_spgemm_fill<512, 1>);
+            else if (umax <= 512) fill(k_spgemm_fill<1024, 1>);
+            else fill(k_spgemm_fill<2048, 1>);
         }
         check_kernels();
         c.arena.release(cnt);
@@ -990,10 +1131,9 @@ struct Setup {
     DCsr galerkin(const DCsr &S, const DCsr &St, const DCsr &A) {
         DCsr T = spgemm(A, S);
         DCsr C = spgemm(St, T);
-        zero(c.iscratch + 5, sizeof(int));
-        hipLaunchKernelGGL(k_mirror, dim3(gsz(C.n)), dim3(kBlock), 0, s, C.n, C.rp, C.ci, C.v, c.iscratch + 5);
+        hipLaunchKernelGGL(k_mirror, dim3(gwave(C.n)), dim3(kBlock), 0, s, C.n, C.rp, C.ci, C.v,
+                           c.iscratch + kFlagMirror);
         check_kernels();
-        if (read_int(c.iscratch + 5)) fail(AMG_ERR_ARG, "coarse matrix pattern is not symmetric");
         c.arena.release(T.rp);
         c.arena.release(T.ci);
         c.arena.release(T.v);
@@ -1007,9 +1147,11 @@ struct Setup {
         const int n = A.n;
         const uint8_t *mask = L0.mask;
         double *d = c.arena.alloc<double>(n);
-        zero(c.iscratch, sizeof(int));
-        hipLaunchKernelGGL(k_diag, dim3(gsz(n)), dim3(kBlock), 0, s, n, A.rp, A.ci, A.v, mask, d, c.iscratch);
-        if (read_int(c.iscratch)) fail(AMG_ERR_NOT_SPD, "non-positive diagonal at level " + std::to_string(j));
+        hipLaunchKernelGGL(k_diag, dim3(gsz(n)), dim3(kBlock), 0, s, n, A.rp, A.ci, A.v, mask, d,
+                           c.iscratch + kFlagDiag + std::min(j, kFlag0 + kFlagN - kFlagDiag - 1));
+        // the input matrix is checked before anything is built on it
+        if (j == 0 && read_int(c.iscratch + kFlagDiag))
+            fail(AMG_ERR_NOT_SPD, "non-positive diagonal at level 0");
         // strength graph
         const double theta = c.o.theta0 * std::ldexp(1.0, -j);
         const double t = theta * theta;
@@ -1107,50 +1249,58 @@ struct Setup {
         hipLaunchKernelGGL(k_l1, dim3(gsz(n)), dim3(kBlock), 0, s, n, L.A.rp, L.A.v, L.dl1inv, dl1);
         double *md = c.arena.alloc<double>(n);
         L.mdinv = c.arena.alloc<double>(n);
-        zero(c.iscratch, sizeof(int));
         hipLaunchKernelGGL(k_diag, dim3(gsz(n)), dim3(kBlock), 0, s, n, L.M.rp, L.M.ci, L.M.v,
-                           (const uint8_t *)nullptr, md, c.iscratch);
+                           (const uint8_t *)nullptr, md, c.iscratch + kFlagMassDiag);
         hipLaunchKernelGGL(k_inv, dim3(gsz(n)), dim3(kBlock), 0, s, n, md, L.mdinv);
         check_kernels();
-        if (read_int(c.iscratch)) fail(AMG_ERR_NOT_SPD, "mass matrix has a non-positive diagonal");
         c.arena.release(dl1);
         c.arena.release(md);
     }
 
-    // dense inverse of a (masked) sparse SPD matrix through its Cholesky factor
-    double *dense_inverse(const DCsr &A, const uint8_t *mask, bool unit_masked_diag) {
-        const int n = A.n;
-        double *D = c.arena.alloc<double>((size_t)n * n);
-        zero(D, sizeof(double) * n * n);
-        hipLaunchKernelGGL(k_densify, dim3(gsz(n)), dim3(kBlock), 0, s, n, A.rp, A.ci, A.v,
-                           (const uint8_t *)nullptr, (const uint8_t *)nullptr, D);
-        (void)mask;
-        (void)unit_masked_diag;
-        return factor_invert(D, n);
+    // dense inverses of nb sparse SPD matrices of one order, returned back to
+    // back (inverse b at the result + b * n * n)
+    double *dense_inverse(std::initializer_list<const DCsr *> mats) {
+        const int nb = (int)mats.size();
+        const int n = (*mats.begin())->n;
+        const size_t nn = (size_t)n * n;
+        double *D = c.arena.alloc<double>(nb * nn);
+        zero(D, sizeof(double) * nb * nn);
+        int b = 0;
+        for (const DCsr *A : mats) {
+            hipLaunchKernelGGL(k_densify, dim3(gwave(n)), dim3(kBlock), 0, s, n, A->rp, A->ci, A->v,
+                               (const uint8_t *)nullptr, (const uint8_t *)nullptr, D + b * nn);
+            ++b;
+        }
+        return factor_invert(D, n, nb);
     }
 
-    double *factor_invert(double *D, int n) {
-        zero(c.iscratch + 9, sizeof(int));
+    // Cholesky factors of the nb matrices in D (overwritten), then their
+    // inverses W^T W, W = L^{-1}, in a new buffer
+    double *factor_invert(double *D, int n, int nb = 1) {
+        const size_t nn = (size_t)n * n;
         for (int k0 = 0; k0 < n; k0 += kTB) {
-            hipLaunchKernelGGL(k_potrf_tile, dim3(1), dim3(kBlock), 0, s, n, D, k0, c.iscratch + 9);
+            hipLaunchKernelGGL(k_potrf_tile, dim3(1, 1, nb), dim3(kBlock), 0, s, n, D, k0, c.iscratch + kFlagChol);
             const int rest = n - (k0 + kTB);
             if (rest <= 0) break;
             const int tiles = ceil_div(rest, kTB);
-            hipLaunchKernelGGL(k_trsm_tile, dim3(tiles), dim3(64), 0, s, n, D, k0);
-            hipLaunchKernelGGL(k_syrk_tile, dim3(tiles * (tiles + 1) / 2), dim3(kBlock), 0, s, n, D, k0);
+            hipLaunchKernelGGL(k_trsm_tile, dim3(tiles, 1, nb), dim3(64), 0, s, n, D, k0);
+            hipLaunchKernelGGL(k_syrk_tile, dim3(tiles * (tiles + 1) / 2, 1, nb), dim3(kBlock), 0, s, n, D, k0);
         }
         check_kernels();
-        if (read_int(c.iscratch + 9)) fail(AMG_ERR_NOT_SPD, "dense Cholesky met a non-positive pivot");
-        double *inv = c.arena.alloc<double>((size_t)n * n);
-        double *Lt = c.arena.alloc<double>((size_t)n * n);
-        hipLaunchKernelGGL(k_lower_transpose, dim3(gsz((long)n * n)), dim3(kBlock), 0, s, n, D, Lt);
-        // LDS: 2 R n doubles within 64 KiB (n <= 4096)
-        const int R = std::max(1, std::min(8, 4096 / n));
-        hipLaunchKernelGGL(k_chol_inv, dim3(ceil_div(n, R)), dim3(kBlock), sizeof(double) * 2 * R * n, s, n, R, D,
-                           Lt, inv);
+        const int T0 = ceil_div(n, kTB);
+        double *lam = c.arena.alloc<double>((size_t)nb * T0 * kTB * kTB);
+        double *acc = c.arena.alloc<double>(nb * nn);
+        double *W = c.arena.alloc<double>(nb * nn);
+        zero(acc, sizeof(double) * nb * nn);
+        zero(W, sizeof(double) * nb * nn);
+        hipLaunchKernelGGL(k_trtri_tile, dim3(T0, 1, nb), dim3(64), 0, s, n, D, lam);
+        for (int k = 0; k < T0; ++k)
+            hipLaunchKernelGGL(k_trinv_step, dim3(std::max(1, T0 - k - 1), k + 1, nb), dim3(kBlock), 0, s, n, k,
+                               D, lam, acc, W);
+        double *inv = c.arena.alloc<double>(nb * nn);
+        hipLaunchKernelGGL(k_wtw, dim3(T0 * (T0 + 1) / 2, 1, nb), dim3(kBlock), 0, s, n, W, inv);
         check_kernels();
-        c.arena.release(D);
-        c.arena.release(Lt);
+        for (void *p : {(void *)D, (void *)lam, (void *)acc, (void *)W}) c.arena.release(p);
         return inv;
     }
 };
@@ -1160,6 +1310,7 @@ struct Setup {
 void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8_t *dirichlet) {
     Setup su(c);
     hipStream_t s = c.stream;
+    su.clear_flags();
     const int N = Ain.nrows;
     c.N = N;
     DCsr A = su.copy_in(Ain);
@@ -1228,15 +1379,15 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
     if (Lc.n > c.o.dense_max)
         fail(AMG_ERR_DENSE_TOO_LARGE, "coarsest level has " + std::to_string(Lc.n) + " rows");
     c.nAinv = Lc.n;
-    c.Ainv = su.dense_inverse(Lc.A, nullptr, false);
+    c.Ainv = su.dense_inverse({&Lc.A});
     // small coarse levels above the coarsest: exact dense A_j and M_j solves
     for (int j = 1; j + 1 < c.L; ++j) {
         Level &Lv = c.lev[j];
         if (Lv.n > c.o.dense_solve_max) continue;
-        Lv.Ainv = su.dense_inverse(Lv.A, nullptr, false);
-        Lv.Minv = su.dense_inverse(Lv.M, nullptr, false);
+        Lv.Ainv = su.dense_inverse({&Lv.A, &Lv.M});
+        Lv.Minv = Lv.Ainv + (size_t)Lv.n * Lv.n;
     }
-    AMG_HIP(hipStreamSynchronize(s));
+    su.check_flags();
 }
 
 // Dense practical-form Hessian at level ell-1: H = X^T M_y X + beta M_u,
@@ -1245,6 +1396,7 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
 void form_dense_hessian(Ctx &c, int ell) {
     Setup su(c);
     hipStream_t s = c.stream;
+    su.clear_flags();
     if (ell < 1) ell = 1;
     if (ell > c.L) ell = c.L;
     const int lv = ell - 1;
@@ -1257,14 +1409,14 @@ void form_dense_hessian(Ctx &c, int ell) {
     c.ell = ell;
     if (n > c.o.dense_max) return;  // solved by loose CG on H (Section 5.2)
     const size_t nn = (size_t)n * n;
-    double *Ainv = (lv == c.L - 1) ? c.Ainv : su.dense_inverse(L.A, nullptr, false);
+    double *Ainv = (lv == c.L - 1) ? c.Ainv : su.dense_inverse({&L.A});
     const uint8_t *mk = lv == 0 ? L.mask : nullptr;
     double *My = c.arena.alloc<double>(nn), *Myu = c.arena.alloc<double>(nn), *Mu = c.arena.alloc<double>(nn);
     for (double *p : {My, Myu, Mu}) su.zero(p, sizeof(double) * nn);
-    hipLaunchKernelGGL(k_densify, dim3(gsz(n)), dim3(kBlock), 0, s, n, L.M.rp, L.M.ci, L.M.v, mk, mk, My);
-    hipLaunchKernelGGL(k_densify, dim3(gsz(n)), dim3(kBlock), 0, s, n, L.M.rp, L.M.ci, L.M.v, mk,
+    hipLaunchKernelGGL(k_densify, dim3(gwave(n)), dim3(kBlock), 0, s, n, L.M.rp, L.M.ci, L.M.v, mk, mk, My);
+    hipLaunchKernelGGL(k_densify, dim3(gwave(n)), dim3(kBlock), 0, s, n, L.M.rp, L.M.ci, L.M.v, mk,
                        (const uint8_t *)nullptr, Myu);
-    hipLaunchKernelGGL(k_densify, dim3(gsz(n)), dim3(kBlock), 0, s, n, L.M.rp, L.M.ci, L.M.v,
+    hipLaunchKernelGGL(k_densify, dim3(gwave(n)), dim3(kBlock), 0, s, n, L.M.rp, L.M.ci, L.M.v,
                        (const uint8_t *)nullptr, (const uint8_t *)nullptr, Mu);
     double *X = c.arena.alloc<double>(nn), *Y = c.arena.alloc<double>(nn), *XtY = c.arena.alloc<double>(nn);
     const dim3 gg(ceil_div(n, 16), ceil_div(n, 16));
@@ -1282,7 +1434,7 @@ void form_dense_hessian(Ctx &c, int ell) {
     c.ell = ell;
     for (double *p : {My, Myu, Mu, X, Y, XtY}) c.arena.release(p);
     if (Ainv != c.Ainv) c.arena.release(Ainv);
-    AMG_HIP(hipStreamSynchronize(s));
+    su.check_flags();
 }
 
 }  // namespace amg
