@@ -3,15 +3,17 @@
 Workload: the 3D unit cube, 64^3 grid split into 6 Kuhn tetrahedra per cube
 (274,625 nodes, 1,572,864 P1 elements), log-normal kappa (16 seeded Fourier
 modes, variance 1), beta = 1e-3, the manufactured desired state of the paper's
-eq. test-state; inner V-cycles and CG in float32 inside FP64 refinement,
-outer Hessian CG, refinement residuals and dense coarse factors in FP64.
+eq. test-state; inner A-solves by FP64 CG preconditioned with float32
+V-cycles (the bulk of the traffic), outer Hessian CG, CG residuals, dot
+products and dense coarse factors in FP64.
 
 One step = the whole hot path on that input, resident in HBM when the timed
 region starts: the smoothed-aggregation setup on the GPU (strength graph,
 aggregation, prolongator smoothing, Galerkin products, dense coarse factors)
 followed by the reduced solve to relative residual 1e-8 (right-hand side
 K^T M_y y_d, outer CG preconditioned with the multilevel Hessian
-preconditioner).  The JSON line also reports the plain FP64 path, the batched
+preconditioner).  The JSON line also reports the plain FP64 path, the
+float32-CG-in-refinement form, the batched
 (16 desired states) path, the V-cycle and dominant-kernel bandwidth, and the
 CPU oracle timed on a bounded sample on this host.
 
@@ -96,10 +98,10 @@ def main():
     yd = torch.as_tensor(p.yd[:, 0].copy()).to(dev)
     torch.cuda.synchronize()
 
-    def step(prec, ydv, nb_max=1):
+    def step(prec, ydv, nb_max=1, **kw):
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev[0].record()
-        s = amg.HessianSolver(A, M, mask, beta=p.beta, inner_precision=prec, nb_max=nb_max)
+        s = amg.HessianSolver(A, M, mask, beta=p.beta, inner_precision=prec, nb_max=nb_max, **kw)
         ev[1].record()
         u, info = s.reduced_solve(ydv, rtol=1e-8)
         ev[2].record()
@@ -143,6 +145,14 @@ def main():
     s64.close()
     log(f"[bench] fp64: setup {fp64_setup_ms:.1f} ms solve {fp64_solve_ms:.1f} ms; mixed vs fp64 {err_mixed_vs_fp64:.2e}")
 
+    # ---- the other float32 form: float32 CG inside FP64 refinement ----
+    sr, ur, infor, ev = step(32, yd, mixed_mode=1)
+    torch.cuda.synchronize()
+    ref_solve_ms = ev[1].elapsed_time(ev[2])
+    err_refine_vs_fp64 = float(torch.linalg.norm(ur - u64) / torch.linalg.norm(u64))
+    sr.close()
+    log(f"[bench] fp32 refinement form: solve {ref_solve_ms:.1f} ms; vs fp64 {err_refine_vs_fp64:.2e}")
+
     # ---- 16 desired states as one block solve vs one at a time ----
     yd16 = torch.as_tensor(inputs.config("c3", nb=16).yd).to(dev).contiguous()
     sb, ub, infob, ev = step(32, yd16, nb_max=16)
@@ -178,7 +188,8 @@ def main():
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "3D unit cube 64^3 Kuhn tets, P1, N=274625, log-normal kappa var 1, beta=1e-3, "
-                               "eq. test-state y_d, nb=1", "N": N, "levels": sizes, "ell": ell},
+                               "eq. test-state y_d, nb=1", "N": N, "levels": sizes, "ell": ell,
+               "inner": "FP64 CG preconditioned by float32 V-cycles"},
         "setup_ms": float(np.median(setup_ms)),
         "solve_ms": float(np.median(solve_ms)),
         "outer_iters": info32["outer_iters"],
@@ -188,6 +199,8 @@ def main():
         "rel_resid": info32["rel_resid"],
         "fp64": {"setup_ms": fp64_setup_ms, "solve_ms": fp64_solve_ms, "outer_iters": info64[0]["outer_iters"]},
         "err_mixed_vs_fp64": err_mixed_vs_fp64,
+        "fp32_refinement": {"solve_ms": ref_solve_ms, "outer_iters": infor[0]["outer_iters"],
+                            "refine_steps": infor[0]["refine_steps"], "err_vs_fp64": err_refine_vs_fp64},
         "batch16": {"solve_ms": batch_solve_ms, "ms_per_state": batch_solve_ms / 16,
                     "outer_iters": max(i["outer_iters"] for i in infob)},
         "vcycle": {"f32_ms": vc_ms, "f32_GBps_alg": vc_bytes / (vc_ms * 1e-3) / 1e9,

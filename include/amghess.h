@@ -83,7 +83,7 @@ typedef struct {
     double mass_rtol;       /* mass-matrix solves (1e-10) */
     double precond_inner_rtol; /* A-solves inside the preconditioner's H_j (1e-10) */
     int32_t inner_maxit, mass_maxit, outer_maxit; /* 500, 500, 200 */
-    int32_t inner_precision;/* 64, or 32: float32 CG + V-cycle inside FP64 refinement */
+    int32_t inner_precision;/* 64, or 32: float32 V-cycles (see mixed_mode) */
     double inner32_rtol;    /* float32 CG tolerance per refinement step (1e-6) */
     int32_t refine_maxit;   /* refinement steps at most (6) */
     int32_t nb_max;         /* widest batch used with this context (1..16) */
@@ -96,6 +96,9 @@ typedef struct {
     int32_t dense_solve_max;/* coarse levels j >= 1 (below the coarsest) with at most this many rows
                                solve A_j and M_j exactly with dense inverses instead of CG (2048;
                                0 = always iterative) */
+    int32_t mixed_mode;     /* inner_precision 32 only.  0 (default): FP64 CG preconditioned by the
+                               float32 V-cycle (residual cast to float32, correction read back);
+                               1: float32 CG + V-cycle inside FP64 iterative refinement */
 } amg_opts;
 
 typedef struct {

@@ -34,7 +34,9 @@ operation order (readings recorded with the design notes):
              j + 1 = max_levels, or when n_{j+1} > 0.9 n_j
   small      on coarse levels (j >= 1) with n_j <= dense_solve_max the
              A_j- and M_j-solves are exact (dense Cholesky) instead of
-             iterative; they return what the iterative solves approximate
+             iterative; they return what the iterative solves approximate.
+             A V-cycle that reaches such a level solves there exactly and
+             goes no deeper (the levels below serve the Hessian levels only)
 """
 from __future__ import annotations
 
@@ -247,6 +249,7 @@ class Opts:
     coarse_hess_rtol: float = 1e-4
     inner32_rtol: float = 1e-6
     refine_maxit: int = 6
+    mixed_mode: int = 0             # float32 path: 0 = FP64 CG with the float32 V-cycle, 1 = refinement
     precond: int = 1                # 0: unpreconditioned outer CG
 
 

@@ -107,10 +107,15 @@ class Oracle:
 
     # ---- V-cycle (AMG preconditioner for A_j) ----
     def vcycle(self, l: int, b: np.ndarray) -> np.ndarray:
+        """One V(nu, nu) cycle from level l; it ends with an exact solve at the
+        coarsest level or at the first coarse level small enough to hold a
+        dense factor of A_l (n_l <= dense_solve_max)."""
         h = self.h
         if l == h.L - 1:
             return sla.cho_solve(h.chol_A, b)
         lev = h.levels[l]
+        if lev.chol_A is not None:
+            return sla.cho_solve(lev.chol_A, b)
         A = lev.A
         x = b / lev.dl1
         for _ in range(self.o.nu - 1):
@@ -126,6 +131,8 @@ class Oracle:
         h = self.h
         if l == h.L - 1:
             return sla.cho_solve(h.chol_A, b.astype(np.float64)).astype(np.float32)
+        if h.levels[l].chol_A is not None:
+            return sla.cho_solve(h.levels[l].chol_A, b.astype(np.float64)).astype(np.float32)
         m = self.l32[l]
         A, dl1 = m["A"], m["dl1"]
         x = b / dl1
@@ -147,9 +154,16 @@ class Oracle:
             return sla.cho_solve(h.chol_A, f)
         if h.levels[j].chol_A is not None:
             return sla.cho_solve(h.levels[j].chol_A, f)
-        if self.mixed:
+        if self.mixed and self.o.mixed_mode == 1:
             return self._solve_A_mixed(j, f, rtol)
         A = h.levels[j].A
+        if self.mixed:
+            # FP64 CG whose preconditioner is the float32 V-cycle applied to
+            # the residual rounded to float32
+            x, it = pcg(A.matvec, lambda r: self.vcycle32(j, r.astype(np.float32)).astype(np.float64), f, rtol,
+                        self.o.inner_maxit)
+            self._count_inner(it)
+            return x
         x, it = pcg(A.matvec, lambda r: self.vcycle(j, r), f, rtol, self.o.inner_maxit)
         self._count_inner(it)
         return x

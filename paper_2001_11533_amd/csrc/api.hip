@@ -82,6 +82,7 @@ void alloc_workspaces(Ctx &c) {
         alloc_cg(c, w.hcg, m);
         alloc_vc(a, w.vc64, m);
         if (mixed) {
+            alloc_cg(c, w.inmx, m);
             alloc_cg(c, w.in32, m);
             alloc_vc(a, w.vc32, m);
             w.rr = a.alloc<double>(m);
@@ -184,6 +185,7 @@ int amg_opts_default(amg_opts *o) {
     o->use_graphs = 1;
     o->coarse_hess_rtol = 1e-4;
     o->dense_solve_max = 2048;
+    o->mixed_mode = 0;
     return AMG_OK;
 }
 
@@ -210,7 +212,8 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
         o.dense_max < 1 || o.dense_max > 4096 || (o.inner_precision != 32 && o.inner_precision != 64) ||
         o.nu != 1 || o.inner_maxit < 1 || o.mass_maxit < 1 || o.outer_maxit < 1 || o.hess_levels < 0 ||
         !(o.theta0 >= 0.0) || o.refine_maxit < 1 || o.use_graphs < 0 || o.use_graphs > 1 ||
-        !(o.coarse_hess_rtol > 0.0) || o.dense_solve_max < 0 || o.dense_solve_max > 4096) {
+        !(o.coarse_hess_rtol > 0.0) || o.dense_solve_max < 0 || o.dense_solve_max > 4096 || o.mixed_mode < 0 ||
+        o.mixed_mode > 1) {
         g_setup_err = "invalid options (beta > 0, 1 <= nb_max <= 16, dense_max <= 4096, nu = 1, precision 32/64)";
         return AMG_ERR_ARG;
     }
@@ -584,8 +587,15 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                 else if (which == 1)  // gathers dinv and b once each, writes x and r
                     *bytes = 4.0 * (n + 1) + (4.0 + sz) * L0.A.nnz + sz * n + 3.0 * sz * n * nbd;
                 else {
+                    // the cycle ends at the first level with a dense inverse
+                    int Lc = c.L - 1;
+                    for (int l = 1; l < c.L - 1; ++l)
+                        if (c.lev[l].Ainv) {
+                            Lc = l;
+                            break;
+                        }
                     double tot = 0.0;
-                    for (int l = 0; l < c.L - 1; ++l) {
+                    for (int l = 0; l < Lc; ++l) {
                         const Level &Lv = c.lev[l];
                         const double nl = Lv.n, nc = c.lev[l + 1].n;
                         const double a = 4.0 * (nl + 1) + (4.0 + sz) * Lv.A.nnz;
@@ -596,7 +606,7 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                         tot += 4.0 * (nc + 1) + (4.0 + sz) * Lv.St.nnz + sz * (nl + nc) * nbd;
                         tot += 4.0 * (nl + 1) + (4.0 + sz) * Lv.S.nnz + sz * (nc + 2 * nl) * nbd;
                     }
-                    const double nc = c.nAinv;
+                    const double nc = c.lev[Lc].n;
                     tot += 8.0 * nc * nc + 2.0 * sz * nc * nbd;
                     *bytes = tot;
                 }

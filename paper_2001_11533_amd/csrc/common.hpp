@@ -86,6 +86,9 @@ struct DCsr {
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)
 constexpr int kMaxGrid = 16384;        // workgroups at most for kernels with reductions
 constexpr int kMaxGridPlain = 1 << 20; // and for kernels without
+// Reducing launches on NB columns: the partials of a finalize grow as grid x NB,
+// so wide batches take fewer (fuller) workgroups.
+template <int NB> constexpr int red_grid_max() { return NB <= 2 ? kMaxGrid : (2 * kMaxGrid) / NB; }
 constexpr int kFinBlock = 1024;        // threads of a finalize kernel
 constexpr int kXcd = 8;          // XCDs of an MI355X
 

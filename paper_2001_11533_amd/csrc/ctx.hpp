@@ -11,6 +11,14 @@
 
 namespace amg {
 
+// A dense coarse operator for x = Inv b: row-major with the row stride ld
+// padded to a multiple of 64 entries (zeros), in FP64 and float32.
+struct DenseOp {
+    int n = 0, ld = 0;
+    double *m64 = nullptr;
+    float *m32 = nullptr;
+};
+
 struct Level {
     int n = 0;
     DCsr A, S, St, M;           // A_j, S_j (n_j x n_{j+1}), S_j^T, mass M_j
@@ -23,6 +31,7 @@ struct Level {
     double omega = 0.0, rho = 0.0;
     double *Ainv = nullptr;     // small coarse levels: dense inverses of A_j and M_j
     double *Minv = nullptr;
+    DenseOp dA, dM;             // their padded apply copies
 };
 
 template <typename T> struct CgWs {
@@ -40,6 +49,7 @@ template <typename T> struct VcWs {
 
 struct LevelWs {
     CgWs<double> in64, mass, hcg;  // inner A-solves, mass solves, coarsest-Hessian CG
+    CgWs<double> inmx;             // inner A-solves preconditioned by the float32 V-cycle
     CgWs<float> in32;
     VcWs<double> vc64;
     VcWs<float> vc32;
@@ -75,6 +85,7 @@ struct Ctx {
     int nAinv = 0;
     double *Hdense = nullptr, *Hinv = nullptr;  // practical-form Hessian at level ell-1
     int nH = 0;
+    DenseOp dAc, dH;  // padded apply copies of Ainv and Hinv
     // reductions (one stream: a single partial buffer and ticket suffice)
     double *part[3] = {nullptr, nullptr, nullptr};  // reduction partials [2*16*kMaxGrid] each
     int pgrid[3] = {0, 0, 0};                       // workgroups that wrote each buffer

@@ -152,8 +152,18 @@ __device__ void sum_partials(const double *__restrict__ partial, int nblk, doubl
     const int q = t / LPS, sub = t % LPS;
     double s = 0.0;
     if (q < Q) {
+        // four running sums (fixed order for a given nblk) keep four loads in flight
         const double *pp = partial + (size_t)q * nblk;
-        for (int b = sub; b < nblk; b += LPS) s += pp[b];
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int b = sub;
+        for (; b + 3 * LPS < nblk; b += 4 * LPS) {
+            s += pp[b];
+            s1 += pp[b + LPS];
+            s2 += pp[b + 2 * LPS];
+            s3 += pp[b + 3 * LPS];
+        }
+        for (; b < nblk; b += LPS) s += pp[b];
+        s = (s + s1) + (s2 + s3);
     }
     red[t] = s;
     __syncthreads();
@@ -273,7 +283,8 @@ __global__ __launch_bounds__(kBlock) void elem_kernel(int n, OP op, Reducer<(NV 
 // non-positive p.q (breakdown, or indefiniteness for the outer CG).
 template <typename T, int NB, bool JAC, int FINE>
 __global__ __launch_bounds__(kBlock) void cg_update_kernel(int n, T *__restrict__ x, T *__restrict__ r,
-                                                           T *__restrict__ z, const T *__restrict__ p,
+                                                           T *__restrict__ z, float *__restrict__ r32,
+                                                           const T *__restrict__ p,
                                                            const T *__restrict__ q, const T *__restrict__ dinv,
                                                            CgScal *sc, const double *__restrict__ part_pq,
                                                            int nblk_pq, int outer,
@@ -331,6 +342,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int n, T *__restrict_
             x[o] += a * p[o];
             const T rv = r[o] - a * q[o];
             r[o] = rv;
+            if (r32) r32[o] = (float)rv;
             acc[0] += (double)rv * (double)rv;
             if constexpr (JAC) {
                 const T zz = dinv[e / NB] * rv;
@@ -357,14 +369,14 @@ template <typename T, int NB> struct GDinvB {  // x_k = dinv_k b_k (first pre-sw
     __device__ T operator()(int k, int c) const { return dinv[k] * b[(size_t)k * NB + c]; }
 };
 
-template <typename T, int NB> struct GZBP {  // p_k = z_k + beta_c pold_k
-    const T *z;
+template <typename T, int NB, typename TZ = T> struct GZBP {  // p_k = z_k + beta_c pold_k
+    const TZ *z;
     const T *pold;
     const CgScal *sc;
     T beta;
     __device__ void prep(int c) { beta = (T)sc->s[c].beta; }
     __device__ T operator()(int k, int c) const {
-        return z[(size_t)k * NB + c] + beta * pold[(size_t)k * NB + c];
+        return (T)z[(size_t)k * NB + c] + beta * pold[(size_t)k * NB + c];
     }
 };
 
@@ -450,8 +462,8 @@ template <typename T, int NB, bool DOT> struct EPost {
 };
 
 // CG search direction and operator: p_i = z_i + beta pold_i, q_i = (A p)_i, acc p.q
-template <typename T, int NB> struct ECgQ {
-    const T *z;
+template <typename T, int NB, typename TZ = T> struct ECgQ {
+    const TZ *z;
     const T *pold;
     T *p;
     T *q;
@@ -463,7 +475,7 @@ template <typename T, int NB> struct ECgQ {
     __device__ void prep(int c) { beta = (T)sc->s[c].beta; }
     __device__ P load(int i, int c) const {
         const size_t o = (size_t)i * NB + c;
-        return {z[o], pold[o]};
+        return {(T)z[o], pold[o]};
     }
     template <int NV> __device__ void operator()(int i, int c, T s, const P &pr, double (&acc)[NV]) const {
         const size_t o = (size_t)i * NB + c;
@@ -700,11 +712,13 @@ template <typename T, int NB, bool JAC> struct OpInit {  // r = b, x = 0, pold =
     const T *b;
     T *r, *x, *pold, *z;
     const T *dinv;
+    float *r32;  // float32 copy of r when not null
     __device__ void prep(int) {}
     template <int NV> __device__ void operator()(int i, int c, double (&acc)[NV]) const {
         const size_t o = (size_t)i * NB + c;
         const T v = b[o];
         r[o] = v;
+        if (r32) r32[o] = (float)v;
         x[o] = T(0);
         pold[o] = T(0);
         acc[0] += (double)v * (double)v;
@@ -944,13 +958,31 @@ template <int NB> struct OpUnpack {  // out[i*nb + c] = in[i*NB + c], c < nb
 };
 
 // ---------------------------------------------------------------------------
-// dense coarse-level apply: x = Inv b (Inv row-major n x n, FP64), one
-// wavefront per row, FP64 accumulation.
-template <typename T, int NB>
-__global__ __launch_bounds__(kBlock) void dense_apply_kernel(int n, const double *__restrict__ inv,
+// dense coarse-level apply: x = Inv b with Inv row-major (stride ld, a
+// multiple of 64 entries, zero padded), entries TM (FP64 or float32), one
+// wavefront per row, 16-byte loads four deep per lane, FP64 accumulation.
+template <typename TM> struct Vec16;
+template <> struct Vec16<double> {
+    using type = double2;
+    static constexpr int n = 2;
+    __device__ static double get(const double2 &v, int e) { return e == 0 ? v.x : v.y; }
+};
+template <> struct Vec16<float> {
+    using type = float4;
+    static constexpr int n = 4;
+    __device__ static double get(const float4 &v, int e) {
+        return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+    }
+};
+
+template <typename T, typename TM, int NB>
+__global__ __launch_bounds__(kBlock) void dense_apply_kernel(int n, int ld, const TM *__restrict__ inv,
                                                              const T *__restrict__ b, T *__restrict__ x,
                                                              const int *__restrict__ stop) {
     if (stop && *stop) return;
+    using V = Vec16<TM>;
+    using VT = typename V::type;
+    constexpr int W = V::n, D = 4;
     const int lane = threadIdx.x % 64;
     const int w = (blockIdx.x * kBlock + threadIdx.x) / 64;
     const int nw = gridDim.x * kBlock / 64;
@@ -958,11 +990,26 @@ __global__ __launch_bounds__(kBlock) void dense_apply_kernel(int n, const double
         double acc[NB];
 #pragma unroll
         for (int c = 0; c < NB; ++c) acc[c] = 0.0;
-        const double *row = inv + (size_t)i * n;
-        for (int k = lane; k < n; k += 64) {
-            const double a = row[k];
+        const TM *row = inv + (size_t)i * ld;
+        for (int k0 = lane * W; k0 < n; k0 += 64 * W * D) {
+            VT m[D];
 #pragma unroll
-            for (int c = 0; c < NB; ++c) acc[c] += a * (double)b[(size_t)k * NB + c];
+            for (int u = 0; u < D; ++u) {
+                const int k = k0 + u * 64 * W;
+                m[u] = k < n ? *reinterpret_cast<const VT *>(row + k) : VT{};
+            }
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+#pragma unroll
+                for (int e = 0; e < W; ++e) {
+                    const int k = k0 + u * 64 * W + e;
+                    if (k < n) {
+                        const double a = V::get(m[u], e);
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) acc[c] += a * (double)b[(size_t)k * NB + c];
+                    }
+                }
+            }
         }
 #pragma unroll
         for (int c = 0; c < NB; ++c) {

@@ -938,6 +938,17 @@ __global__ __launch_bounds__(kBlock) void k_wtw(int n, const double *Wb, double 
         }
 }
 
+// padded FP64 and float32 copies of a dense n x n operator (row stride ld)
+__global__ void k_pad_dense(int n, int ld, const double *src, double *d64, float *d32) {
+    const long tot = (long)n * ld;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot; e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / ld), k = (int)(e % ld);
+        const double v = k < n ? src[(size_t)i * n + k] : 0.0;
+        d64[e] = v;
+        d32[e] = (float)v;
+    }
+}
+
 // C = op(A) B, n x n row-major, op(A) = A or A^T; 16x16 LDS tiles
 __global__ void k_gemm(int n, const double *A, int transA, const double *B, double *C) {
     __shared__ double ta[16][17], tb[16][17];
@@ -1257,6 +1268,16 @@ struct Setup {
         c.arena.release(md);
     }
 
+    DenseOp dense_op(const double *inv, int n) {
+        DenseOp d;
+        d.n = n;
+        d.ld = ceil_div(n, 64) * 64;
+        d.m64 = c.arena.alloc<double>((size_t)n * d.ld);
+        d.m32 = c.arena.alloc<float>((size_t)n * d.ld);
+        hipLaunchKernelGGL(k_pad_dense, dim3(gsz((long)n * d.ld)), dim3(kBlock), 0, s, n, d.ld, inv, d.m64, d.m32);
+        return d;
+    }
+
     // dense inverses of nb sparse SPD matrices of one order, returned back to
     // back (inverse b at the result + b * n * n)
     double *dense_inverse(std::initializer_list<const DCsr *> mats) {
@@ -1380,12 +1401,15 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
         fail(AMG_ERR_DENSE_TOO_LARGE, "coarsest level has " + std::to_string(Lc.n) + " rows");
     c.nAinv = Lc.n;
     c.Ainv = su.dense_inverse({&Lc.A});
+    c.dAc = su.dense_op(c.Ainv, Lc.n);
     // small coarse levels above the coarsest: exact dense A_j and M_j solves
     for (int j = 1; j + 1 < c.L; ++j) {
         Level &Lv = c.lev[j];
         if (Lv.n > c.o.dense_solve_max) continue;
         Lv.Ainv = su.dense_inverse({&Lv.A, &Lv.M});
         Lv.Minv = Lv.Ainv + (size_t)Lv.n * Lv.n;
+        Lv.dA = su.dense_op(Lv.Ainv, Lv.n);
+        Lv.dM = su.dense_op(Lv.Minv, Lv.n);
     }
     su.check_flags();
 }
@@ -1404,7 +1428,10 @@ void form_dense_hessian(Ctx &c, int ell) {
     const int n = L.n;
     if (c.Hdense) c.arena.release(c.Hdense);
     if (c.Hinv) c.arena.release(c.Hinv);
+    if (c.dH.m64) c.arena.release(c.dH.m64);
+    if (c.dH.m32) c.arena.release(c.dH.m32);
     c.Hdense = c.Hinv = nullptr;
+    c.dH = DenseOp{};
     c.nH = 0;
     c.ell = ell;
     if (n > c.o.dense_max) return;  // solved by loose CG on H (Section 5.2)
@@ -1429,6 +1456,7 @@ void form_dense_hessian(Ctx &c, int ell) {
     double *Hf = c.arena.alloc<double>(nn);
     AMG_HIP(hipMemcpyAsync(Hf, H, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
     c.Hinv = su.factor_invert(Hf, n);
+    c.dH = su.dense_op(c.Hinv, n);
     c.Hdense = H;
     c.nH = n;
     c.ell = ell;

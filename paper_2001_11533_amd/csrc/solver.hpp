@@ -32,7 +32,7 @@ template <int NB> struct Solver {
     template <typename T, int NV, class GX, class EP, class FIN>
     void spmv(const DCsr &A, const T *vals, GX gx, EP ep, FIN fin, const int *stop, int pbuf = 0) {
         const Geo geo = make_geo(A.nnz, A.n, NB);
-        const int g = grid_rows(A.n, geo.rpb(), NV > 0 ? kMaxGrid : kMaxGridPlain);
+        const int g = grid_rows(A.n, geo.rpb(), NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
         Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
         if (NV > 0) c.pgrid[pbuf] = g;
         if (A.n == c.N)
@@ -45,7 +45,7 @@ template <int NB> struct Solver {
     }
 
     template <int NV, class OP, class FIN> void elem(int n, OP op, FIN fin, const int *stop, int pbuf = 0) {
-        const int g = grid_rows((long)n * NB, kBlock, NV > 0 ? kMaxGrid : kMaxGridPlain);
+        const int g = grid_rows((long)n * NB, kBlock, NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
         Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
         if (NV > 0) c.pgrid[pbuf] = g;
         if (n == c.N)
@@ -59,8 +59,8 @@ template <int NB> struct Solver {
     // r.r (and r.z) partials into buffer 1
     template <typename T, bool JAC>
     void cg_update(int n, T *x, T *r, T *z, const T *p, const T *q, const T *dinv, CgScal *sc, int outer,
-                   const int *stop) {
-        const int g = grid_rows((long)n * NB, kBlock, kMaxGrid);
+                   const int *stop, float *r32 = nullptr) {
+        const int g = grid_rows((long)n * NB, kBlock, red_grid_max<NB>());
         Reducer<JAC ? 2 : 1, NB> red{c.part[1]};
         // alpha: every workgroup sums the p.q partials itself when they are few,
         // else one finalize kernel forms it first
@@ -71,17 +71,21 @@ template <int NB> struct Solver {
         }
         c.pgrid[1] = g;
         if (n == c.N)
-            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 1>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, p, q, dinv,
+            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 1>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, p, q, dinv,
                                sc, c.part[0], nblk_pq, outer, red, stop);
         else
-            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 0>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, p, q, dinv,
+            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 0>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, p, q, dinv,
                                sc, c.part[0], nblk_pq, outer, red, stop);
     }
 
-    template <typename T> void dense_apply(int n, const double *inv, const T *b, T *x, const int *stop) {
-        const int waves = std::max(1, std::min(n, 1024));
-        const int g = ceil_div(waves * 64, kBlock);
-        hipLaunchKernelGGL((dense_apply_kernel<T, NB>), dim3(g), dim3(kBlock), 0, s, n, inv, b, x, stop);
+    template <typename T> void dense_apply(const DenseOp &d, const T *b, T *x, const int *stop) {
+        const int g = ceil_div((long)d.n * 64, kBlock);
+        if constexpr (std::is_same_v<T, float>)
+            hipLaunchKernelGGL((dense_apply_kernel<T, float, NB>), dim3(g), dim3(kBlock), 0, s, d.n, d.ld, d.m32, b,
+                               x, stop);
+        else
+            hipLaunchKernelGGL((dense_apply_kernel<T, double, NB>), dim3(g), dim3(kBlock), 0, s, d.n, d.ld, d.m64,
+                               b, x, stop);
     }
 
     void read_sc(const CgScal *d) {
@@ -101,11 +105,18 @@ template <int NB> struct Solver {
 
     // ---------------- V-cycle (AMG preconditioner for A_j) ----------------
     // z = V_j b: one l1-Jacobi sweep from zero, residual, restriction with
-    // S^T, recursion, prolongation with S, one l1-Jacobi sweep; the coarsest
-    // level is solved with the dense inverse.  With dot the last kernel also
-    // writes the partials of r.z for the CG (b is the CG residual) to buffer 2.
+    // S^T, recursion, prolongation with S, one l1-Jacobi sweep; the cycle ends
+    // with the dense inverse at the coarsest level or at the first coarser
+    // level that holds one (n <= dense_solve_max).  With dot the last kernel
+    // also writes the partials of r.z for the CG (b is the CG residual) to
+    // buffer 2.
     template <typename T> void vcycle(int j, const T *b, T *z, bool dot, const int *stop) {
-        const int Lc = c.L - 1;
+        int Lc = c.L - 1;
+        for (int l = j + 1; l < c.L - 1; ++l)
+            if (c.lev[l].Ainv) {
+                Lc = l;
+                break;
+            }
         const T *bl = b;
         for (int l = j; l < Lc; ++l) {
             Level &Lv = c.lev[l];
@@ -117,7 +128,7 @@ template <int NB> struct Solver {
             bl = bn;
         }
         T *xc = (j == Lc) ? z : vcws<T>(c.ws[Lc]).x;
-        dense_apply<T>(c.nAinv, c.Ainv, bl, xc, stop);
+        dense_apply<T>(Lc == c.L - 1 ? c.dAc : c.lev[Lc].dA, bl, xc, stop);
         for (int l = Lc - 1; l >= j; --l) {
             Level &Lv = c.lev[l];
             VcWs<T> &v = vcws<T>(c.ws[l]);
@@ -182,10 +193,23 @@ template <int NB> struct Solver {
     // one iteration in flight while it reads the convergence flag of the one
     // before; iterations after convergence return at once in every kernel.
     // Returns the largest iteration count over the columns; x_out gets x.
-    template <typename T, bool JAC>
+    // MIX (FP64 CG only): the preconditioner is the float32 V-cycle; the CG
+    // update also writes r in float32 and the next direction reads z from it.
+    template <typename T, bool JAC, bool MIX = false>
     void cg_iter(int j, const DCsr &A, const T *vals, const T *dinv, CgWs<T> &w, T *pold, T *pnew) {
         const int n = A.n;
         const int *stop = &w.sc->all_conv;
+        if constexpr (MIX) {
+            static_assert(std::is_same_v<T, double> && !JAC, "float32 preconditioning of the FP64 CG only");
+            float *r32 = c.ws[j].b32, *z32 = c.ws[j].d32;
+            spmv<T, 1>(A, vals, GZBP<T, NB, float>{z32, pold, w.sc}, ECgQ<T, NB, float>{z32, pold, pnew, w.q, w.sc},
+                       NoFin{}, stop, 0);
+            cg_update<T, false>(n, nullptr, w.r, w.z, pnew, w.q, dinv, w.sc, 0, stop, r32);
+            vcycle<float>(j, r32, z32, true, stop);
+            hipLaunchKernelGGL((fin2_kernel<NB, FinUB<NB>>), dim3(1), dim3(kFinBlock), 0, s, c.part[1], c.pgrid[1],
+                               c.part[2], c.pgrid[2], FinUB<NB>{w.sc}, stop);
+            return;
+        }
         spmv<T, 1>(A, vals, GZBP<T, NB>{w.z, pold, w.sc}, ECgQ<T, NB>{w.z, pold, pnew, w.q, w.sc}, NoFin{}, stop, 0);
         cg_update<T, JAC>(n, nullptr, w.r, w.z, pnew, w.q, dinv, w.sc, 0, stop);
         if constexpr (JAC) {
@@ -197,24 +221,27 @@ template <int NB> struct Solver {
         }
     }
 
-    template <typename T, bool JAC>
+    template <typename T, bool JAC, bool MIX = false>
     int cg(int j, const DCsr &A, const T *vals, const double *mdinv, CgWs<T> &w, const T *b, T *x, double rtol,
            int maxit, int nlive) {
         const int n = A.n;
         const int *stop = &w.sc->all_conv;
         const T *dinv = nullptr;
         if constexpr (JAC) dinv = mdinv;
-        elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, w.p0, w.z, dinv},
+        float *r32 = nullptr;
+        if constexpr (MIX) r32 = c.ws[j].b32;
+        elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, w.p0, w.z, dinv, r32},
                           FinInit<NB, JAC>{w.sc, rtol, nlive, (void *)x}, nullptr);
         const bool graphs = c.o.use_graphs != 0;
         auto first_precond = [&] {
-            vcycle<T>(j, w.r, w.z, true, stop);
+            if constexpr (MIX) vcycle<float>(j, c.ws[j].b32, c.ws[j].d32, true, stop);
+            else vcycle<T>(j, w.r, w.z, true, stop);
             finish<1>(2, FinRho0<NB>{w.sc}, stop);
         };
         if (graphs && !w.ga) {
             if constexpr (!JAC) w.g0 = capture(first_precond);
-            w.ga = capture([&] { cg_iter<T, JAC>(j, A, vals, dinv, w, w.p0, w.p1); });
-            w.gb = capture([&] { cg_iter<T, JAC>(j, A, vals, dinv, w, w.p1, w.p0); });
+            w.ga = capture([&] { cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p0, w.p1); });
+            w.gb = capture([&] { cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p1, w.p0); });
         }
         if constexpr (!JAC) {
             if (graphs) launch(w.g0);
@@ -223,8 +250,8 @@ template <int NB> struct Solver {
         int it = 0;
         auto step = [&]() {
             if (graphs) launch((it & 1) ? w.gb : w.ga);
-            else if (it & 1) cg_iter<T, JAC>(j, A, vals, dinv, w, w.p1, w.p0);
-            else cg_iter<T, JAC>(j, A, vals, dinv, w, w.p0, w.p1);
+            else if (it & 1) cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p1, w.p0);
+            else cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p0, w.p1);
             ++it;
         };
         const int first = std::min(std::max(1, w.pred - 1), maxit);
@@ -259,16 +286,19 @@ template <int NB> struct Solver {
     // ---------------- solves with A_j ----------------
     void solve_A(int j, const double *f, double *x, double rtol) {
         if (j == c.L - 1 || c.lev[j].Ainv) {
-            dense_apply<double>(c.lev[j].n, j == c.L - 1 ? c.Ainv : c.lev[j].Ainv, f, x, nullptr);
+            dense_apply<double>(j == c.L - 1 ? c.dAc : c.lev[j].dA, f, x, nullptr);
             AMG_HIP(hipGetLastError());
             return;
         }
-        if (c.o.inner_precision == 32) {
+        if (c.o.inner_precision == 32 && c.o.mixed_mode == 1) {
             solve_A_mixed(j, f, x, rtol);
             return;
         }
         Level &L = c.lev[j];
-        const int it = cg<double, false>(j, L.A, L.A.v, nullptr, c.ws[j].in64, f, x, rtol, c.o.inner_maxit, NB);
+        const int it = c.o.inner_precision == 32
+                           ? cg<double, false, true>(j, L.A, L.A.v, nullptr, c.ws[j].inmx, f, x, rtol,
+                                                     c.o.inner_maxit, NB)
+                           : cg<double, false>(j, L.A, L.A.v, nullptr, c.ws[j].in64, f, x, rtol, c.o.inner_maxit, NB);
         c.st.inner_solves++;
         c.st.inner_iters += it;
         c.st.inner_max = std::max<long>(c.st.inner_max, it);
@@ -304,7 +334,7 @@ template <int NB> struct Solver {
     void mass_solve(int j, const double *b, double *x) {
         Level &L = c.lev[j];
         if (L.Minv) {
-            dense_apply<double>(L.n, L.Minv, b, x, nullptr);
+            dense_apply<double>(L.dM, b, x, nullptr);
             AMG_HIP(hipGetLastError());
             return;
         }
@@ -381,7 +411,7 @@ template <int NB> struct Solver {
     void Bop(int l, const double *r, double *z) {
         if (l == c.ell - 1) {
             if (c.Hinv) {
-                dense_apply<double>(c.nH, c.Hinv, r, z, nullptr);
+                dense_apply<double>(c.dH, r, z, nullptr);
                 AMG_HIP(hipGetLastError());
             } else {
                 hess_cg(l, r, z);

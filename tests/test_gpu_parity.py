@@ -25,7 +25,7 @@ def _need_gpu():
 
 
 ORACLE_KEYS = ("hess_levels", "max_coarse", "inner_rtol", "mass_rtol", "precond_inner_rtol", "precond", "dense_max", "dense_solve_max",
-               "inner32_rtol")
+               "inner32_rtol", "mixed_mode")
 
 
 def make(name, n, nb_max=1, **opts):
@@ -144,14 +144,21 @@ def test_reduced_solve_tiny_against_dense():
     assert rel(u, ref) < 1e-9
 
 
-def test_mixed_precision_solve():
-    p, g, o = make("c3", 16, inner_precision=32)
+@pytest.mark.parametrize("mode", [0, 1])
+def test_mixed_precision_solve(mode):
+    # mode 0: FP64 CG preconditioned by the float32 V-cycle; mode 1: float32
+    # CG inside FP64 refinement.  Both against the FP64 oracle to 1e-8, and
+    # the inner iteration counts against the oracle's own float32 emulation.
+    p, g, o = make("c3", 16, inner_precision=32, mixed_mode=mode)
     o64 = osolve.Oracle(o.h)
     yd = p.yd[:, 0]
     u, info = g.reduced_solve(cuda(yd), rtol=1e-8)
     uo, _ = o64.reduced_solve(yd, rtol=1e-12)
-    assert info[0]["refine_steps"] > 0
+    assert (info[0]["refine_steps"] > 0) == (mode == 1)
     assert rel(u, uo) < 1e-8
+    um, _ = o.reduced_solve(yd, rtol=1e-8)
+    assert rel(um, uo) < 1e-8
+    assert abs(info[0]["inner_iters_total"] - o.cnt.inner_iters) <= 0.2 * o.cnt.inner_iters + 5
 
 
 def test_batched_matches_single_columns():
