@@ -207,7 +207,7 @@ def main():
                    "f64_ms": vc64_ms, "f64_GBps_alg": vc64_bytes / (vc64_ms * 1e-3) / 1e9},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "level-0 float32 first l1-Jacobi sweep + residual (spmv_kernel<float,1,0,GDinvB,EPre,1>)",
+                     "kernel": "level-0 float32 first l1-Jacobi sweep + residual (sell_kernel<float,0,GDinvB,EPre>)",
                      "ms": kern_ms, "bytes": kern_bytes},
         "cpu_baseline": cpu,
     }

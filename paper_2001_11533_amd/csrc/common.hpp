@@ -81,6 +81,14 @@ struct DCsr {
     int *ci = nullptr;
     double *v = nullptr;
     float *v32 = nullptr;
+    // optional sliced-ELL copy (finest level): slices of 64 rows stored column
+    // by column, entry k of row 64 s + l at sl_off[s] + 64 k + l; the rows of a
+    // slice are padded to its longest with (column 0, value 0)
+    int nsl = 0;
+    int *sl_off = nullptr;  // [nsl + 1]
+    int *sl_ci = nullptr;
+    double *sl_v = nullptr;
+    float *sl_v32 = nullptr;
 };
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)

@@ -256,6 +256,53 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__re
     if constexpr (NV > 0) block_partials<NV, NB>(acc, red);
 }
 
+// The same product over the sliced-ELL copy (single column): one wavefront
+// per slice of 64 rows, one lane per row; a lane issues the loads of up to 16
+// entries of its row at once, with no dependence on row pointers.
+template <typename T, int NV, class GX, class EP>
+__global__ __launch_bounds__(kBlock) void sell_kernel(int nrows, int nsl, const int *__restrict__ soff,
+                                                      const int *__restrict__ ci, const T *__restrict__ av, GX gx,
+                                                      EP ep, Reducer<(NV > 0 ? NV : 1), 1> red,
+                                                      const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nblk = gridDim.x, b = xcd_block(blockIdx.x, nblk);
+    constexpr int WPB = kBlock / 64;
+    const int per = ceil_div_dev(nsl, nblk * WPB) * WPB;  // contiguous slices per workgroup
+    const int s0 = b * per, s1 = min(nsl, s0 + per);
+    gx.prep(0);
+    ep.prep(0);
+    constexpr int NVA = NV > 0 ? NV : 1;
+    double acc[NVA];
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) acc[v] = 0.0;
+    constexpr int U = 16;
+    for (int sl = s0 + wv; sl < s1; sl += WPB) {
+        const int row = sl * 64 + lane;
+        const bool live = row < nrows;
+        typename EP::P pr{};
+        if (live) pr = ep.load(row, 0);
+        const int o = soff[sl], w = (soff[sl + 1] - o) >> 6;
+        T sum = T(0);
+        for (int k0 = 0; k0 < w; k0 += U) {
+            int kk[U];
+            T aa[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = k0 + u < w;
+                const size_t q = (size_t)o + (size_t)(k0 + u) * 64 + lane;
+                kk[u] = ok ? ci[q] : 0;
+                aa[u] = ok ? av[q] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (k0 + u < w) sum += aa[u] * gx(kk[u], 0);
+        }
+        if (live) ep(row, 0, sum, pr, acc);
+    }
+    if constexpr (NV > 0) block_partials<NV, 1>(acc, red);
+}
+
 // Elementwise kernel over n rows x NB columns with fused reductions.
 template <int NB, int NV, class OP, int FINE>
 __global__ __launch_bounds__(kBlock) void elem_kernel(int n, OP op, Reducer<(NV > 0 ? NV : 1), NB> red,

@@ -938,6 +938,35 @@ __global__ __launch_bounds__(kBlock) void k_wtw(int n, const double *Wb, double 
         }
 }
 
+// sliced-ELL copy of a CSR matrix, one wavefront per slice of 64 rows:
+// widths (64 x the longest row of the slice), then the column-major fill
+__global__ void k_sell_width(int n, int nsl, const int *rp, int *cnt) {
+    const int lane = threadIdx.x % 64;
+    const int w = (blockIdx.x * blockDim.x + threadIdx.x) / 64, nw = gridDim.x * blockDim.x / 64;
+    for (int sl = w; sl < nsl; sl += nw) {
+        const int r = sl * 64 + lane;
+        int len = r < n ? rp[r + 1] - rp[r] : 0;
+        for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off));
+        if (lane == 0) cnt[sl] = len * 64;
+    }
+}
+
+__global__ void k_sell_fill(int n, int nsl, const int *rp, const int *ci, const double *v, const int *soff,
+                            int *sci, double *sv) {
+    const int lane = threadIdx.x % 64;
+    const int w = (blockIdx.x * blockDim.x + threadIdx.x) / 64, nw = gridDim.x * blockDim.x / 64;
+    for (int sl = w; sl < nsl; sl += nw) {
+        const int r = sl * 64 + lane;
+        const int o = soff[sl], wd = (soff[sl + 1] - o) / 64;
+        const int p0 = r < n ? rp[r] : 0, len = r < n ? rp[r + 1] - p0 : 0;
+        for (int k = 0; k < wd; ++k) {
+            const size_t q = (size_t)o + (size_t)k * 64 + lane;
+            sci[q] = k < len ? ci[p0 + k] : 0;
+            sv[q] = k < len ? v[p0 + k] : 0.0;
+        }
+    }
+}
+
 // padded FP64 and float32 copies of a dense n x n operator (row stride ld)
 __global__ void k_pad_dense(int n, int ld, const double *src, double *d64, float *d32) {
     const long tot = (long)n * ld;
@@ -1268,6 +1297,25 @@ struct Setup {
         c.arena.release(md);
     }
 
+    void make_sell(DCsr &A) {
+        const int nsl = ceil_div(A.n, 64);
+        int *cnt = c.arena.alloc<int>(nsl + 1);
+        A.sl_off = c.arena.alloc<int>(nsl + 1);
+        hipLaunchKernelGGL(k_sell_width, dim3(gwave(nsl)), dim3(kBlock), 0, s, A.n, nsl, A.rp, cnt);
+        const int tot = scan(cnt, A.sl_off, nsl);
+        A.sl_ci = c.arena.alloc<int>(tot);
+        A.sl_v = c.arena.alloc<double>(tot);
+        hipLaunchKernelGGL(k_sell_fill, dim3(gwave(nsl)), dim3(kBlock), 0, s, A.n, nsl, A.rp, A.ci, A.v, A.sl_off,
+                           A.sl_ci, A.sl_v);
+        if (A.v32) {
+            A.sl_v32 = c.arena.alloc<float>(tot);
+            hipLaunchKernelGGL(k_to_f32, dim3(gsz(tot)), dim3(kBlock), 0, s, (long)tot, A.sl_v, A.sl_v32);
+        }
+        A.nsl = nsl;
+        check_kernels();
+        c.arena.release(cnt);
+    }
+
     DenseOp dense_op(const double *inv, int n) {
         DenseOp d;
         d.n = n;
@@ -1394,6 +1442,10 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
         L.dl1inv32 = c.arena.alloc<float>(L.n);
         hipLaunchKernelGGL(k_to_f32, dim3(gsz(L.n)), dim3(kBlock), 0, s, (long)L.n, L.dl1inv, L.dl1inv32);
     }
+    // sliced-ELL copies of the finest-level A and M (rows of near-equal length;
+    // the prolongator's rows vary too much for the padding to pay)
+    su.make_sell(c.lev[0].A);
+    su.make_sell(c.lev[0].M);
     su.check_kernels();
     // dense inverse of the coarsest stiffness matrix
     Level &Lc = c.lev[c.L - 1];

@@ -31,6 +31,20 @@ template <int NB> struct Solver {
 
     template <typename T, int NV, class GX, class EP, class FIN>
     void spmv(const DCsr &A, const T *vals, GX gx, EP ep, FIN fin, const int *stop, int pbuf = 0) {
+        if constexpr (NB == 1) {
+            const T *sv = nullptr;
+            if constexpr (std::is_same_v<T, float>) sv = vals == A.v32 ? A.sl_v32 : nullptr;
+            else sv = vals == A.v ? A.sl_v : nullptr;
+            if (A.sl_off && sv) {
+                const int g = grid_rows(A.nsl, kBlock / 64, NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
+                Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
+                if (NV > 0) c.pgrid[pbuf] = g;
+                hipLaunchKernelGGL((sell_kernel<T, NV, GX, EP>), dim3(g), dim3(kBlock), 0, s, A.n, A.nsl, A.sl_off,
+                                   A.sl_ci, sv, gx, ep, red, stop);
+                finish<NV>(pbuf, fin, stop);
+                return;
+            }
+        }
         const Geo geo = make_geo(A.nnz, A.n, NB);
         const int g = grid_rows(A.n, geo.rpb(), NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
         Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
@@ -392,17 +406,22 @@ template <int NB> struct Solver {
     // ---------------- multilevel preconditioner (practical form) ----------------
     // C_l(r) = S_l (B_{l+1} q - beta^{-1} M_{l+1}^{-1} q) + beta^{-1} M_l^{-1} r (+ zprev),
     // q = S_l^T r
-    void Cop(int l, const double *r, double *out, const double *zprev) {
+    // mself: M_l^{-1} r when the caller has it already (the parent C_{l-1}
+    // formed M_l^{-1} (S_{l-1}^T r) for its own correction term), else null
+    void Cop(int l, const double *r, double *out, const double *zprev, const double *mself = nullptr) {
         Level &Lv = c.lev[l];
         LevelWs &w1 = c.ws[l + 1];
         LevelWs &w0 = c.ws[l];
         spmv<double, 0>(Lv.St, Lv.St.v, GPlain<double, NB>{r}, EStore<double, NB>{w1.ml_in}, NoFin{}, nullptr);
         mass_solve(l + 1, w1.ml_in, w1.ml_mup);
         Bop(l + 1, w1.ml_in, w1.ml_out);
-        mass_solve(l, r, w0.ml_mself);
+        if (!mself) {
+            mass_solve(l, r, w0.ml_mself);
+            mself = w0.ml_mself;
+        }
         const double ib = 1.0 / c.o.beta;
         spmv<double, 0>(Lv.S, Lv.S.v, GLin<NB>{w1.ml_out, nullptr, w1.ml_mup, -ib},
-                        ELin<NB>{out, nullptr, 1.0, w0.ml_mself, ib, zprev, 1.0, nullptr}, NoFin{}, nullptr);
+                        ELin<NB>{out, nullptr, 1.0, mself, ib, zprev, 1.0, nullptr}, NoFin{}, nullptr);
         AMG_HIP(hipGetLastError());
     }
 
@@ -422,8 +441,9 @@ template <int NB> struct Solver {
             Cop(0, r, z, nullptr);
             return;
         }
+        // B_l is only reached from C_{l-1}, which left M_l^{-1} r in ml_mup of this level
         LevelWs &w = c.ws[l];
-        Cop(l, r, w.ml_z1, nullptr);
+        Cop(l, r, w.ml_z1, nullptr, w.ml_mup);
         hessian_apply(l, w.ml_z1, w.ml_t, c.o.precond_inner_rtol, r);  // t = r - H_l z1
         Cop(l, w.ml_t, z, w.ml_z1);                                     // z = z1 + C_l t
     }
