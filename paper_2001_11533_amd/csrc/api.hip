@@ -559,9 +559,9 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                     if (which == 0)
                         S.template spmv<T, 0>(L0.A, avals<T>(L0.A), GPlain<T, NB>{v.x}, EStore<T, NB>{v.r}, NoFin{},
                                               nullptr);
-                    else if (which == 1)
-                        S.template spmv<T, 0>(L0.A, avals<T>(L0.A), GDinvB<T, NB>{dl1inv<T>(L0), v.b},
-                                              EPre<T, NB>{dl1inv<T>(L0), v.b, v.x, v.r}, NoFin{}, nullptr);
+                    else if (which == 1)  // the pre-sweep residual r = b - A x, x = D^{-1} b given
+                        S.template spmv<T, 0>(L0.A, avals<T>(L0.A), GPlain<T, NB>{v.x}, EResB<T, NB>{v.b, v.r},
+                                              NoFin{}, nullptr);
                     else
                         S.template vcycle<T>(0, v.b, v.x2, false, nullptr);
                 };
@@ -584,8 +584,8 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
             *ms_avg = ms / reps;
             if (bytes) {
                 if (which == 0) *bytes = spmv_b;
-                else if (which == 1)  // gathers dinv and b once each, writes x and r
-                    *bytes = 4.0 * (n + 1) + (4.0 + sz) * L0.A.nnz + sz * n + 3.0 * sz * n * nbd;
+                else if (which == 1)  // gathers x once, reads b, writes r
+                    *bytes = 4.0 * (n + 1) + (4.0 + sz) * L0.A.nnz + 3.0 * sz * n * nbd;
                 else {
                     // the cycle ends at the first level with a dense inverse
                     int Lc = c.L - 1;
@@ -599,11 +599,13 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                         const Level &Lv = c.lev[l];
                         const double nl = Lv.n, nc = c.lev[l + 1].n;
                         const double a = 4.0 * (nl + 1) + (4.0 + sz) * Lv.A.nnz;
-                        // pre + residual (b, dinv in; x, r out), post (x, b, dinv in; out)
+                        // pre-sweep residual (x gathered, b in, r out), post (x, b, dinv in; out)
+                        tot += a + sz * nl * nbd * 3;
                         tot += a + sz * nl * nbd * 3 + sz * nl;
-                        tot += a + sz * nl * nbd * 3 + sz * nl;
-                        // restriction and prolongation (+ add)
+                        // restriction (with the next level's first iterate when it is
+                        // smoothed) and prolongation (+ add)
                         tot += 4.0 * (nc + 1) + (4.0 + sz) * Lv.St.nnz + sz * (nl + nc) * nbd;
+                        if (l + 1 < Lc) tot += sz * nc + sz * nc * nbd;
                         tot += 4.0 * (nl + 1) + (4.0 + sz) * Lv.S.nnz + sz * (nc + 2 * nl) * nbd;
                     }
                     const double nc = c.lev[Lc].n;

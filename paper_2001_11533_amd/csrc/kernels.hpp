@@ -331,6 +331,7 @@ __global__ __launch_bounds__(kBlock) void elem_kernel(int n, OP op, Reducer<(NV 
 template <typename T, int NB, bool JAC, int FINE>
 __global__ __launch_bounds__(kBlock) void cg_update_kernel(int n, T *__restrict__ x, T *__restrict__ r,
                                                            T *__restrict__ z, float *__restrict__ r32,
+                                                           float *__restrict__ x32, const float *__restrict__ d32,
                                                            const T *__restrict__ p,
                                                            const T *__restrict__ q, const T *__restrict__ dinv,
                                                            CgScal *sc, const double *__restrict__ part_pq,
@@ -389,12 +390,19 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int n, T *__restrict_
             x[o] += a * p[o];
             const T rv = r[o] - a * q[o];
             r[o] = rv;
-            if (r32) r32[o] = (float)rv;
             acc[0] += (double)rv * (double)rv;
             if constexpr (JAC) {
                 const T zz = dinv[e / NB] * rv;
                 z[o] = zz;
                 acc[1] += (double)rv * (double)zz;
+            } else {
+                // the V-cycle's first pre-sweep iterate x0 = D^{-1} r (in its precision)
+                if (z) z[o] = dinv[e / NB] * rv;
+                if (r32) {
+                    const float rf = (float)rv;
+                    r32[o] = rf;
+                    if (x32) x32[o] = d32[e / NB] * rf;
+                }
             }
         }
     }
@@ -407,13 +415,6 @@ template <typename T, int NB> struct GPlain {  // x_k
     const T *x;
     __device__ void prep(int) {}
     __device__ T operator()(int k, int c) const { return x[(size_t)k * NB + c]; }
-};
-
-template <typename T, int NB> struct GDinvB {  // x_k = dinv_k b_k (first pre-sweep from zero)
-    const T *dinv;
-    const T *b;
-    __device__ void prep(int) {}
-    __device__ T operator()(int k, int c) const { return dinv[k] * b[(size_t)k * NB + c]; }
 };
 
 template <typename T, int NB, typename TZ = T> struct GZBP {  // p_k = z_k + beta_c pold_k
@@ -469,21 +470,36 @@ template <typename T, int NB> struct EAdd {  // y_i += sum
     }
 };
 
-// pre-smoothing + residual: x_i = dinv_i b_i, r_i = b_i - (A x)_i
-template <typename T, int NB> struct EPre {
-    const T *dinv;
+// residual after the first pre-sweep, whose iterate x = dinv b the producer
+// of b has written: r_i = b_i - (A x)_i
+template <typename T, int NB> struct EResB {
     const T *b;
-    T *x;
     T *r;
     struct P {
-        T b, d;
+        T b;
     };
     __device__ void prep(int) {}
-    __device__ P load(int i, int c) const { return {b[(size_t)i * NB + c], dinv[i]}; }
+    __device__ P load(int i, int c) const { return {b[(size_t)i * NB + c]}; }
+    template <int NV> __device__ void operator()(int i, int c, T s, const P &pr, double (&)[NV]) const {
+        r[(size_t)i * NB + c] = pr.b - s;
+    }
+};
+
+// restriction that also starts the next level's pre-sweep: y_i = sum,
+// x_i = dinv_i sum
+template <typename T, int NB> struct EStoreX {
+    T *y;
+    const T *dinv;
+    T *x;
+    struct P {
+        T d;
+    };
+    __device__ void prep(int) {}
+    __device__ P load(int i, int) const { return {dinv[i]}; }
     template <int NV> __device__ void operator()(int i, int c, T s, const P &pr, double (&)[NV]) const {
         const size_t o = (size_t)i * NB + c;
-        x[o] = pr.d * pr.b;
-        r[o] = pr.b - s;
+        y[o] = s;
+        x[o] = pr.d * s;
     }
 };
 
@@ -755,17 +771,29 @@ template <int NB> struct FinStore {  // plain reduction result into out[v*NB + c
 
 // ---------------------------------------------------------------------------
 // elementwise operations
-template <typename T, int NB, bool JAC> struct OpInit {  // r = b, x = 0, pold = 0 (Jacobi: z = dinv r)
+// r = b, x = 0, pold = 0; Jacobi: z = dinv r; else, when z is given, the
+// V-cycle's first pre-sweep iterate z = dinv r, and with r32 the float32
+// residual and its iterate x32 = d32 r32
+template <typename T, int NB, bool JAC> struct OpInit {
     const T *b;
     T *r, *x, *pold, *z;
     const T *dinv;
-    float *r32;  // float32 copy of r when not null
+    float *r32;
+    float *x32;
+    const float *d32;
     __device__ void prep(int) {}
     template <int NV> __device__ void operator()(int i, int c, double (&acc)[NV]) const {
         const size_t o = (size_t)i * NB + c;
         const T v = b[o];
         r[o] = v;
-        if (r32) r32[o] = (float)v;
+        if constexpr (!JAC) {
+            if (z) z[o] = dinv[i] * v;
+            if (r32) {
+                const float rf = (float)v;
+                r32[o] = rf;
+                if (x32) x32[o] = d32[i] * rf;
+            }
+        }
         x[o] = T(0);
         pold[o] = T(0);
         acc[0] += (double)v * (double)v;

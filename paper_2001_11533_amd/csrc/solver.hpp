@@ -73,7 +73,7 @@ template <int NB> struct Solver {
     // r.r (and r.z) partials into buffer 1
     template <typename T, bool JAC>
     void cg_update(int n, T *x, T *r, T *z, const T *p, const T *q, const T *dinv, CgScal *sc, int outer,
-                   const int *stop, float *r32 = nullptr) {
+                   const int *stop, float *r32 = nullptr, float *x32 = nullptr, const float *d32 = nullptr) {
         const int g = grid_rows((long)n * NB, kBlock, red_grid_max<NB>());
         Reducer<JAC ? 2 : 1, NB> red{c.part[1]};
         // alpha: every workgroup sums the p.q partials itself when they are few,
@@ -85,10 +85,10 @@ template <int NB> struct Solver {
         }
         c.pgrid[1] = g;
         if (n == c.N)
-            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 1>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, p, q, dinv,
+            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 1>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, x32, d32, p, q, dinv,
                                sc, c.part[0], nblk_pq, outer, red, stop);
         else
-            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 0>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, p, q, dinv,
+            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 0>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, x32, d32, p, q, dinv,
                                sc, c.part[0], nblk_pq, outer, red, stop);
     }
 
@@ -123,7 +123,9 @@ template <int NB> struct Solver {
     // with the dense inverse at the coarsest level or at the first coarser
     // level that holds one (n <= dense_solve_max).  With dot the last kernel
     // also writes the partials of r.z for the CG (b is the CG residual) to
-    // buffer 2.
+    // buffer 2.  The first sweep's iterate x = D^{-1} b is written by whoever
+    // produces b: the caller at level j (into the level's V-cycle x), the
+    // restriction below it.
     template <typename T> void vcycle(int j, const T *b, T *z, bool dot, const int *stop) {
         int Lc = c.L - 1;
         for (int l = j + 1; l < c.L - 1; ++l)
@@ -135,10 +137,14 @@ template <int NB> struct Solver {
         for (int l = j; l < Lc; ++l) {
             Level &Lv = c.lev[l];
             VcWs<T> &v = vcws<T>(c.ws[l]);
-            spmv<T, 0>(Lv.A, avals<T>(Lv.A), GDinvB<T, NB>{dl1inv<T>(Lv), bl},
-                       EPre<T, NB>{dl1inv<T>(Lv), bl, v.x, v.r}, NoFin{}, stop);
-            T *bn = vcws<T>(c.ws[l + 1]).b;
-            spmv<T, 0>(Lv.St, avals<T>(Lv.St), GPlain<T, NB>{v.r}, EStore<T, NB>{bn}, NoFin{}, stop);
+            spmv<T, 0>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x}, EResB<T, NB>{bl, v.r}, NoFin{}, stop);
+            VcWs<T> &vn = vcws<T>(c.ws[l + 1]);
+            if (l + 1 < Lc)
+                spmv<T, 0>(Lv.St, avals<T>(Lv.St), GPlain<T, NB>{v.r},
+                           EStoreX<T, NB>{vn.b, dl1inv<T>(c.lev[l + 1]), vn.x}, NoFin{}, stop);
+            else
+                spmv<T, 0>(Lv.St, avals<T>(Lv.St), GPlain<T, NB>{v.r}, EStore<T, NB>{vn.b}, NoFin{}, stop);
+            T *bn = vn.b;
             bl = bn;
         }
         T *xc = (j == Lc) ? z : vcws<T>(c.ws[Lc]).x;
@@ -218,14 +224,16 @@ template <int NB> struct Solver {
             float *r32 = c.ws[j].b32, *z32 = c.ws[j].d32;
             spmv<T, 1>(A, vals, GZBP<T, NB, float>{z32, pold, w.sc}, ECgQ<T, NB, float>{z32, pold, pnew, w.q, w.sc},
                        NoFin{}, stop, 0);
-            cg_update<T, false>(n, nullptr, w.r, w.z, pnew, w.q, dinv, w.sc, 0, stop, r32);
+            cg_update<T, false>(n, nullptr, w.r, nullptr, pnew, w.q, nullptr, w.sc, 0, stop, r32,
+                                vcws<float>(c.ws[j]).x, c.lev[j].dl1inv32);
             vcycle<float>(j, r32, z32, true, stop);
             hipLaunchKernelGGL((fin2_kernel<NB, FinUB<NB>>), dim3(1), dim3(kFinBlock), 0, s, c.part[1], c.pgrid[1],
                                c.part[2], c.pgrid[2], FinUB<NB>{w.sc}, stop);
             return;
         }
         spmv<T, 1>(A, vals, GZBP<T, NB>{w.z, pold, w.sc}, ECgQ<T, NB>{w.z, pold, pnew, w.q, w.sc}, NoFin{}, stop, 0);
-        cg_update<T, JAC>(n, nullptr, w.r, w.z, pnew, w.q, dinv, w.sc, 0, stop);
+        if constexpr (JAC) cg_update<T, JAC>(n, nullptr, w.r, w.z, pnew, w.q, dinv, w.sc, 0, stop);
+        else cg_update<T, JAC>(n, nullptr, w.r, vcws<T>(c.ws[j]).x, pnew, w.q, dl1inv<T>(c.lev[j]), w.sc, 0, stop);
         if constexpr (JAC) {
             finish<2>(1, FinUpd<NB, true>{w.sc}, stop);
         } else {
@@ -242,9 +250,20 @@ template <int NB> struct Solver {
         const int *stop = &w.sc->all_conv;
         const T *dinv = nullptr;
         if constexpr (JAC) dinv = mdinv;
-        float *r32 = nullptr;
-        if constexpr (MIX) r32 = c.ws[j].b32;
-        elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, w.p0, w.z, dinv, r32},
+        float *r32 = nullptr, *x32 = nullptr;
+        const float *d32 = nullptr;
+        T *z0 = w.z;
+        const T *d0 = dinv;
+        if constexpr (MIX) {
+            r32 = c.ws[j].b32;
+            x32 = vcws<float>(c.ws[j]).x;
+            d32 = c.lev[j].dl1inv32;
+            z0 = nullptr;
+        } else if constexpr (!JAC) {
+            z0 = vcws<T>(c.ws[j]).x;
+            d0 = dl1inv<T>(c.lev[j]);
+        }
+        elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, w.p0, z0, d0, r32, x32, d32},
                           FinInit<NB, JAC>{w.sc, rtol, nlive, (void *)x}, nullptr);
         const bool graphs = c.o.use_graphs != 0;
         auto first_precond = [&] {
