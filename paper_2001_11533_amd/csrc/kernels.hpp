@@ -77,8 +77,12 @@ __device__ __forceinline__ int xcd_block(int b, int nblk) {
     return (b % kXcd) * per + b / kXcd;
 }
 
-// Lanes per row: NB columns x G lanes per (row, column), G a power of two
-// chosen per matrix from its mean row length; LPR = NB G <= 64.
+// Columns per lane: a lane serves CV consecutive columns of the batch, so its
+// gathers and stores are CV contiguous values.
+template <int NB> constexpr int spmv_cv() { return NB >= 4 ? 4 : NB; }
+
+// Lanes per row: NB / CV column groups x G lanes per (row, group), G a power
+// of two chosen per matrix from its mean row length; LPR = (NB / CV) G <= 64.
 struct Geo {
     int lg;   // log2 G
     int llpr; // log2 LPR
@@ -92,20 +96,20 @@ inline int ilog2(int x) {
     return l;
 }
 
-// entries a lane loads together (wide batches: one lane per column walks the row)
-template <int NB> constexpr int spmv_unroll() { return NB >= 8 ? 16 : 4; }
+// entries a lane loads together
+constexpr int kSpmvUnroll = 4;
 
-// G = next power of two >= (mean entries per row) / U, at most 64 / NB
-inline Geo make_geo(long nnz, long rows, int NB) {
+// G = next power of two >= (mean entries per row) / U, at most 64 / (NB / CV)
+template <int NB> inline Geo make_geo(long nnz, long rows) {
+    constexpr int NG = NB / spmv_cv<NB>();
     const double m = rows > 0 ? (double)nnz / (double)rows : 1.0;
-    const double u = NB >= 8 ? 16.0 : 4.0;
     int g = 1;
-    while (g < 64 && g < m / u) g <<= 1;
-    while (g * NB > 64) g >>= 1;
+    while (g < 64 && g < m / kSpmvUnroll) g <<= 1;
+    while (g * NG > 64) g >>= 1;
     if (g < 1) g = 1;
     Geo geo;
     geo.lg = ilog2(g);
-    geo.llpr = ilog2(g * NB);
+    geo.llpr = ilog2(g * NG);
     return geo;
 }
 
@@ -123,22 +127,32 @@ constexpr int pow2floor(int x) {
 // fixed LDS tree; thread t < NV*NB then writes partial (t / NB, t % NB) of
 // this workgroup.  The totals are formed by fin_kernel, launched next on the
 // same stream (a kernel boundary orders the partials; no device-scope fence
-// is issued by the workgroups).
-template <int NV, int NB>
-__device__ void block_partials(const double (&acc)[NV], Reducer<NV, NB> r) {
-    __shared__ double red[NV][kBlock];
+// is issued by the workgroups).  With CV columns per thread, slot t CV + v
+// holds column (t CV + v) mod NB, the column thread t serves as its v-th.
+template <int NV, int NB, int CV>
+__device__ void block_partials_cv(const double (&acc)[CV][NV], Reducer<NV, NB> r) {
+    constexpr int W = kBlock * CV;
+    __shared__ double red[NV][W];
     const int t = threadIdx.x;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) red[v][t] = acc[v];
-    __syncthreads();
-    for (int s = kBlock / 2; s >= NB; s >>= 1) {
-        if (t < s) {
+    for (int v = 0; v < CV; ++v)
 #pragma unroll
-            for (int v = 0; v < NV; ++v) red[v][t] += red[v][t + s];
+        for (int q = 0; q < NV; ++q) red[q][t * CV + v] = acc[v][q];
+    __syncthreads();
+    for (int s = W / 2; s >= NB; s >>= 1) {
+        for (int i = t; i < s; i += kBlock) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) red[q][i] += red[q][i + s];
         }
         __syncthreads();
     }
     if (t < NV * NB) r.partial[(size_t)t * gridDim.x + blockIdx.x] = red[t / NB][t % NB];
+}
+
+template <int NV, int NB>
+__device__ void block_partials(const double (&acc)[NV], Reducer<NV, NB> r) {
+    const double(&a1)[1][NV] = *reinterpret_cast<const double(*)[1][NV]>(&acc);
+    block_partials_cv<NV, NB, 1>(a1, r);
 }
 
 // Sums the nblk partials of each (quantity, column) in a fixed order with
@@ -213,26 +227,41 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__re
                                                       Reducer<(NV > 0 ? NV : 1), NB> red,
                                                       const int *__restrict__ stop) {
     if (stop && *stop) return;
+    constexpr int CV = spmv_cv<NB>(), NG = NB / CV;
     const int t = threadIdx.x;
     const int LPR = geo.lpr(), RPB = geo.rpb(), G = 1 << geo.lg;
-    const int lane = t & (LPR - 1), c = lane % NB, g = lane / NB, rl = t >> geo.llpr;
+    const int lane = t & (LPR - 1), c0 = (lane % NG) * CV, g = lane / NG, rl = t >> geo.llpr;
     const int nblk = gridDim.x, b = xcd_block(blockIdx.x, nblk);
     const int span = ceil_div_dev(nrows, nblk * RPB) * RPB;
     const int r0 = b * span;
     const int r1 = min(nrows, r0 + span);
-    gx.prep(c);
-    ep.prep(c);
-    constexpr int NVA = NV > 0 ? NV : 1;
-    double acc[NVA];
+    GX gxv[CV];
+    EP epv[CV];
 #pragma unroll
-    for (int v = 0; v < NVA; ++v) acc[v] = 0.0;
-    constexpr int U = spmv_unroll<NB>();  // entries per lane issued together
+    for (int v = 0; v < CV; ++v) {
+        gxv[v] = gx;
+        gxv[v].prep(c0 + v);
+        epv[v] = ep;
+        epv[v].prep(c0 + v);
+    }
+    constexpr int NVA = NV > 0 ? NV : 1;
+    double acc[CV][NVA];
+#pragma unroll
+    for (int v = 0; v < CV; ++v)
+#pragma unroll
+        for (int q = 0; q < NVA; ++q) acc[v][q] = 0.0;
+    constexpr int U = kSpmvUnroll;  // entries per lane issued together
     for (int base = r0; base < r1; base += RPB) {
         const int row = base + rl;
         const bool live = row < r1;
-        typename EP::P pr{};
-        if (live && g == 0) pr = ep.load(row, c);
-        T sum = T(0);
+        typename EP::P pr[CV];
+        if (live && g == 0) {
+#pragma unroll
+            for (int v = 0; v < CV; ++v) pr[v] = epv[v].load(row, c0 + v);
+        }
+        T sum[CV];
+#pragma unroll
+        for (int v = 0; v < CV; ++v) sum[v] = T(0);
         if (live) {
             const int p1 = rp[row + 1];
             for (int p = rp[row] + g; p < p1; p += U * G) {
@@ -247,13 +276,22 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__re
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (kk[u] >= 0) sum += aa[u] * gx(kk[u], c);
+                    if (kk[u] >= 0) {
+#pragma unroll
+                        for (int v = 0; v < CV; ++v) sum[v] += aa[u] * gxv[v](kk[u], c0 + v);
+                    }
             }
         }
-        for (int off = NB; off < LPR; off <<= 1) sum += __shfl_xor(sum, off);
-        if (live && g == 0) ep(row, c, sum, pr, acc);
+        for (int off = NG; off < LPR; off <<= 1) {
+#pragma unroll
+            for (int v = 0; v < CV; ++v) sum[v] += __shfl_xor(sum[v], off);
+        }
+        if (live && g == 0) {
+#pragma unroll
+            for (int v = 0; v < CV; ++v) epv[v](row, c0 + v, sum[v], pr[v], acc[v]);
+        }
     }
-    if constexpr (NV > 0) block_partials<NV, NB>(acc, red);
+    if constexpr (NV > 0) block_partials_cv<NV, NB, CV>(acc, red);
 }
 
 // The same product over the sliced-ELL copy (single column): one wavefront

@@ -45,7 +45,7 @@ template <int NB> struct Solver {
                 return;
             }
         }
-        const Geo geo = make_geo(A.nnz, A.n, NB);
+        const Geo geo = make_geo<NB>(A.nnz, A.n);
         const int g = grid_rows(A.n, geo.rpb(), NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
         Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
         if (NV > 0) c.pgrid[pbuf] = g;
