@@ -1,0 +1,71 @@
+"""The 3D 128^3 workload (N = 2,146,689, log-normal kappa with variance 2,
+beta = 1e-4) with 16 desired states solved as one batch, float32 V-cycles
+inside FP64 CG: too large for the oracle, so it is checked by properties that
+hold at any size, on the CPU with the assembled matrices (scipy matvecs):
+
+* every state solve the check uses has its own residual A_0 y = M_yu u;
+* the adjoint solve is the transpose of the state solve (<K^T w, v> = <w, K v>);
+* the solution makes the reduced gradient of eq. functional vanish:
+  K^T M_y (K u - y_d) + beta M_u u = 0 relative to K^T M_y y_d (Section 5.2,
+  eq. firstorderpractice)."""
+import numpy as np
+import pytest
+
+import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+sp = pytest.importorskip("scipy.sparse")
+
+
+def colnorm(x):
+    return np.linalg.norm(x, axis=0)
+
+
+@pytest.mark.timeout(900)
+def test_128cube_batch16_first_order_conditions():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_11533_amd as amg
+    p = inputs.config("c5")
+    N = p.mesh.nverts
+    print(f"128^3 batch of {p.yd.shape[1]}: N={N}", flush=True)
+    rp, ci, va, vm = amg.assemble_p1(p.mesh.coords, p.mesh.elems, p.kappa)
+    A = sp.csr_matrix((va, ci, rp), shape=(N, N))
+    M = sp.csr_matrix((vm, ci, rp), shape=(N, N))
+    d = (p.dirichlet == 0).astype(np.float64)[:, None]           # D = diag(1 - mask)
+    A0 = lambda y: d * (A @ (d * y)) + (1.0 - d) * y              # D A D + (I - D)
+    Myu = lambda u: d * (M @ u)                                    # D M
+    My = lambda y: d * (M @ (d * y))                               # D M D
+
+    g = amg.HessianSolver((rp, ci, va), (rp, ci, vm), p.dirichlet, beta=p.beta, inner_precision=32,
+                          nb_max=16)
+    Yd = torch.tensor(p.yd, device="cuda")
+    U, info = g.reduced_solve(Yd, rtol=1e-8)
+    print(f"outer {max(i['outer_iters'] for i in info)} levels {g.levels()}", flush=True)
+    assert max(i["rel_resid"] for i in info) <= 1e-8
+    u = U.cpu().numpy()
+    yd = p.yd
+
+    # state solve, checked by its residual
+    Y = g.state_solve(U).cpu().numpy()
+    f = Myu(u)
+    assert np.all(colnorm(A0(Y) - f) <= 1e-9 * colnorm(f))
+
+    # adjoint = transpose of the state solve, on two seeded random blocks
+    rng = np.random.default_rng(17)
+    w = rng.standard_normal((N, 2))
+    v = rng.standard_normal((N, 2))
+    Ktw = g.adjoint_solve(torch.tensor(w, device="cuda")).cpu().numpy()
+    Kv = g.state_solve(torch.tensor(v, device="cuda")).cpu().numpy()
+    lhs, rhs = np.sum(Ktw * v, axis=0), np.sum(w * Kv, axis=0)
+    assert np.all(np.abs(lhs - rhs) <= 1e-9 * (np.abs(lhs) + colnorm(w) * colnorm(Kv)))
+
+    # reduced gradient at the solution
+    Z = g.adjoint_solve(torch.tensor(My(Y - yd), device="cuda")).cpu().numpy()
+    b = g.adjoint_solve(torch.tensor(My(yd), device="cuda")).cpu().numpy()
+    grad = Z + p.beta * (M @ u)
+    rel = colnorm(grad) / colnorm(b)
+    print(f"max relative reduced gradient {rel.max():.2e}", flush=True)
+    assert np.all(rel <= 1e-6)
+    g.close()
