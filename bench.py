@@ -4,8 +4,9 @@ Workload: the 3D unit cube, 64^3 grid split into 6 Kuhn tetrahedra per cube
 (274,625 nodes, 1,572,864 P1 elements), log-normal kappa (16 seeded Fourier
 modes, variance 1), beta = 1e-3, the manufactured desired state of the paper's
 eq. test-state; inner A-solves by FP64 CG preconditioned with float32
-V-cycles (the bulk of the traffic), outer Hessian CG, CG residuals, dot
-products and dense coarse factors in FP64.
+V-cycles (the bulk of the traffic; degree-2 Chebyshev smoothing on the l1
+diagonal), outer Hessian CG, CG residuals, dot products and dense coarse
+factors in FP64.
 
 One step = the whole hot path on that input, resident in HBM when the timed
 region starts: the smoothed-aggregation setup on the GPU (strength graph,
@@ -114,6 +115,7 @@ def main():
     torch.cuda.synchronize()
 
     def step(prec, ydv, nb_max=1, **kw):
+        kw.setdefault("smoother", 1)  # V-cycles with the degree-2 Chebyshev smoother
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev[0].record()
         s = amg.HessianSolver(A, M, mask, beta=p.beta, inner_precision=prec, nb_max=nb_max, **kw)
@@ -168,6 +170,20 @@ def main():
     sr.close()
     log(f"[bench] fp32 refinement form: solve {ref_solve_ms:.1f} ms; vs fp64 {err_refine_vs_fp64:.2e}")
 
+    # ---- the paper's comparisons on this workload: plain outer CG (Table 4's
+    # setting) and two Hessian levels (Table 5's), same inner solves; and the
+    # V-cycle with one l1-Jacobi sweep instead of the Chebyshev smoother ----
+    variants = {}
+    for key, kw in (("plain_cg", {"precond": 0}), ("two_level", {"hess_levels": 2}),
+                    ("l1_jacobi_smoother", {"smoother": 0})):
+        sv, uv, infov, ev = step(32, yd, **kw)
+        torch.cuda.synchronize()
+        variants[key] = {"outer_iters": infov[0]["outer_iters"], "solve_ms": ev[1].elapsed_time(ev[2]),
+                         "inner_iters_total": infov[0]["inner_iters_total"],
+                         "rel_diff_vs_multilevel": float(torch.linalg.norm(uv - u32) / torch.linalg.norm(u32))}
+        sv.close()
+        log(f"[bench] {key}: outer {variants[key]['outer_iters']} solve {variants[key]['solve_ms']:.1f} ms")
+
     # ---- 16 desired states as one block solve vs one at a time ----
     yd16 = torch.as_tensor(inputs.config("c3", nb=16).yd).to(dev).contiguous()
     sb, ub, infob, ev = step(32, yd16, nb_max=16)
@@ -204,7 +220,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "3D unit cube 64^3 Kuhn tets, P1, N=274625, log-normal kappa var 1, beta=1e-3, "
                                "eq. test-state y_d, nb=1", "N": N, "levels": sizes, "ell": ell,
-               "inner": "FP64 CG preconditioned by float32 V-cycles"},
+               "inner": "FP64 CG preconditioned by float32 V-cycles",
+               "smoother": "Chebyshev degree 2 on the l1 diagonal"},
         "setup_ms": float(np.median(setup_ms)),
         "solve_ms": float(np.median(solve_ms)),
         "outer_iters": info32["outer_iters"],
@@ -216,6 +233,7 @@ def main():
         "err_mixed_vs_fp64": err_mixed_vs_fp64,
         "fp32_refinement": {"solve_ms": ref_solve_ms, "outer_iters": infor[0]["outer_iters"],
                             "refine_steps": infor[0]["refine_steps"], "err_vs_fp64": err_refine_vs_fp64},
+        "multilevel_vs": variants,
         "batch16": {"solve_ms": batch_solve_ms, "ms_per_state": batch_solve_ms / 16,
                     "outer_iters": max(i["outer_iters"] for i in infob)},
         "vcycle": {"f32_ms": vc_ms, "f32_GBps_alg": vc_bytes / (vc_ms * 1e-3) / 1e9,

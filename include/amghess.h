@@ -99,6 +99,10 @@ typedef struct {
     int32_t mixed_mode;     /* inner_precision 32 only.  0 (default): FP64 CG preconditioned by the
                                float32 V-cycle (residual cast to float32, correction read back);
                                1: float32 CG + V-cycle inside FP64 iterative refinement */
+    int32_t smoother;       /* V-cycle smoothing: 0 (default) nu l1-Jacobi sweeps; 1 the Chebyshev
+                               iteration of degree 2 preconditioned by the l1 diagonal on the interval
+                               [0.3, 1] of the spectrum of D_l1^{-1} A (bounded by 1 on every level),
+                               before and after the coarse correction */
 } amg_opts;
 
 typedef struct {

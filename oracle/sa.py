@@ -240,6 +240,7 @@ class Opts:
     theta0: float = 0.08
     agg_seed: int = 0x200111533
     nu: int = 1
+    smoother: int = 0               # 0 = l1-Jacobi, 1 = Chebyshev of degree 2 (pre and post)
     inner_rtol: float = 1e-10
     mass_rtol: float = 1e-10
     precond_inner_rtol: float = 1e-10

@@ -35,7 +35,8 @@ class Opts(C.Structure):
                 ("inner_precision", C.c_int32), ("inner32_rtol", C.c_double), ("refine_maxit", C.c_int32),
                 ("nb_max", C.c_int32), ("precond", C.c_int32), ("check_every", C.c_int32),
                 ("use_graphs", C.c_int32), ("coarse_hess_rtol", C.c_double),
-                ("dense_solve_max", C.c_int32), ("mixed_mode", C.c_int32)]
+                ("dense_solve_max", C.c_int32), ("mixed_mode", C.c_int32),
+                ("smoother", C.c_int32)]
 
 
 class Info(C.Structure):

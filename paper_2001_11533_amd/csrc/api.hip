@@ -66,6 +66,7 @@ template <typename T> void alloc_vc(Arena &a, VcWs<T> &v, size_t m) {
     v.x = a.alloc<T>(m);
     v.r = a.alloc<T>(m);
     v.x2 = a.alloc<T>(m);
+    v.t = a.alloc<T>(m);
 }
 
 void alloc_workspaces(Ctx &c) {
@@ -186,6 +187,7 @@ int amg_opts_default(amg_opts *o) {
     o->coarse_hess_rtol = 1e-4;
     o->dense_solve_max = 2048;
     o->mixed_mode = 0;
+    o->smoother = 0;
     return AMG_OK;
 }
 
@@ -213,7 +215,7 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
         o.nu != 1 || o.inner_maxit < 1 || o.mass_maxit < 1 || o.outer_maxit < 1 || o.hess_levels < 0 ||
         !(o.theta0 >= 0.0) || o.refine_maxit < 1 || o.use_graphs < 0 || o.use_graphs > 1 ||
         !(o.coarse_hess_rtol > 0.0) || o.dense_solve_max < 0 || o.dense_solve_max > 4096 || o.mixed_mode < 0 ||
-        o.mixed_mode > 1) {
+        o.mixed_mode > 1 || o.smoother < 0 || o.smoother > 1) {
         g_setup_err = "invalid options (beta > 0, 1 <= nb_max <= 16, dense_max <= 4096, nu = 1, precision 32/64)";
         return AMG_ERR_ARG;
     }
@@ -599,9 +601,18 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                         const Level &Lv = c.lev[l];
                         const double nl = Lv.n, nc = c.lev[l + 1].n;
                         const double a = 4.0 * (nl + 1) + (4.0 + sz) * Lv.A.nnz;
-                        // pre-sweep residual (x gathered, b in, r out), post (x, b, dinv in; out)
-                        tot += a + sz * nl * nbd * 3;
-                        tot += a + sz * nl * nbd * 3 + sz * nl;
+                        if (c.o.smoother == 1) {
+                            // Chebyshev: pre step (x, b, dinv in; t out), residual (t, b in; r
+                            // out), post steps (t, b, dinv in; x out) and (x, t, b, dinv in; out)
+                            tot += a + sz * nl * nbd * 3 + sz * nl;
+                            tot += a + sz * nl * nbd * 3;
+                            tot += a + sz * nl * nbd * 3 + sz * nl;
+                            tot += a + sz * nl * nbd * 4 + sz * nl;
+                        } else {
+                            // pre-sweep residual (x gathered, b in, r out), post (x, b, dinv in; out)
+                            tot += a + sz * nl * nbd * 3;
+                            tot += a + sz * nl * nbd * 3 + sz * nl;
+                        }
                         // restriction (with the next level's first iterate when it is
                         // smoothed) and prolongation (+ add)
                         tot += 4.0 * (nc + 1) + (4.0 + sz) * Lv.St.nnz + sz * (nl + nc) * nbd;

@@ -45,6 +45,7 @@ template <typename T> struct CgWs {
 
 template <typename T> struct VcWs {
     T *b = nullptr, *x = nullptr, *r = nullptr, *x2 = nullptr;
+    T *t = nullptr;  // Chebyshev smoothing: the iterate after pre-smoothing
 };
 
 struct LevelWs {

@@ -370,6 +370,7 @@ template <typename T, int NB, bool JAC, int FINE>
 __global__ __launch_bounds__(kBlock) void cg_update_kernel(int n, T *__restrict__ x, T *__restrict__ r,
                                                            T *__restrict__ z, float *__restrict__ r32,
                                                            float *__restrict__ x32, const float *__restrict__ d32,
+                                                           double s0,
                                                            const T *__restrict__ p,
                                                            const T *__restrict__ q, const T *__restrict__ dinv,
                                                            CgScal *sc, const double *__restrict__ part_pq,
@@ -435,11 +436,11 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int n, T *__restrict_
                 acc[1] += (double)rv * (double)zz;
             } else {
                 // the V-cycle's first pre-sweep iterate x0 = D^{-1} r (in its precision)
-                if (z) z[o] = dinv[e / NB] * rv;
+                if (z) z[o] = (dinv[e / NB] * rv) * (T)s0;
                 if (r32) {
                     const float rf = (float)rv;
                     r32[o] = rf;
-                    if (x32) x32[o] = d32[e / NB] * rf;
+                    if (x32) x32[o] = (d32[e / NB] * rf) * (float)s0;
                 }
             }
         }
@@ -523,12 +524,13 @@ template <typename T, int NB> struct EResB {
     }
 };
 
-// restriction that also starts the next level's pre-sweep: y_i = sum,
-// x_i = dinv_i sum
+// restriction that also starts the next level's pre-smoothing: y_i = sum,
+// x_i = (dinv_i sum) s0 (s0 = 1 for l1-Jacobi, 1/theta for Chebyshev)
 template <typename T, int NB> struct EStoreX {
     T *y;
     const T *dinv;
     T *x;
+    T s0;
     struct P {
         T d;
     };
@@ -537,7 +539,77 @@ template <typename T, int NB> struct EStoreX {
     template <int NV> __device__ void operator()(int i, int c, T s, const P &pr, double (&)[NV]) const {
         const size_t o = (size_t)i * NB + c;
         y[o] = s;
-        x[o] = pr.d * s;
+        x[o] = (pr.d * s) * s0;
+    }
+};
+
+// Chebyshev smoothing (degree 2, l1 diagonal), second step from the first
+// iterate x1 = (dinv b) / theta: out_i = x1_i + (c1 x1_i + c2 dinv_i (b_i - (A x1)_i))
+template <typename T, int NB> struct EChebPre {
+    const T *b;
+    const T *dinv;
+    const T *x1;
+    T *out;
+    T c1, c2;
+    struct P {
+        T b, d, x;
+    };
+    __device__ void prep(int) {}
+    __device__ P load(int i, int c) const {
+        const size_t o = (size_t)i * NB + c;
+        return {b[o], dinv[i], x1[o]};
+    }
+    template <int NV> __device__ void operator()(int i, int c, T s, const P &pr, double (&)[NV]) const {
+        const T r = pr.d * (pr.b - s);
+        const T d = c1 * pr.x + c2 * r;
+        out[(size_t)i * NB + c] = pr.x + d;
+    }
+};
+
+// Chebyshev smoothing from an iterate y0, first step:
+// y1_i = y0_i + (dinv_i (b_i - (A y0)_i)) s0
+template <typename T, int NB> struct EChebPost1 {
+    const T *b;
+    const T *dinv;
+    const T *y0;
+    T *y1;
+    T s0;
+    struct P {
+        T b, d, y;
+    };
+    __device__ void prep(int) {}
+    __device__ P load(int i, int c) const {
+        const size_t o = (size_t)i * NB + c;
+        return {b[o], dinv[i], y0[o]};
+    }
+    template <int NV> __device__ void operator()(int i, int c, T s, const P &pr, double (&)[NV]) const {
+        y1[(size_t)i * NB + c] = pr.y + (pr.d * (pr.b - s)) * s0;
+    }
+};
+
+// second step: out_i = y1_i + (c1 (y1_i - y0_i) + c2 dinv_i (b_i - (A y1)_i));
+// optionally acc += b_i out_i
+template <typename T, int NB, bool DOT> struct EChebPost2 {
+    const T *b;
+    const T *dinv;
+    const T *y0;
+    const T *y1;
+    T *out;
+    T c1, c2;
+    struct P {
+        T b, d, y0, y1;
+    };
+    __device__ void prep(int) {}
+    __device__ P load(int i, int c) const {
+        const size_t o = (size_t)i * NB + c;
+        return {b[o], dinv[i], y0[o], y1[o]};
+    }
+    template <int NV> __device__ void operator()(int i, int c, T s, const P &pr, double (&acc)[NV]) const {
+        const T r = pr.d * (pr.b - s);
+        const T d = c1 * (pr.y1 - pr.y0) + c2 * r;
+        const T v = pr.y1 + d;
+        out[(size_t)i * NB + c] = v;
+        if constexpr (DOT) acc[0] += (double)pr.b * (double)v;
     }
 };
 
@@ -819,17 +891,18 @@ template <typename T, int NB, bool JAC> struct OpInit {
     float *r32;
     float *x32;
     const float *d32;
+    double s0;  // scale of the first smoothing iterate (1, or 1/theta for Chebyshev)
     __device__ void prep(int) {}
     template <int NV> __device__ void operator()(int i, int c, double (&acc)[NV]) const {
         const size_t o = (size_t)i * NB + c;
         const T v = b[o];
         r[o] = v;
         if constexpr (!JAC) {
-            if (z) z[o] = dinv[i] * v;
+            if (z) z[o] = (dinv[i] * v) * (T)s0;
             if (r32) {
                 const float rf = (float)v;
                 r32[o] = rf;
-                if (x32) x32[o] = d32[i] * rf;
+                if (x32) x32[o] = (d32[i] * rf) * (float)s0;
             }
         }
         x[o] = T(0);

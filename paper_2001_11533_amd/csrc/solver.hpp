@@ -15,6 +15,20 @@
 
 namespace amg {
 
+// Chebyshev smoothing of degree 2 with the l1 diagonal on the interval
+// [kChebLo, kChebHi] of the spectrum of D_l1^{-1} A (its top is at most 1 on
+// every level): first iterate from zero s0 dinv b, then steps
+// d = c1 d + c2 dinv (b - A x), x += d (Chebyshev acceleration).
+constexpr double kChebLo = 0.3, kChebHi = 1.0;
+struct ChebConst {
+    double s0, c1, c2;
+};
+inline ChebConst cheb_const() {
+    const double theta = (kChebHi + kChebLo) / 2, delta = (kChebHi - kChebLo) / 2, sigma = theta / delta;
+    const double rho0 = 1.0 / sigma, rho1 = 1.0 / (2.0 * sigma - rho0);
+    return {1.0 / theta, rho1 * rho0, 2.0 * rho1 / delta};
+}
+
 template <int NB> struct Solver {
     Ctx &c;
     hipStream_t s;
@@ -73,7 +87,8 @@ template <int NB> struct Solver {
     // r.r (and r.z) partials into buffer 1
     template <typename T, bool JAC>
     void cg_update(int n, T *x, T *r, T *z, const T *p, const T *q, const T *dinv, CgScal *sc, int outer,
-                   const int *stop, float *r32 = nullptr, float *x32 = nullptr, const float *d32 = nullptr) {
+                   const int *stop, float *r32 = nullptr, float *x32 = nullptr, const float *d32 = nullptr,
+                   double s0 = 1.0) {
         const int g = grid_rows((long)n * NB, kBlock, red_grid_max<NB>());
         Reducer<JAC ? 2 : 1, NB> red{c.part[1]};
         // alpha: every workgroup sums the p.q partials itself when they are few,
@@ -85,10 +100,10 @@ template <int NB> struct Solver {
         }
         c.pgrid[1] = g;
         if (n == c.N)
-            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 1>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, x32, d32, p, q, dinv,
+            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 1>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, x32, d32, s0, p, q, dinv,
                                sc, c.part[0], nblk_pq, outer, red, stop);
         else
-            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 0>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, x32, d32, p, q, dinv,
+            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 0>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, x32, d32, s0, p, q, dinv,
                                sc, c.part[0], nblk_pq, outer, red, stop);
     }
 
@@ -126,7 +141,13 @@ template <int NB> struct Solver {
     // buffer 2.  The first sweep's iterate x = D^{-1} b is written by whoever
     // produces b: the caller at level j (into the level's V-cycle x), the
     // restriction below it.
+    // scale of the first smoothing iterate written by the producers of b
+    double first_scale() const { return c.o.smoother == 1 ? cheb_const().s0 : 1.0; }
+
     template <typename T> void vcycle(int j, const T *b, T *z, bool dot, const int *stop) {
+        const bool cheb = c.o.smoother == 1;
+        const ChebConst cc = cheb_const();
+        const T s0 = (T)first_scale(), c1 = (T)cc.c1, c2 = (T)cc.c2;
         int Lc = c.L - 1;
         for (int l = j + 1; l < c.L - 1; ++l)
             if (c.lev[l].Ainv) {
@@ -137,11 +158,17 @@ template <int NB> struct Solver {
         for (int l = j; l < Lc; ++l) {
             Level &Lv = c.lev[l];
             VcWs<T> &v = vcws<T>(c.ws[l]);
-            spmv<T, 0>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x}, EResB<T, NB>{bl, v.r}, NoFin{}, stop);
+            if (cheb) {
+                spmv<T, 0>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x},
+                           EChebPre<T, NB>{bl, dl1inv<T>(Lv), v.x, v.t, c1, c2}, NoFin{}, stop);
+                spmv<T, 0>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.t}, EResB<T, NB>{bl, v.r}, NoFin{}, stop);
+            } else {
+                spmv<T, 0>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x}, EResB<T, NB>{bl, v.r}, NoFin{}, stop);
+            }
             VcWs<T> &vn = vcws<T>(c.ws[l + 1]);
             if (l + 1 < Lc)
                 spmv<T, 0>(Lv.St, avals<T>(Lv.St), GPlain<T, NB>{v.r},
-                           EStoreX<T, NB>{vn.b, dl1inv<T>(c.lev[l + 1]), vn.x}, NoFin{}, stop);
+                           EStoreX<T, NB>{vn.b, dl1inv<T>(c.lev[l + 1]), vn.x, s0}, NoFin{}, stop);
             else
                 spmv<T, 0>(Lv.St, avals<T>(Lv.St), GPlain<T, NB>{v.r}, EStore<T, NB>{vn.b}, NoFin{}, stop);
             T *bn = vn.b;
@@ -153,9 +180,22 @@ template <int NB> struct Solver {
             Level &Lv = c.lev[l];
             VcWs<T> &v = vcws<T>(c.ws[l]);
             const T *e = (l + 1 == Lc) ? vcws<T>(c.ws[Lc]).x : vcws<T>(c.ws[l + 1]).x2;
-            spmv<T, 0>(Lv.S, avals<T>(Lv.S), GPlain<T, NB>{e}, EAdd<T, NB>{v.x}, NoFin{}, stop);
             const T *bb = (l == j) ? b : v.b;
             T *out = (l == j) ? z : v.x2;
+            if (cheb) {
+                // the iterate is t; the first post step writes x, the second out
+                spmv<T, 0>(Lv.S, avals<T>(Lv.S), GPlain<T, NB>{e}, EAdd<T, NB>{v.t}, NoFin{}, stop);
+                spmv<T, 0>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.t},
+                           EChebPost1<T, NB>{bb, dl1inv<T>(Lv), v.t, v.x, s0}, NoFin{}, stop);
+                if (l == j && dot)
+                    spmv<T, 1>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x},
+                               EChebPost2<T, NB, true>{bb, dl1inv<T>(Lv), v.t, v.x, out, c1, c2}, NoFin{}, stop, 2);
+                else
+                    spmv<T, 0>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x},
+                               EChebPost2<T, NB, false>{bb, dl1inv<T>(Lv), v.t, v.x, out, c1, c2}, NoFin{}, stop);
+                continue;
+            }
+            spmv<T, 0>(Lv.S, avals<T>(Lv.S), GPlain<T, NB>{e}, EAdd<T, NB>{v.x}, NoFin{}, stop);
             if (l == j && dot)
                 spmv<T, 1>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x},
                            EPost<T, NB, true>{dl1inv<T>(Lv), bb, v.x, out}, NoFin{}, stop, 2);
@@ -225,7 +265,7 @@ template <int NB> struct Solver {
             spmv<T, 1>(A, vals, GZBP<T, NB, float>{z32, pold, w.sc}, ECgQ<T, NB, float>{z32, pold, pnew, w.q, w.sc},
                        NoFin{}, stop, 0);
             cg_update<T, false>(n, nullptr, w.r, nullptr, pnew, w.q, nullptr, w.sc, 0, stop, r32,
-                                vcws<float>(c.ws[j]).x, c.lev[j].dl1inv32);
+                                vcws<float>(c.ws[j]).x, c.lev[j].dl1inv32, first_scale());
             vcycle<float>(j, r32, z32, true, stop);
             hipLaunchKernelGGL((fin2_kernel<NB, FinUB<NB>>), dim3(1), dim3(kFinBlock), 0, s, c.part[1], c.pgrid[1],
                                c.part[2], c.pgrid[2], FinUB<NB>{w.sc}, stop);
@@ -233,7 +273,9 @@ template <int NB> struct Solver {
         }
         spmv<T, 1>(A, vals, GZBP<T, NB>{w.z, pold, w.sc}, ECgQ<T, NB>{w.z, pold, pnew, w.q, w.sc}, NoFin{}, stop, 0);
         if constexpr (JAC) cg_update<T, JAC>(n, nullptr, w.r, w.z, pnew, w.q, dinv, w.sc, 0, stop);
-        else cg_update<T, JAC>(n, nullptr, w.r, vcws<T>(c.ws[j]).x, pnew, w.q, dl1inv<T>(c.lev[j]), w.sc, 0, stop);
+        else
+            cg_update<T, JAC>(n, nullptr, w.r, vcws<T>(c.ws[j]).x, pnew, w.q, dl1inv<T>(c.lev[j]), w.sc, 0, stop,
+                              nullptr, nullptr, nullptr, first_scale());
         if constexpr (JAC) {
             finish<2>(1, FinUpd<NB, true>{w.sc}, stop);
         } else {
@@ -263,7 +305,7 @@ template <int NB> struct Solver {
             z0 = vcws<T>(c.ws[j]).x;
             d0 = dl1inv<T>(c.lev[j]);
         }
-        elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, w.p0, z0, d0, r32, x32, d32},
+        elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, w.p0, z0, d0, r32, x32, d32, first_scale()},
                           FinInit<NB, JAC>{w.sc, rtol, nlive, (void *)x}, nullptr);
         const bool graphs = c.o.use_graphs != 0;
         auto first_precond = [&] {

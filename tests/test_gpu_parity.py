@@ -25,7 +25,7 @@ def _need_gpu():
 
 
 ORACLE_KEYS = ("hess_levels", "max_coarse", "inner_rtol", "mass_rtol", "precond_inner_rtol", "precond", "dense_max", "dense_solve_max",
-               "inner32_rtol", "mixed_mode")
+               "inner32_rtol", "mixed_mode", "smoother")
 
 
 def make(name, n, nb_max=1, **opts):
@@ -158,6 +158,19 @@ def test_mixed_precision_solve(mode):
     assert rel(u, uo) < 1e-8
     um, _ = o.reduced_solve(yd, rtol=1e-8)
     assert rel(um, uo) < 1e-8
+    assert abs(info[0]["inner_iters_total"] - o.cnt.inner_iters) <= 0.2 * o.cnt.inner_iters + 5
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_chebyshev_smoother_solve(prec):
+    # the V-cycle with the degree-2 Chebyshev smoother: same solution as the
+    # oracle with the same smoother, and the same inner iteration counts
+    p, g, o = make("c3", 16, smoother=1, inner_precision=prec)
+    yd = p.yd[:, 0]
+    u, info = g.reduced_solve(cuda(yd), rtol=1e-10 if prec == 64 else 1e-8)
+    uo, _ = osolve.Oracle(o.h).reduced_solve(yd, rtol=1e-12)
+    assert rel(u, uo) < (1e-10 if prec == 64 else 1e-8)
+    o.reduced_solve(yd, rtol=1e-10 if prec == 64 else 1e-8)
     assert abs(info[0]["inner_iters_total"] - o.cnt.inner_iters) <= 0.2 * o.cnt.inner_iters + 5
 
 

@@ -37,6 +37,48 @@ def test_vcycle_is_symmetric_and_contracts():
     assert ev.min() > 0 and ev.max() < 2.0       # ||I - BA||_A < 1
 
 
+def test_chebyshev_smoother_is_the_scaled_chebyshev_polynomial():
+    # one pass from any x maps the error e to p(D^{-1} A) e with
+    # p(l) = T_2((theta - l) / delta) / T_2(theta / delta), T_2(z) = 2 z^2 - 1,
+    # theta, delta the centre and half-width of [CHEB_LO, CHEB_HI]
+    p, h = build("c1", 6, smoother=1)
+    o = solve.Oracle(h)
+    lev = h.levels[0]
+    A, d = lev.A.dense(), lev.dl1
+    rng = np.random.default_rng(5)
+    xt, x0 = rng.standard_normal(lev.n), rng.standard_normal(lev.n)
+    x1 = o.smooth(lev.A, d, A @ xt, x0)
+    s = 1.0 / np.sqrt(d)
+    lam, V = np.linalg.eigh(s[:, None] * A * s[None, :])     # D^{-1/2} A D^{-1/2}
+    assert lam.max() <= 1.0 + 1e-12                          # the l1 bound
+    th = (solve.CHEB_HI + solve.CHEB_LO) / 2
+    de = (solve.CHEB_HI - solve.CHEB_LO) / 2
+    T2 = lambda z: 2 * z * z - 1
+    pl = T2((th - lam) / de) / T2(th / de)
+    e0 = (x0 - xt) / s                                       # D^{1/2} e
+    e1 = s * (V @ (pl * (V.T @ e0)))
+    assert np.max(np.abs((x1 - xt) - e1)) <= 1e-12 * np.max(np.abs(x0 - xt))
+    # from zero it is the same polynomial applied to e = -x_true
+    z1 = o.smooth(lev.A, d, A @ xt, None)
+    ez = s * (V @ (pl * (V.T @ (-xt / s))))
+    assert np.max(np.abs((z1 - xt) - ez)) <= 1e-12 * np.max(np.abs(xt))
+
+
+def test_chebyshev_vcycle_symmetric_contracting_same_solution():
+    p, h = build("c2", 12, max_coarse=12, smoother=1)
+    o = solve.Oracle(h)
+    n = h.levels[0].n
+    B = dense.vcycle_matrix(lambda e: o.vcycle(0, e), n)
+    assert np.max(np.abs(B - B.T)) <= 1e-13 * np.max(np.abs(B))
+    ev = np.linalg.eigvals(B @ h.levels[0].A.dense()).real
+    assert ev.min() > 0 and ev.max() < 2.0
+    yd = p.yd[:, 0]
+    u1, _ = o.reduced_solve(yd, rtol=1e-10)
+    h.opts.smoother = 0
+    u0, _ = solve.Oracle(h).reduced_solve(yd, rtol=1e-10)
+    assert np.linalg.norm(u1 - u0) <= 1e-8 * np.linalg.norm(u0)
+
+
 @pytest.mark.parametrize("name,n", [("c1", 8), ("c3", 4)])
 def test_state_adjoint_hessian_against_dense(name, n):
     p, h = build(name, n, max_coarse=10, **tight())
