@@ -69,7 +69,7 @@ def cpu_baseline(p, gpu_outer_iters: int):
         bc = p.dirichlet.astype(bool)
         t0 = time.perf_counter()
         A0 = fem.dirichlet_stiffness(A, bc)
-        h = sa.build(A0, M, bc, sa.Opts(beta=p.beta))
+        h = sa.build(A0, M, bc, sa.Opts(beta=p.beta, smoother=1))  # the GPU step's configuration
         t_setup = time.perf_counter() - t0
         o = solve.Oracle(h)
         t0 = time.perf_counter()
