@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -29,19 +30,37 @@ struct Error {
     } while (0)
 
 // Every device allocation of a context goes through one arena so that a
-// failure anywhere in setup releases everything.  A released block is kept
-// and handed out again to a later request of at most its size (and at least
-// half of it): all work of a context runs in order on its one stream, so the
-// kernels that used the block are ahead of any that reuse it, and no hipFree
-// (which waits for the whole device) happens before the context ends.
+// failure anywhere in setup releases everything.  Requests up to a quarter of a
+// chunk are carved from large chunks (few hipMalloc calls, and few hipFree
+// calls when the context ends: each waits for the device); larger ones get
+// their own allocation.  A released block is kept and handed out again to a
+// later request of at most its size (and at least half of it): all work of a
+// context runs in order on its one stream, so the kernels that used the block
+// are ahead of any that reuse it.
 struct Arena {
     struct Blk {
         void *p;
         size_t bytes;
         bool live;
     };
-    std::vector<Blk> blks;
+    std::vector<Blk> blks;      // every block handed out
+    std::vector<void *> chunks; // what hipMalloc returned
+    char *cur = nullptr;
+    size_t cur_left = 0, next_chunk = size_t(8) << 20;
     size_t bytes = 0;
+    static constexpr size_t kMaxChunk = size_t(128) << 20;
+
+    void *dev_malloc(size_t b) {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(AMG_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+        }
+        chunks.push_back(p);
+        bytes += b;
+        return p;
+    }
     template <class T> T *alloc(size_t n) {
         if (n == 0) n = 1;
         const size_t want = (n * sizeof(T) + 255) & ~(size_t)255;
@@ -52,14 +71,21 @@ struct Arena {
             best->live = true;
             return static_cast<T *>(best->p);
         }
-        void *p = nullptr;
-        hipError_t e = hipMalloc(&p, want);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            fail(AMG_ERR_OOM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+        void *p;
+        if (want > kMaxChunk / 4) {
+            p = dev_malloc(want);
+        } else {
+            if (want > cur_left) {
+                const size_t c = std::max(next_chunk, want);
+                cur = static_cast<char *>(dev_malloc(c));
+                cur_left = c;
+                next_chunk = std::min(kMaxChunk, 2 * next_chunk);
+            }
+            p = cur;
+            cur += want;
+            cur_left -= want;
         }
         blks.push_back({p, want, true});
-        bytes += want;
         return static_cast<T *>(p);
     }
     void release(void *p) {
@@ -67,8 +93,11 @@ struct Arena {
             if (b.p == p) b.live = false;
     }
     void free_all() {
-        for (auto &b : blks) (void)hipFree(b.p);
+        for (void *p : chunks) (void)hipFree(p);
+        chunks.clear();
         blks.clear();
+        cur = nullptr;
+        cur_left = 0;
         bytes = 0;
     }
 };
