@@ -227,6 +227,16 @@ def _col(v):
     return np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1, 1))
 
 
+def ball_problem(n: int, alpha: float) -> Problem:
+    """The varying-coefficient setting of the paper's Section 5.6 on the n^3
+    Kuhn cube: kappa = alpha inside the ball of radius 1/4 about the centre and
+    1 outside, Dirichlet nodes only on the face z = 0 (homogeneous Neumann on
+    the others), y_d = 1, beta = 1."""
+    m = mesh3d(n)
+    face = (m.coords[:, 2] == 0.0).astype(np.uint8)
+    return Problem(f"ball{alpha:g}", m, kappa_ball(m, alpha), 1.0, np.ones((m.nverts, 1)), face)
+
+
 def config(name: str, n: int | None = None, nb: int | None = None) -> Problem:
     """The five workloads, optionally at a reduced grid size n (for tests).
 

@@ -1,0 +1,55 @@
+"""The varying-coefficient experiment of the paper's Section 5.6 (Table 7) on
+the synthetic cube: kappa = alpha in a ball, Dirichlet on z = 0 only, y_d = 1,
+beta = 1, plain CG against the multilevel preconditioner with a fixed number
+of Hessian levels (no fallback).  The properties the table shows: for mild
+contrast a few outer iterations with any number of levels, far fewer than plain
+CG; for high contrast only few levels give a definite preconditioner, and the
+loss of definiteness with more levels is detected and reported.  The table of
+counts is printed (run with -s)."""
+import pytest
+
+import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+INDEFINITE, NOCONV = -5, -4
+
+
+def run(p, ell):
+    import paper_2001_11533_amd as amg
+    from paper_2001_11533_amd import AmgError
+    rp, ci, va, vm = amg.assemble_p1(p.mesh.coords, p.mesh.elems, p.kappa)
+    kw = dict(precond=0) if ell == 0 else dict(hess_levels=ell, auto_levels=0)
+    g = amg.HessianSolver((rp, ci, va), (rp, ci, vm), p.dirichlet, beta=p.beta, smoother=1, inner_precision=32,
+                          outer_maxit=200, **kw)
+    try:
+        if ell > g.levels()[0]:
+            return None
+        u, info = g.reduced_solve(torch.tensor(p.yd[:, 0], device="cuda"), rtol=1e-8)
+        return info[0]["outer_iters"]
+    except AmgError as e:
+        return e.code
+    finally:
+        g.close()
+
+
+@pytest.mark.timeout(600)
+def test_ball_coefficient_table():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    n = 32
+    table = {}
+    for alpha in (1e-4, 1e-3, 1e-2, 1e-1, 1.0):
+        p = inputs.ball_problem(n, alpha)
+        table[alpha] = [run(p, ell) for ell in (0, 2, 3)]
+        print(f"{n}^3 alpha={alpha:g}: none {table[alpha][0]}, multilevel l=2 {table[alpha][1]}, "
+              f"l=3 {table[alpha][2]}", flush=True)
+    for alpha in (1e-2, 1e-1, 1.0):
+        plain, l2, l3 = table[alpha]
+        assert 0 < l2 <= 6 and 0 < l3 <= 6 and 5 * max(l2, l3) <= plain
+    plain, l2, l3 = table[1e-3]
+    assert 0 < l2 <= 15 and 4 * l2 <= plain
+    assert l3 == INDEFINITE or 0 < l3 <= 20
+    # high contrast: many levels lose definiteness, which is reported
+    assert table[1e-4][2] in (INDEFINITE, NOCONV)
