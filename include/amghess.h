@@ -80,8 +80,8 @@ typedef struct {
     uint64_t agg_seed;      /* seed of the aggregation priority hash */
     int32_t nu;             /* l1-Jacobi sweeps before and after the coarse correction (1) */
     double inner_rtol;      /* A-solves inside K and K^T (1e-10) */
-    double mass_rtol;       /* mass-matrix solves (1e-10) */
-    double precond_inner_rtol; /* A-solves inside the preconditioner's H_j (1e-10) */
+    double mass_rtol;       /* mass-matrix solves, all inside the preconditioner (1e-8, Section 5.3) */
+    double precond_inner_rtol; /* A-solves inside the preconditioner's H_j (1e-8, Section 5.3) */
     int32_t inner_maxit, mass_maxit, outer_maxit; /* 500, 500, 200 */
     int32_t inner_precision;/* 64, or 32: float32 V-cycles (see mixed_mode) */
     double inner32_rtol;    /* float32 CG tolerance per refinement step (1e-6) */

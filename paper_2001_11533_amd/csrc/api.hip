@@ -172,8 +172,8 @@ int amg_opts_default(amg_opts *o) {
     o->agg_seed = 0x200111533ull;
     o->nu = 1;
     o->inner_rtol = 1e-10;
-    o->mass_rtol = 1e-10;
-    o->precond_inner_rtol = 1e-10;
+    o->mass_rtol = 1e-8;
+    o->precond_inner_rtol = 1e-8;
     o->inner_maxit = 500;
     o->mass_maxit = 500;
     o->outer_maxit = 200;
