@@ -39,6 +39,7 @@ template <typename T> struct CgWs {
     CgScal *sc = nullptr;
     Mail *hmail = nullptr;  // host view of the mailbox the finalize kernels write
     int pred = 0;  // iteration count of the previous solve (poll schedule)
+    int fused = -1; // 1: each iteration's finalize runs in the next iteration's first kernel
     // captured graphs: first preconditioner application, iteration p0->p1, iteration p1->p0
     hipGraphExec_t g0 = nullptr, ga = nullptr, gb = nullptr;
 };

@@ -30,6 +30,7 @@ __device__ __forceinline__ long ceil_div_dev_l(long a, long b) { return (a + b -
 // per-column CG state kept in device memory
 struct ColScal {
     double rho, alpha, beta, bb, tol2, rr, pq, rz;
+    double rho_next;  // fused finalize: r.z of the latest residual, committed to rho by the update
     int conv, iters, bad, pad;
 };
 
@@ -189,6 +190,104 @@ __device__ void sum_partials(const double *__restrict__ partial, int nblk, doubl
     __syncthreads();
 }
 
+// Convergence test and beta of one CG column after an update (r.r = rr) and
+// the preconditioner (r.z = rz): the step of the finalize kernels, shared by
+// the fused form below.  Returns the new beta (0 when the column stops).
+__device__ __forceinline__ double cg_col_step(const ColScal &s, double rr, double rz, int &conv, int &bad) {
+    conv = s.conv;
+    bad = s.bad;
+    if (conv) return 0.0;
+    if (bad || rr <= s.tol2) {
+        conv = 1;
+        return 0.0;
+    }
+    if (!(rz > 0.0)) {
+        bad = 1;
+        conv = 1;
+        return 0.0;
+    }
+    return rz / s.rho;
+}
+
+// The finalize of a captured CG iteration folded into the first kernel of the
+// next one: every workgroup sums the partials of r.r (buffer p1, quantity 0)
+// and r.z (Jacobi: p1, quantity 1; else buffer p2) in the same fixed order,
+// so all reach the same beta and convergence decisions; workgroup 0 records
+// them (rho_next = r.z, committed to rho by the update kernel that follows,
+// so no workgroup here reads a value another one writes, conv and bad only
+// ever switch on), counts the iteration and publishes the mailbox.
+struct NoPro {
+    static constexpr bool active = false;
+};
+
+template <int NB, bool JAC> struct FusedFin {
+    static constexpr bool active = true;
+    CgScal *sc;
+    const double *p1;
+    int n1;
+    const double *p2;
+    int n2;
+};
+
+// Returns whether every column has stopped; beta[c] (in LDS) holds the new betas.
+template <int NB, bool JAC>
+__device__ bool fused_fin(const FusedFin<NB, JAC> &f, const double *&beta) {
+    __shared__ double t1[JAC ? 2 : 1][NB], t2[1][NB];
+    __shared__ double sb[NB];
+    __shared__ int sall;
+    sum_partials<JAC ? 2 : 1, NB>(f.p1, f.n1, t1);
+    if constexpr (!JAC) sum_partials<1, NB>(f.p2, f.n2, t2);
+    if (threadIdx.x == 0) {
+        int all = 1;
+        for (int c = 0; c < NB; ++c) {
+            ColScal &s = f.sc->s[c];
+            const double rr = t1[0][c], rz = JAC ? t1[1][c] : t2[0][c];
+            const int was = s.conv;
+            int conv, bad;
+            const double b = cg_col_step(s, rr, rz, conv, bad);
+            if (blockIdx.x == 0 && !was) {
+                s.iters += 1;
+                s.rr = rr;
+                s.rz = rz;
+                s.beta = b;
+                s.rho_next = rz;
+                s.bad = bad;
+                s.conv = conv;
+            }
+            sb[c] = b;
+            all &= conv;
+        }
+        sall = all;
+        if (blockIdx.x == 0) publish(f.sc, NB);
+    }
+    __syncthreads();
+    beta = sb;
+    return sall != 0;
+}
+
+// The same step as a finalize kernel (after the last update a CG is allowed).
+template <int NB, bool JAC> struct FinFusedTail {
+    CgScal *sc;
+    __device__ void step(const double (&rr)[NB], const double (&rz)[NB]) const {
+        for (int c = 0; c < NB; ++c) {
+            ColScal &s = sc->s[c];
+            if (s.conv) continue;
+            int conv, bad;
+            const double b = cg_col_step(s, rr[c], rz[c], conv, bad);
+            s.iters += 1;
+            s.rr = rr[c];
+            s.rz = rz[c];
+            s.beta = b;
+            s.rho_next = rz[c];
+            s.bad = bad;
+            s.conv = conv;
+        }
+        publish(sc, NB);
+    }
+    __device__ void operator()(double (&tot)[2][NB]) const { step(tot[0], tot[1]); }  // Jacobi
+    __device__ void operator()(double (&rr)[1][NB], double (&rz)[1][NB]) const { step(rr[0], rz[0]); }
+};
+
 // One workgroup: totals of the partials, then the finalize step on thread 0.
 template <int NV, int NB, class FIN>
 __global__ __launch_bounds__(kFinBlock) void fin_kernel(const double *__restrict__ partial, int nblk, FIN fin,
@@ -220,12 +319,12 @@ struct NoFin {
 // functor (what is written for row i); optional fused reductions.
 // FINE = 1 marks launches on the finest level (a separate instantiation, so that
 // profiles separate the fine-level kernels from the coarse-level ones).
-template <typename T, int NB, int NV, class GX, class EP, int FINE>
+template <typename T, int NB, int NV, class GX, class EP, int FINE, class PRO = NoPro>
 __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__restrict__ rp,
                                                       const int *__restrict__ ci,
                                                       const T *__restrict__ av, GX gx, EP ep, Geo geo,
                                                       Reducer<(NV > 0 ? NV : 1), NB> red,
-                                                      const int *__restrict__ stop) {
+                                                      const int *__restrict__ stop, PRO pro = PRO{}) {
     if (stop && *stop) return;
     constexpr int CV = spmv_cv<NB>(), NG = NB / CV;
     const int t = threadIdx.x;
@@ -243,6 +342,15 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__re
         gxv[v].prep(c0 + v);
         epv[v] = ep;
         epv[v].prep(c0 + v);
+    }
+    if constexpr (PRO::active) {  // the previous iteration's finalize, then this one
+        const double *fb;
+        if (fused_fin(pro, fb)) return;
+#pragma unroll
+        for (int v = 0; v < CV; ++v) {
+            gxv[v].set_beta(fb[c0 + v]);
+            epv[v].set_beta(fb[c0 + v]);
+        }
     }
     constexpr int NVA = NV > 0 ? NV : 1;
     double acc[CV][NVA];
@@ -297,11 +405,11 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__re
 // The same product over the sliced-ELL copy (single column): one wavefront
 // per slice of 64 rows, one lane per row; a lane issues the loads of up to 16
 // entries of its row at once, with no dependence on row pointers.
-template <typename T, int NV, class GX, class EP>
+template <typename T, int NV, class GX, class EP, class PRO = NoPro>
 __global__ __launch_bounds__(kBlock) void sell_kernel(int nrows, int nsl, const int *__restrict__ soff,
                                                       const int *__restrict__ ci, const T *__restrict__ av, GX gx,
                                                       EP ep, Reducer<(NV > 0 ? NV : 1), 1> red,
-                                                      const int *__restrict__ stop) {
+                                                      const int *__restrict__ stop, PRO pro = PRO{}) {
     if (stop && *stop) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int nblk = gridDim.x, b = xcd_block(blockIdx.x, nblk);
@@ -310,6 +418,12 @@ __global__ __launch_bounds__(kBlock) void sell_kernel(int nrows, int nsl, const 
     const int s0 = b * per, s1 = min(nsl, s0 + per);
     gx.prep(0);
     ep.prep(0);
+    if constexpr (PRO::active) {  // the previous iteration's finalize, then this one
+        const double *fb;
+        if (fused_fin(pro, fb)) return;
+        gx.set_beta(fb[0]);
+        ep.set_beta(fb[0]);
+    }
     constexpr int NVA = NV > 0 ? NV : 1;
     double acc[NVA];
 #pragma unroll
@@ -370,7 +484,7 @@ template <typename T, int NB, bool JAC, int FINE>
 __global__ __launch_bounds__(kBlock) void cg_update_kernel(int n, T *__restrict__ x, T *__restrict__ r,
                                                            T *__restrict__ z, float *__restrict__ r32,
                                                            float *__restrict__ x32, const float *__restrict__ d32,
-                                                           double s0,
+                                                           double s0, int fused,
                                                            const T *__restrict__ p,
                                                            const T *__restrict__ q, const T *__restrict__ dinv,
                                                            CgScal *sc, const double *__restrict__ part_pq,
@@ -397,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int n, T *__restrict_
         int live = !s.conv;
         if (live) {
             if (v > 0.0) {
-                a = s.rho / v;
+                a = (fused ? s.rho_next : s.rho) / v;
             } else {
                 live = 0;
                 if (blockIdx.x == 0) {
@@ -411,6 +525,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int n, T *__restrict_
         if (blockIdx.x == 0) {
             s.alpha = a;
             s.pq = v;
+            if (fused && !s.conv) s.rho = s.rho_next;
         }
     }
     __syncthreads();
@@ -462,6 +577,7 @@ template <typename T, int NB, typename TZ = T> struct GZBP {  // p_k = z_k + bet
     const CgScal *sc;
     T beta;
     __device__ void prep(int c) { beta = (T)sc->s[c].beta; }
+    __device__ void set_beta(double b) { beta = (T)b; }
     __device__ T operator()(int k, int c) const {
         return (T)z[(size_t)k * NB + c] + beta * pold[(size_t)k * NB + c];
     }
@@ -646,6 +762,7 @@ template <typename T, int NB, typename TZ = T> struct ECgQ {
         T z, po;
     };
     __device__ void prep(int c) { beta = (T)sc->s[c].beta; }
+    __device__ void set_beta(double b) { beta = (T)b; }
     __device__ P load(int i, int c) const {
         const size_t o = (size_t)i * NB + c;
         return {(T)z[o], pold[o]};
@@ -708,9 +825,11 @@ template <int NB> struct EResid {
 template <int NB> struct FinAlpha {  // alpha = rho / p.q on live columns
     CgScal *sc;
     int outer;  // 1: flag indefiniteness instead of treating it as breakdown
+    int fused;  // 1: rho is the rho_next of the fused finalize, committed here
     __device__ void operator()(double (&tot)[1][NB]) const {
         for (int c = 0; c < NB; ++c) {
             ColScal &s = sc->s[c];
+            if (fused && !s.conv) s.rho = s.rho_next;
             s.pq = tot[0][c];
             if (s.conv) {
                 s.alpha = 0.0;
@@ -845,6 +964,7 @@ template <int NB, bool JAC> struct FinInit {
     double rtol;
     int nlive;
     void *x;
+    int fused;  // the first fused finalize then gives beta = 0, rho_next = r.z and iteration 0
     __device__ void operator()(double (&tot)[JAC ? 2 : 1][NB]) const {
         sc->xptr = x;
         sc->nb = nlive;
@@ -863,6 +983,10 @@ template <int NB, bool JAC> struct FinInit {
             if constexpr (JAC) {
                 s.rz = tot[1][c];
                 s.rho = s.conv ? 1.0 : s.rz;
+            }
+            if (fused) {
+                s.rho = __builtin_huge_val();
+                s.iters = -1;
             }
             all &= s.conv;
         }

@@ -29,6 +29,9 @@ inline ChebConst cheb_const() {
     return {1.0 / theta, rho1 * rho0, 2.0 * rho1 / delta};
 }
 
+// partials a fused finalize may sum in every workgroup of the next kernel
+constexpr long kFusedPartials = 4096;
+
 template <int NB> struct Solver {
     Ctx &c;
     hipStream_t s;
@@ -43,8 +46,15 @@ template <int NB> struct Solver {
                                c.pgrid[pbuf], fin, stop);
     }
 
-    template <typename T, int NV, class GX, class EP, class FIN>
-    void spmv(const DCsr &A, const T *vals, GX gx, EP ep, FIN fin, const int *stop, int pbuf = 0) {
+    // workgroups of a reducing product with A (the partials it leaves)
+    int red_grid(const DCsr &A) const {
+        if (NB == 1 && A.sl_off) return grid_rows(A.nsl, kBlock / 64, red_grid_max<NB>());
+        return grid_rows(A.n, make_geo<NB>(A.nnz, A.n).rpb(), red_grid_max<NB>());
+    }
+
+    template <typename T, int NV, class GX, class EP, class FIN, class PRO = NoPro>
+    void spmv(const DCsr &A, const T *vals, GX gx, EP ep, FIN fin, const int *stop, int pbuf = 0,
+              PRO pro = PRO{}) {
         if constexpr (NB == 1) {
             const T *sv = nullptr;
             if constexpr (std::is_same_v<T, float>) sv = vals == A.v32 ? A.sl_v32 : nullptr;
@@ -53,8 +63,8 @@ template <int NB> struct Solver {
                 const int g = grid_rows(A.nsl, kBlock / 64, NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
                 Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
                 if (NV > 0) c.pgrid[pbuf] = g;
-                hipLaunchKernelGGL((sell_kernel<T, NV, GX, EP>), dim3(g), dim3(kBlock), 0, s, A.n, A.nsl, A.sl_off,
-                                   A.sl_ci, sv, gx, ep, red, stop);
+                hipLaunchKernelGGL((sell_kernel<T, NV, GX, EP, PRO>), dim3(g), dim3(kBlock), 0, s, A.n, A.nsl,
+                                   A.sl_off, A.sl_ci, sv, gx, ep, red, stop, pro);
                 finish<NV>(pbuf, fin, stop);
                 return;
             }
@@ -64,11 +74,11 @@ template <int NB> struct Solver {
         Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
         if (NV > 0) c.pgrid[pbuf] = g;
         if (A.n == c.N)
-            hipLaunchKernelGGL((spmv_kernel<T, NB, NV, GX, EP, 1>), dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci,
-                               vals, gx, ep, geo, red, stop);
+            hipLaunchKernelGGL((spmv_kernel<T, NB, NV, GX, EP, 1, PRO>), dim3(g), dim3(kBlock), 0, s, A.n, A.rp,
+                               A.ci, vals, gx, ep, geo, red, stop, pro);
         else
-            hipLaunchKernelGGL((spmv_kernel<T, NB, NV, GX, EP, 0>), dim3(g), dim3(kBlock), 0, s, A.n, A.rp, A.ci,
-                               vals, gx, ep, geo, red, stop);
+            hipLaunchKernelGGL((spmv_kernel<T, NB, NV, GX, EP, 0, PRO>), dim3(g), dim3(kBlock), 0, s, A.n, A.rp,
+                               A.ci, vals, gx, ep, geo, red, stop, pro);
         finish<NV>(pbuf, fin, stop);
     }
 
@@ -88,22 +98,22 @@ template <int NB> struct Solver {
     template <typename T, bool JAC>
     void cg_update(int n, T *x, T *r, T *z, const T *p, const T *q, const T *dinv, CgScal *sc, int outer,
                    const int *stop, float *r32 = nullptr, float *x32 = nullptr, const float *d32 = nullptr,
-                   double s0 = 1.0) {
+                   double s0 = 1.0, int fused = 0) {
         const int g = grid_rows((long)n * NB, kBlock, red_grid_max<NB>());
         Reducer<JAC ? 2 : 1, NB> red{c.part[1]};
         // alpha: every workgroup sums the p.q partials itself when they are few,
         // else one finalize kernel forms it first
         int nblk_pq = c.pgrid[0];
         if ((long)nblk_pq * NB > 2048) {
-            finish<1>(0, FinAlpha<NB>{sc, outer}, stop);
+            finish<1>(0, FinAlpha<NB>{sc, outer, fused}, stop);
             nblk_pq = 0;
         }
         c.pgrid[1] = g;
         if (n == c.N)
-            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 1>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, x32, d32, s0, p, q, dinv,
+            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 1>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, x32, d32, s0, fused, p, q, dinv,
                                sc, c.part[0], nblk_pq, outer, red, stop);
         else
-            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 0>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, x32, d32, s0, p, q, dinv,
+            hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 0>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, x32, d32, s0, fused, p, q, dinv,
                                sc, c.part[0], nblk_pq, outer, red, stop);
     }
 
@@ -259,30 +269,53 @@ template <int NB> struct Solver {
     void cg_iter(int j, const DCsr &A, const T *vals, const T *dinv, CgWs<T> &w, T *pold, T *pnew) {
         const int n = A.n;
         const int *stop = &w.sc->all_conv;
+        const int fused = w.fused;
+        const FusedFin<NB, JAC> pro{w.sc, c.part[1], c.pgrid[1], c.part[2], c.pgrid[2]};
+        // the first kernel: (fused: the previous finalize,) p = z + beta pold, q = A p, p.q partials
+        auto first = [&](auto gx, auto ep) {
+            if (fused) spmv<T, 1>(A, vals, gx, ep, NoFin{}, stop, 0, pro);
+            else spmv<T, 1>(A, vals, gx, ep, NoFin{}, stop, 0);
+        };
         if constexpr (MIX) {
             static_assert(std::is_same_v<T, double> && !JAC, "float32 preconditioning of the FP64 CG only");
             float *r32 = c.ws[j].b32, *z32 = c.ws[j].d32;
-            spmv<T, 1>(A, vals, GZBP<T, NB, float>{z32, pold, w.sc}, ECgQ<T, NB, float>{z32, pold, pnew, w.q, w.sc},
-                       NoFin{}, stop, 0);
+            first(GZBP<T, NB, float>{z32, pold, w.sc}, ECgQ<T, NB, float>{z32, pold, pnew, w.q, w.sc});
             cg_update<T, false>(n, nullptr, w.r, nullptr, pnew, w.q, nullptr, w.sc, 0, stop, r32,
-                                vcws<float>(c.ws[j]).x, c.lev[j].dl1inv32, first_scale());
+                                vcws<float>(c.ws[j]).x, c.lev[j].dl1inv32, first_scale(), fused);
             vcycle<float>(j, r32, z32, true, stop);
-            hipLaunchKernelGGL((fin2_kernel<NB, FinUB<NB>>), dim3(1), dim3(kFinBlock), 0, s, c.part[1], c.pgrid[1],
-                               c.part[2], c.pgrid[2], FinUB<NB>{w.sc}, stop);
+            if (!fused)
+                hipLaunchKernelGGL((fin2_kernel<NB, FinUB<NB>>), dim3(1), dim3(kFinBlock), 0, s, c.part[1],
+                                   c.pgrid[1], c.part[2], c.pgrid[2], FinUB<NB>{w.sc}, stop);
             return;
         }
-        spmv<T, 1>(A, vals, GZBP<T, NB>{w.z, pold, w.sc}, ECgQ<T, NB>{w.z, pold, pnew, w.q, w.sc}, NoFin{}, stop, 0);
-        if constexpr (JAC) cg_update<T, JAC>(n, nullptr, w.r, w.z, pnew, w.q, dinv, w.sc, 0, stop);
+        first(GZBP<T, NB>{w.z, pold, w.sc}, ECgQ<T, NB>{w.z, pold, pnew, w.q, w.sc});
+        if constexpr (JAC)
+            cg_update<T, JAC>(n, nullptr, w.r, w.z, pnew, w.q, dinv, w.sc, 0, stop, nullptr, nullptr, nullptr, 1.0,
+                              fused);
         else
             cg_update<T, JAC>(n, nullptr, w.r, vcws<T>(c.ws[j]).x, pnew, w.q, dl1inv<T>(c.lev[j]), w.sc, 0, stop,
-                              nullptr, nullptr, nullptr, first_scale());
+                              nullptr, nullptr, nullptr, first_scale(), fused);
         if constexpr (JAC) {
-            finish<2>(1, FinUpd<NB, true>{w.sc}, stop);
+            if (!fused) finish<2>(1, FinUpd<NB, true>{w.sc}, stop);
         } else {
             vcycle<T>(j, w.r, w.z, true, stop);
-            hipLaunchKernelGGL((fin2_kernel<NB, FinUB<NB>>), dim3(1), dim3(kFinBlock), 0, s, c.part[1], c.pgrid[1],
-                               c.part[2], c.pgrid[2], FinUB<NB>{w.sc}, stop);
+            if (!fused)
+                hipLaunchKernelGGL((fin2_kernel<NB, FinUB<NB>>), dim3(1), dim3(kFinBlock), 0, s, c.part[1],
+                                   c.pgrid[1], c.part[2], c.pgrid[2], FinUB<NB>{w.sc}, stop);
         }
+    }
+
+    // fused mode: the finalize of the last update when the iteration limit ends the loop
+    template <bool JAC> void fused_tail(CgWs<double> &w) { fused_tail_impl<JAC>(w.sc); }
+    template <bool JAC> void fused_tail(CgWs<float> &w) { fused_tail_impl<JAC>(w.sc); }
+    template <bool JAC> void fused_tail_impl(CgScal *sc) {
+        if constexpr (JAC)
+            hipLaunchKernelGGL((fin_kernel<2, NB, FinFusedTail<NB, true>>), dim3(1), dim3(kFinBlock), 0, s, c.part[1],
+                               c.pgrid[1], FinFusedTail<NB, true>{sc}, &sc->all_conv);
+        else
+            hipLaunchKernelGGL((fin2_kernel<NB, FinFusedTail<NB, false>>), dim3(1), dim3(kFinBlock), 0, s,
+                               c.part[1], c.pgrid[1], c.part[2], c.pgrid[2], FinFusedTail<NB, false>{sc},
+                               &sc->all_conv);
     }
 
     template <typename T, bool JAC, bool MIX = false>
@@ -305,13 +338,21 @@ template <int NB> struct Solver {
             z0 = vcws<T>(c.ws[j]).x;
             d0 = dl1inv<T>(c.lev[j]);
         }
+        if (w.fused < 0) {
+            // fold each finalize into the next iteration's first kernel when every
+            // workgroup can afford to sum the partials it needs
+            long q = (JAC ? 2L : 1L) * grid_rows((long)n * NB, kBlock, red_grid_max<NB>()) * NB;
+            if constexpr (!JAC) q += (long)red_grid(A) * NB;
+            w.fused = q <= kFusedPartials ? 1 : 0;
+        }
+        const int fused = w.fused;
         elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, w.p0, z0, d0, r32, x32, d32, first_scale()},
-                          FinInit<NB, JAC>{w.sc, rtol, nlive, (void *)x}, nullptr);
+                          FinInit<NB, JAC>{w.sc, rtol, nlive, (void *)x, fused}, nullptr, fused ? 1 : 0);
         const bool graphs = c.o.use_graphs != 0;
         auto first_precond = [&] {
             if constexpr (MIX) vcycle<float>(j, c.ws[j].b32, c.ws[j].d32, true, stop);
             else vcycle<T>(j, w.r, w.z, true, stop);
-            finish<1>(2, FinRho0<NB>{w.sc}, stop);
+            if (!fused) finish<1>(2, FinRho0<NB>{w.sc}, stop);
         };
         if (graphs && !w.ga) {
             if constexpr (!JAC) w.g0 = capture(first_precond);
@@ -329,13 +370,18 @@ template <int NB> struct Solver {
             else cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p0, w.p1);
             ++it;
         };
-        const int first = std::min(std::max(1, w.pred - 1), maxit);
+        // fused: the convergence of update k is decided in iteration k + 1
+        const int first = std::min(std::max(1, fused ? w.pred : w.pred - 1), maxit);
         while (it < first) step();
         post_flag(0);
         int cur = 0;
         bool done = false;
         while (!done) {
             if (it >= maxit) {
+                if (fused) {
+                    fused_tail<JAC>(w);
+                    post_flag(cur);
+                }
                 done = wait_flag(cur, w);
                 break;
             }
@@ -354,8 +400,8 @@ template <int NB> struct Solver {
         }
         if (m.bad)
             fail(AMG_ERR_NOCONV, std::string(JAC ? "mass" : "inner") + " CG breakdown at level " + std::to_string(j));
-        w.pred = m.iters;
-        return m.iters;
+        w.pred = std::max(0, m.iters);  // fused: -1 when every column stopped before the first update
+        return w.pred;
     }
 
     // ---------------- solves with A_j ----------------
