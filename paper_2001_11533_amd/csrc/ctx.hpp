@@ -74,7 +74,8 @@ struct Ctx {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
     std::vector<hipGraphExec_t> graphs; // every instantiated graph (freed with the context)
-    hipEvent_t poll_ev[2] = {nullptr, nullptr};
+    static constexpr int kPollRing = 4;
+    hipEvent_t poll_ev[kPollRing] = {nullptr, nullptr, nullptr, nullptr};
     amg_opts o{};
     Arena arena;
     int N = 0;

@@ -370,28 +370,36 @@ template <int NB> struct Solver {
             else cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p0, w.p1);
             ++it;
         };
-        // fused: the convergence of update k is decided in iteration k + 1
-        const int first = std::min(std::max(1, fused ? w.pred : w.pred - 1), maxit);
+        // The iterations the previous solve at this level needed (one more when
+        // fused: the convergence of update k is decided in iteration k + 1) go
+        // out at once; then the host keeps kAhead iterations in flight beyond
+        // the last one it has seen, reading the mailbox after an event.
+        constexpr int kAhead = 1, kRing = Ctx::kPollRing;
+        const int first = std::min(std::max(1, w.pred + (fused ? 1 : 0)), maxit);
         while (it < first) step();
         post_flag(0);
-        int cur = 0;
+        int posted = 1, seen = 0;
         bool done = false;
         while (!done) {
             if (it >= maxit) {
-                if (fused) {
-                    fused_tail<JAC>(w);
-                    post_flag(cur);
-                }
-                done = wait_flag(cur, w);
+                if (fused) fused_tail<JAC>(w);
+                post_flag(posted % kRing);
+                ++posted;
+                AMG_HIP(hipEventSynchronize(c.poll_ev[(posted - 1) % kRing]));
+                done = __atomic_load_n(&w.hmail->all_conv, __ATOMIC_ACQUIRE) != 0;
                 break;
             }
-            step();
-            post_flag(cur ^ 1);
-            done = wait_flag(cur, w);
-            cur ^= 1;
+            if (posted - seen < kAhead) {
+                step();
+                post_flag(posted % kRing);
+                ++posted;
+                continue;
+            }
+            done = wait_flag(seen % kRing, w);
+            ++seen;
         }
         // the last posted event covers every launch: the mailbox is final
-        AMG_HIP(hipEventSynchronize(c.poll_ev[cur]));
+        AMG_HIP(hipEventSynchronize(c.poll_ev[(posted - 1) % kRing]));
         const Mail &m = *w.hmail;
         if (!m.all_conv) {
             w.pred = it;
