@@ -211,6 +211,19 @@ int amg_copy_csr(amg_ctx *ctx, int level, int which, int32_t *rowptr, int32_t *c
 int amg_copy_dense(amg_ctx *ctx, int which, int32_t *n, double *out);
 /* Use l Hessian levels from now on (1 <= l <= L); rebuilds the dense H_{l-1}. */
 int amg_set_hess_levels(amg_ctx *ctx, int ell);
+
+/* ---- hierarchy quality (Section 4, eqs. ajnumerical and aj-tilde) ----
+ * a~_j = ||K_j - S_j K_{j+1} Pi_j||_2, the approximation number of the coarse
+ * spaces that governs the multilevel preconditioner (Pi_j = M_{u,j+1}^{-1}
+ * S_j^T M_{u,j}, the control projection with P_j = S_j), estimated as in the
+ * paper by the power method on E^T E: iters steps from v0, *a_tilde = the square
+ * root of the last Rayleigh quotient.  Each step costs two A-solves on levels
+ * level and level + 1 each (inner_rtol) and two mass solves on level + 1.
+ *   level: 0 <= level < L - 1.  v0: device FP64 [n_level], not all zero
+ *   (caller-owned, not modified).  iters >= 1.
+ * Errors: AMG_ERR_ARG for a bad level, null pointers or iters < 1; AMG_ERR_NOCONV
+ * from an inner solve. */
+int amg_hierarchy_quality(amg_ctx *ctx, int level, const double *v0, int iters, double *a_tilde);
 /* Text of the last error of ctx (or of the last failed amg_setup when ctx is NULL). */
 const char *amg_last_error(amg_ctx *ctx);
 

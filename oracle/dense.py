@@ -78,3 +78,20 @@ def rhs_practical(h: sa.Hierarchy, yd: np.ndarray) -> np.ndarray:
 def vcycle_matrix(apply, n: int) -> np.ndarray:
     """Columns of an operator applied to the unit vectors."""
     return np.stack([apply(e) for e in np.eye(n)], axis=1)
+
+
+def quality(h: sa.Hierarchy, j: int):
+    """(a_j, a~_j): a_j = ||M_y^{1/2} E M_u^{-1/2}||_2 (eq. ajnumerical, with
+    symmetric square roots of the level's mass matrices) and a~_j = ||E||_2
+    (eq. aj-tilde), E = K_j - S_j K_{j+1} Pi_j, both by singular values."""
+    o0, o1 = level_ops(h, j), level_ops(h, j + 1)
+    E = o0["K"] - h.levels[j].S.dense() @ o1["K"] @ projection(h, j)
+
+    def sqrt_spd(B):
+        w, V = np.linalg.eigh(0.5 * (B + B.T))
+        return (V * np.sqrt(np.clip(w, 0.0, None))) @ V.T
+
+    My_half = sqrt_spd(o0["My"])
+    Mu_half = sqrt_spd(o0["Mu"])
+    a = np.linalg.norm(My_half @ E @ np.linalg.inv(Mu_half), 2)
+    return float(a), float(np.linalg.norm(E, 2))

@@ -305,6 +305,29 @@ class Oracle:
     def precond(self, r: np.ndarray) -> np.ndarray:
         return self.B(0, r) if self.o.precond else r.copy()
 
+    # ---- hierarchy quality (Section 4: eqs. ajnumerical and aj-tilde) ----
+    def quality_apply(self, j: int, v: np.ndarray, transpose: bool) -> np.ndarray:
+        """E v or E^T v for E = K_j - S_j K_{j+1} Pi_j, Pi_j = M_{u,j+1}^{-1}
+        S_j^T M_{u,j} (the control projection with P_j = S_j)."""
+        h = self.h
+        lev = h.levels[j]
+        if not transpose:
+            pv = self.mass_solve(j + 1, lev.St.matvec(sa.mass_u(h, j, v)))
+            return self.state_solve(j, v) - lev.S.matvec(self.state_solve(j + 1, pv))
+        q = self.mass_solve(j + 1, self.adjoint_solve(j + 1, lev.St.matvec(v)))
+        return self.adjoint_solve(j, v) - sa.mass_u(h, j, lev.S.matvec(q))
+
+    def quality(self, j: int, v0: np.ndarray, iters: int) -> float:
+        """a~_j = ||E||_2 estimated, as the paper does, by the power method on
+        E^T E from v0: iters steps, the last Rayleigh quotient's square root."""
+        v = v0 / np.linalg.norm(v0)
+        lam = 0.0
+        for _ in range(iters):
+            y = self.quality_apply(j, self.quality_apply(j, v, False), True)
+            lam = float(v @ y)
+            v = y / np.linalg.norm(y)
+        return float(np.sqrt(max(lam, 0.0)))
+
     # ---- outer solve (Section 5.3) ----
     def reduced_solve(self, yd: np.ndarray, rtol: float = 1e-8):
         """Solve H_0 u = b for one desired state; on an indefinite

@@ -76,6 +76,7 @@ SIGNATURES = {
     "amg_set_hess_levels": (C.c_int, [P, C.c_int]),
     "amg_last_error": (C.c_char_p, [P]),
     "amg_time_kernel": (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_int, PD, PD]),
+    "amg_hierarchy_quality": (C.c_int, [P, C.c_int, C.c_void_p, C.c_int, PD]),
 }
 
 _lib = None

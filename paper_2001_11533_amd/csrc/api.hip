@@ -531,6 +531,68 @@ int amg_set_hess_levels(amg_ctx *ctx, int ell) {
     });
 }
 
+int amg_hierarchy_quality(amg_ctx *ctx, int level, const double *v0, int iters, double *a_tilde) {
+    if (!ctx || !v0 || !a_tilde || iters < 1 || level < 0 || level + 1 >= ctx->c.L) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    return guarded(&c, [&]() {
+        c.st.reset();
+        return dispatch_nb(c.nbp, [&](auto tag) {
+            constexpr int NB = decltype(tag)::value;
+            Solver<NB> S(c);
+            const int j = level, n = c.lev[j].n;
+            Level &L = c.lev[j];
+            LevelWs &w0 = c.ws[j], &w1 = c.ws[j + 1];
+            const double rtol = c.o.inner_rtol;
+            double *v = w0.ml_in, *y = w0.ml_z1, *d = c.dscratch;
+            auto restrict_ = [&](const double *x, double *out) {
+                S.template spmv<double, 0>(L.St, L.St.v, GPlain<double, NB>{x}, EStore<double, NB>{out}, NoFin{},
+                                           nullptr);
+            };
+            auto prolong = [&](const double *x, double *out) {
+                S.template spmv<double, 0>(L.S, L.S.v, GPlain<double, NB>{x}, EStore<double, NB>{out}, NoFin{},
+                                           nullptr);
+            };
+            auto dots = [&](const double *a, const double *b, const double *p, const double *q) {
+                S.template elem<2>(n, OpDot<NB>{a, b, p, q}, FinStore<NB>{d}, nullptr);
+                AMG_HIP(hipMemcpyAsync(c.hscr, d, 2 * NB * sizeof(double), hipMemcpyDeviceToHost, c.stream));
+                AMG_HIP(hipStreamSynchronize(c.stream));
+            };
+            // v = v0 / ||v0|| in column 0 (the other columns stay zero)
+            S.template elem<0>(n, OpPack<NB>{v, v0, 1}, NoFin{}, nullptr);
+            dots(v, v, v, v);
+            if (!(c.hscr[0] > 0.0)) fail(AMG_ERR_ARG, "v0 is zero");
+            S.template elem<0>(n, OpAxpby<NB>{v, v, nullptr, 1.0 / std::sqrt(c.hscr[0]), 0.0}, NoFin{}, nullptr);
+            double lam = 0.0;
+            for (int it = 0; it < iters; ++it) {
+                // E v = K_j v - S_j K_{j+1} M_{j+1}^{-1} S_j^T M_j v
+                S.mass_apply(j, 0, v, w0.ml_out, nullptr, nullptr);
+                restrict_(w0.ml_out, w1.ml_in);
+                S.mass_solve(j + 1, w1.ml_in, w1.ml_mup);
+                S.state_solve(j + 1, w1.ml_mup, w1.ml_out, rtol);
+                prolong(w1.ml_out, w0.ml_mup);
+                S.state_solve(j, v, w0.ml_mself, rtol);
+                S.template elem<0>(n, OpAxpby<NB>{w0.ml_t, w0.ml_mself, w0.ml_mup, 1.0, -1.0}, NoFin{}, nullptr);
+                // y = E^T (E v) = K_j^T e - M_j S_j M_{j+1}^{-1} K_{j+1}^T S_j^T e
+                restrict_(w0.ml_t, w1.ml_in);
+                S.adjoint_solve(j + 1, w1.ml_in, w1.ml_out, rtol);
+                S.mass_solve(j + 1, w1.ml_out, w1.ml_mup);
+                prolong(w1.ml_mup, w0.ml_mup);
+                S.mass_apply(j, 0, w0.ml_mup, w0.ml_out, nullptr, nullptr);
+                S.adjoint_solve(j, w0.ml_t, w0.ml_mself, rtol);
+                S.template elem<0>(n, OpAxpby<NB>{y, w0.ml_mself, w0.ml_out, 1.0, -1.0}, NoFin{}, nullptr);
+                // Rayleigh quotient and the next iterate
+                dots(v, y, y, y);
+                lam = c.hscr[0];
+                const double ny = std::sqrt(c.hscr[NB]);
+                if (!(ny > 0.0)) break;
+                S.template elem<0>(n, OpAxpby<NB>{v, y, nullptr, 1.0 / ny, 0.0}, NoFin{}, nullptr);
+            }
+            *a_tilde = std::sqrt(std::max(lam, 0.0));
+            return AMG_OK;
+        });
+    });
+}
+
 int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double *ms_avg, double *bytes) {
     if (int e = check_vec_call(ctx ? &ctx->c : nullptr, 0, nb)) return e;
     if (which < 0 || which > 2 || (prec != 32 && prec != 64) || reps < 1 || !ms_avg) return AMG_ERR_ARG;

@@ -247,6 +247,14 @@ class HessianSolver:
     def set_hess_levels(self, ell: int):
         check(lib().amg_set_hess_levels(self._h, ell), self._h)
 
+    def hierarchy_quality(self, level: int, v0, iters: int = 30) -> float:
+        """a~_j = ||K_j - S_j K_{j+1} Pi_j||_2 by the power method from v0 (a
+        float64 GPU tensor of n_level entries)."""
+        v, _ = self._vec(v0, self.level_n(level))
+        a = C.c_double()
+        check(lib().amg_hierarchy_quality(self._h, level, v.data_ptr(), iters, C.byref(a)), self._h)
+        return a.value
+
     def time_kernel(self, which: int, prec: int = 64, nb: int = 1, reps: int = 50):
         """(ms per launch, algorithmic bytes per launch) of 0: SpMV, 1: smoother sweep, 2: V-cycle."""
         ms, by = C.c_double(), C.c_double()

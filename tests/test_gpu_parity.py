@@ -278,3 +278,19 @@ def test_coarsest_hessian_by_loose_cg():
     u, info = g.reduced_solve(cuda(yd), rtol=1e-10)
     uo, it = o.reduced_solve(yd, rtol=1e-12)
     assert rel(u, uo) < 1e-8
+
+
+def test_hierarchy_quality_against_oracle():
+    # a~_j of Section 4 by the same power method from the same start vector on
+    # both sides, and near the largest singular value of the explicit E
+    p, g, o = make("c2", 24, max_coarse=12, **TIGHT)
+    rng = np.random.default_rng(29)
+    L = g.levels()[0]
+    assert L >= 3
+    for j in range(L - 1):
+        v0 = rng.standard_normal(p.mesh.nverts if j == 0 else g.level_n(j))
+        at_gpu = g.hierarchy_quality(j, cuda(v0), iters=40)
+        at_orc = o.quality(j, v0, 40)
+        assert abs(at_gpu - at_orc) <= 1e-8 * at_orc
+        a, at = odense.quality(o.h, j)
+        assert at_orc <= at * (1 + 1e-9) and at_orc >= 0.99 * at

@@ -293,3 +293,25 @@ def test_exact_small_coarse_solves_do_not_change_the_solution():
     u1, _ = solve.Oracle(h1).reduced_solve(yd, rtol=1e-11)
     u0, _ = solve.Oracle(h0).reduced_solve(yd, rtol=1e-11)
     assert np.linalg.norm(u1 - u0) <= 1e-9 * np.linalg.norm(u0)
+
+
+def test_hierarchy_quality_power_method_and_ajnumerical():
+    # Section 4: a~_j = ||K_j - S_j K_{j+1} Pi_j||_2 by the power method equals
+    # the largest singular value of the explicit E, and approximates
+    # a_j = ||M_y^{1/2} E M_u^{-1/2}||_2 up to the mass matrices' spectral
+    # scale (the paper's argument for using a~_j): the ratio a_j / a~_j lies in
+    # [sqrt(lmin(M_y)) / sqrt(lmax(M_u)), sqrt(lmax(M_y)) / sqrt(lmin(M_u))]
+    p, h = build("c2", 16, max_coarse=12, **tight())
+    assert h.L >= 3
+    o = solve.Oracle(h)
+    rng = np.random.default_rng(23)
+    for j in range(h.L - 1):
+        a, at = dense.quality(h, j)
+        est = o.quality(j, rng.standard_normal(h.levels[j].n), 300)
+        assert abs(est - at) <= 1e-6 * at
+        ops = dense.level_ops(h, j)
+        ly = np.linalg.eigvalsh(ops["My"])
+        lu = np.linalg.eigvalsh(ops["Mu"])
+        lo = np.sqrt(max(ly.min(), 0.0) / lu.max())
+        hi = np.sqrt(ly.max() / lu.min())
+        assert lo * at * (1 - 1e-9) <= a <= hi * at * (1 + 1e-9)
