@@ -151,6 +151,11 @@ def main():
     kern_ms, kern_bytes = s.time_kernel(1, prec=32, nb=1, reps=200)
     vc_ms, vc_bytes = s.time_kernel(2, prec=32, nb=1, reps=50)
     vc64_ms = vc64_bytes = None
+    # the hierarchy's approximation numbers a~_j (Section 4), power method from a seeded vector
+    gen = torch.Generator(device="cpu").manual_seed(31)
+    quality = [s.hierarchy_quality(j, torch.randn(sizes[j][0], generator=gen, dtype=torch.float64).to(dev), 20)
+               for j in range(L - 1)]
+    log(f"[bench] a~_j: {', '.join(f'{a:.3e}' for a in quality)}")
     s.close()
 
     # ---- plain FP64 path on the same input ----
@@ -252,6 +257,7 @@ def main():
         "fp32_refinement": {"solve_ms": ref_solve_ms, "outer_iters": infor[0]["outer_iters"],
                             "refine_steps": infor[0]["refine_steps"], "err_vs_fp64": err_refine_vs_fp64},
         "multilevel_vs": variants,
+        "hierarchy_quality_a_tilde": quality,
         "batch16": {"solve_ms": batch_solve_ms, "ms_per_state": batch_solve_ms / 16,
                     "outer_iters": max(i["outer_iters"] for i in infob)},
         "vcycle": {"f32_ms": vc_ms, "f32_GBps_alg": vc_bytes / (vc_ms * 1e-3) / 1e9,
