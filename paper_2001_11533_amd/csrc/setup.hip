@@ -36,6 +36,22 @@ namespace {
 constexpr int kHS = 2048;        // LDS hash slots per wavefront in the sparse product
 constexpr int kMaxRowOut = 1024; // output columns per row at most
 
+// Atomics from many wavefronts on one word are serialised (roughly 10 ns per
+// wavefront instruction), so reductions into a single word combine within the
+// wavefront first, and a maximum is only sent when it raises the stored one
+// (the stored value only grows, so a stale read never skips a needed update).
+__device__ __forceinline__ int wave_max(int v) {
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return v;
+}
+__device__ __forceinline__ int wave_sum(int v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+template <class T> __device__ __forceinline__ void raise_max(T *dst, T v) {
+    if (v > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(dst, v);
+}
+
 __global__ void k_check_sym(int n, const int *rp, const int *ci, const double *v, int *bad) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         for (int p = rp[i]; p < rp[i + 1]; ++p) {
@@ -272,13 +288,16 @@ __global__ void k_mis_r1(int n, const int *srp, const int *sci, const int8_t *st
 }
 
 __global__ void k_mis_r2(int n, const int *srp, const int *sci, const uint8_t *r1, int8_t *st, int *undec) {
+    int left = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         if (st[i] != UNDEC) continue;
         bool any = r1[i];
         for (int p = srp[i]; p < srp[i + 1] && !any; ++p) any = r1[sci[p]];
         if (any) st[i] = OUT;
-        else atomicAdd(undec, 1);
+        else ++left;
     }
+    left = wave_sum(left);
+    if (threadIdx.x % 64 == 0 && left) atomicAdd(undec, left);
 }
 
 __global__ void k_root_flags(int n, const int8_t *st, uint8_t *root, int *cnt) {
@@ -343,11 +362,15 @@ __global__ void k_phase3(int n, const int *srp, const int *sci, const double *sa
 
 __global__ void k_rho(int n, const double *dl1, const double *d, const uint8_t *mask,
                       unsigned long long *maxbits) {
+    // r > 0: the order of the bit patterns is the order of the values
+    unsigned long long m = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         if (mask && mask[i]) continue;
         const double r = dl1[i] / d[i];
-        atomicMax(maxbits, (unsigned long long)__double_as_longlong(r));  // r > 0: bit order = value order
+        m = max(m, (unsigned long long)__double_as_longlong(r));
     }
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned long long)__shfl_xor(m, off));
+    if (threadIdx.x % 64 == 0 && m) raise_max(maxbits, m);
 }
 
 // tentative prolongator: one unit entry per non-Dirichlet row
@@ -472,33 +495,64 @@ __device__ __forceinline__ void hs_insert_row(int *tab, const int *bci, int qb, 
     }
 }
 
-// Symbolic pass, W wavefronts per row of A sharing one LDS hash: output
-// columns per row; maxes[0] and maxes[1] receive the largest output row and
-// the longest row of B that is referenced.
-template <int W>
+// Symbolic pass, W wavefronts per row of A sharing one LDS hash of HS slots:
+// output columns per row; maxes[0] and maxes[1] receive the largest output row
+// and the longest row of B that is referenced.  With HS < kHS (first tier) a
+// row whose outputs do not fit (or nearly fill) half the table gets cnt = -1 and maxes[2] = 1;
+// the second tier (recount, HS = kHS) then counts only those rows.
+template <int HS>
+__device__ __forceinline__ void hs_insert_row_capped(int *tab, const int *bci, int qb, int qe, int *ucount,
+                                                     int *full) {
+    for (int q0 = qb; q0 < qe; q0 += 8) {
+        int key[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) key[i] = q0 + i < qe ? bci[q0 + i] : -1;
+        // over the tier's capacity (checked per batch of 8): stop filling
+        if (__hip_atomic_load(ucount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= HS / 2 - 8) {
+            *full = 1;
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (key[i] >= 0) hs_insert<HS>(tab, key[i], ucount, full);
+    }
+}
+
+template <int W, int HS>
 __global__ __launch_bounds__(64 * W) void k_spgemm_count(int n, const int *arp, const int *aci, const int *brp,
-                                                         const int *bci, int *cnt, int *ovf, int *maxes) {
+                                                         const int *bci, int *cnt, int *ovf, int *maxes,
+                                                         int recount) {
     constexpr int NT = 64 * W;
-    __shared__ int tab[kHS];
-    __shared__ int uc;
+    __shared__ int tab[HS];
+    __shared__ int uc, full;
     __shared__ int red[2][W];
     const int t = threadIdx.x;
     int umax = 0, bmax = 0;
     for (int row = blockIdx.x; row < n; row += gridDim.x) {
-        for (int s = t; s < kHS; s += NT) tab[s] = -1;
-        if (t == 0) uc = 0;
+        if (recount && cnt[row] >= 0) continue;  // counted by the first tier (uniform per workgroup)
+        for (int s = t; s < HS; s += NT) tab[s] = -1;
+        if (t == 0) {
+            uc = 0;
+            full = 0;
+        }
         __syncthreads();
         for (int p = arp[row] + t; p < arp[row + 1]; p += NT) {
             const int k = aci[p];
             const int qb = brp[k], qe = brp[k + 1];
             bmax = max(bmax, qe - qb);
-            hs_insert_row<kHS>(tab, bci, qb, qe, &uc, ovf);
+            if (HS < kHS) hs_insert_row_capped<HS>(tab, bci, qb, qe, &uc, &full);
+            else hs_insert_row<HS>(tab, bci, qb, qe, &uc, ovf);
         }
         __syncthreads();
         if (t == 0) {
-            cnt[row] = uc;
-            umax = max(umax, uc);
-            if (uc > kMaxRowOut) atomicOr(ovf, 1);
+            if (HS < kHS && (full || uc > HS / 2)) {
+                cnt[row] = -1;
+                maxes[2] = 1;
+            } else {
+                cnt[row] = uc;
+                umax = max(umax, uc);
+                if (uc > kMaxRowOut) atomicOr(ovf, 1);
+            }
         }
         __syncthreads();
     }
@@ -516,8 +570,8 @@ __global__ __launch_bounds__(64 * W) void k_spgemm_count(int n, const int *arp, 
             umax = max(umax, red[0][w]);
             bmax = max(bmax, red[1][w]);
         }
-        atomicMax(&maxes[0], umax);
-        atomicMax(&maxes[1], bmax);
+        raise_max(&maxes[0], umax);
+        raise_max(&maxes[1], bmax);
     }
 }
 
@@ -648,6 +702,200 @@ __global__ __launch_bounds__(64 * W) void k_spgemm_fill(int n, int G, const int 
         __syncthreads();
         for (int e = t; e < u; e += NT) cv[cs + e] = acc[e];
         __syncthreads();
+    }
+}
+
+// The same two passes for many short rows: a workgroup of kBlock threads
+// holds kBlock / LPR groups of LPR lanes, each group on its own row with its
+// own LDS hash of HS slots, so that many rows (and their chains of dependent
+// loads) are in flight per CU.  A group's lanes lie in one wavefront, whose LDS
+// accesses take effect in program order: the phases of a row are separated by
+// wavefront syncs, not workgroup barriers, and the groups run independently.
+//
+// Symbolic pass: a row whose outputs do not fit (or nearly fill) HS / 2 gets cnt = -1 and
+// maxes[2] = 1, and is counted again by k_spgemm_count with kHS slots.
+template <int LPR, int HS>
+__global__ __launch_bounds__(kBlock) void k_spgemm_count_sub(int n, const int *arp, const int *aci, const int *brp,
+                                                             const int *bci, int *cnt, int *maxes) {
+    constexpr int NG = kBlock / LPR;
+    __shared__ int tab[NG][HS];
+    __shared__ int uc[NG], full[NG];
+    const int g = threadIdx.x / LPR, gl = threadIdx.x % LPR;
+    int *tb = tab[g];
+    int umax = 0, bmax = 0;
+    for (int row = blockIdx.x * NG + g; row < n; row += gridDim.x * NG) {
+        for (int s = gl; s < HS; s += LPR) tb[s] = -1;
+        if (gl == 0) {
+            uc[g] = 0;
+            full[g] = 0;
+        }
+        __syncwarp();
+        const int a1 = arp[row + 1];
+        for (int p = arp[row] + gl; p < a1; p += LPR) {
+            const int k = aci[p];
+            const int qb = brp[k], qe = brp[k + 1];
+            bmax = max(bmax, qe - qb);
+            hs_insert_row_capped<HS>(tb, bci, qb, qe, &uc[g], &full[g]);
+        }
+        __syncwarp();
+        if (gl == 0) {
+            const int u = uc[g];
+            if (full[g] || u > HS / 2) {
+                cnt[row] = -1;
+                maxes[2] = 1;  // a plain store: every writer stores 1
+            } else {
+                cnt[row] = u;
+                umax = max(umax, u);
+            }
+        }
+        __syncwarp();
+    }
+    __shared__ int red[2][kBlock / 64];
+    umax = wave_max(umax);
+    bmax = wave_max(bmax);
+    if (threadIdx.x % 64 == 0) {
+        red[0][threadIdx.x / 64] = umax;
+        red[1][threadIdx.x / 64] = bmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) {
+            umax = max(umax, red[0][w]);
+            bmax = max(bmax, red[1][w]);
+        }
+        raise_max(&maxes[0], umax);
+        raise_max(&maxes[1], bmax);
+    }
+}
+
+// Numeric pass (HS / 2 >= every output count): the group inserts and ranks the
+// row's columns as k_spgemm_fill does, then walks the stored A[i,k] in
+// ascending k, LPR entries of the A row loaded at a time (one per lane) and
+// handed out by shuffles.  A step gives GS = LPR / BL consecutive k to GS
+// subgroups of BL lanes, one lane per entry of the row of B (a longer row
+// takes further rounds), with the loads of the next step issued first; the
+// subgroups then add their products one after another.  For one k the
+// products go to distinct outputs, so every output entry receives its
+// products strictly in ascending k: the rounded sums of a sequential loop.
+template <int LPR, int HS, int BL>
+__global__ __launch_bounds__(kBlock) void k_spgemm_fill_sub(int n, const int *arp, const int *aci,
+                                                            const double *av, const int *brp, const int *bci,
+                                                            const double *bv, const int *crp, int *cci, double *cv,
+                                                            int *ovf) {
+    constexpr int NG = kBlock / LPR, GS = LPR / BL;
+    __shared__ int tab[NG][HS];
+    __shared__ int pos[NG][HS];
+    __shared__ int lst[NG][HS / 2];
+    __shared__ double acc[NG][HS / 2];
+    __shared__ int uc[NG], uc2[NG];
+    const int g = threadIdx.x / LPR, gl = threadIdx.x % LPR, sg = gl / BL, sl = gl % BL;
+    int *tb = tab[g], *ps = pos[g], *ls = lst[g];
+    double *ac = acc[g];
+    for (int row = blockIdx.x * NG + g; row < n; row += gridDim.x * NG) {
+        for (int s = gl; s < HS; s += LPR) tb[s] = -1;
+        if (gl == 0) {
+            uc[g] = 0;
+            uc2[g] = 0;
+        }
+        __syncwarp();
+        const int a0 = arp[row], a1 = arp[row + 1];
+        for (int p = a0 + gl; p < a1; p += LPR) {
+            const int k = aci[p];
+            hs_insert_row<HS>(tb, bci, brp[k], brp[k + 1], &uc[g], ovf);
+        }
+        __syncwarp();
+        const int u = uc[g];
+        if (u > HS / 2) {  // the host sized HS from the symbolic pass: cannot happen
+            if (gl == 0) atomicOr(ovf, 2);
+            __syncwarp();
+            continue;
+        }
+        for (int s = gl; s < HS; s += LPR) {
+            const int key = tb[s];
+            if (key >= 0) ls[atomicAdd(&uc2[g], 1)] = key;
+        }
+        __syncwarp();
+        const int cs = crp[row];
+        for (int s = gl; s < HS; s += LPR) {
+            const int key = tb[s];
+            if (key < 0) continue;
+            int rank = 0;
+            for (int f = 0; f < u; ++f) rank += ls[f] < key;
+            ps[s] = rank;
+            cci[cs + rank] = key;
+            ac[rank] = 0.0;
+        }
+        __syncwarp();
+        for (int c0 = a0; c0 < a1; c0 += LPR) {
+            const int cn = min(LPR, a1 - c0);
+            int mb = 0, me = 0;
+            double ma = 0.0;
+            if (gl < cn) {
+                const int k = aci[c0 + gl];
+                ma = av[c0 + gl];
+                mb = brp[k];
+                me = brp[k + 1];
+            }
+            const int nst = (cn + GS - 1) / GS;
+            // entry e * GS + sg of the chunk for step e (every lane of the group takes part)
+            int qb, qe;
+            double a;
+            auto take = [&](int e) {
+                const int src = e * GS + sg;
+                qb = __shfl(mb, src, LPR);
+                qe = __shfl(me, src, LPR);
+                a = __shfl(ma, src, LPR);
+                if (src >= cn) qe = qb;
+            };
+            take(0);
+            int nkey = -1;
+            double nval = 0.0;
+            if (qb + sl < qe) {
+                nkey = bci[qb + sl];
+                nval = bv[qb + sl];
+            }
+            for (int e = 0; e < nst; ++e) {
+                const int key = nkey, cb = qb, ce = qe;
+                const double val = nval, ca = a;
+                nkey = -1;
+                if (e + 1 < nst) {
+                    take(e + 1);
+                    if (qb + sl < qe) {
+                        nkey = bci[qb + sl];
+                        nval = bv[qb + sl];
+                    }
+                }
+                int r = -1;
+                double prod = 0.0;
+                if (key >= 0) {
+                    const int slot = hs_find<HS>(tb, key);
+                    if (slot < 0) {  // cannot happen: every key was inserted above
+                        atomicOr(ovf, 2);
+                    } else {
+                        r = ps[slot];
+                        prod = ca * val;
+                    }
+                }
+                for (int t2 = 0; t2 < GS; ++t2) {
+                    if (sg == t2) {
+                        if (r >= 0) ac[r] = ac[r] + prod;
+                        for (int q = cb + BL + sl; q < ce; q += BL) {  // rows of B longer than BL
+                            const int slot = hs_find<HS>(tb, bci[q]);
+                            if (slot < 0) {
+                                atomicOr(ovf, 2);
+                                continue;
+                            }
+                            const int r2 = ps[slot];
+                            const double prod2 = ca * bv[q];
+                            ac[r2] = ac[r2] + prod2;
+                        }
+                    }
+                    __syncwarp();
+                }
+            }
+        }
+        for (int e = gl; e < u; e += LPR) cv[cs + e] = ac[e];
+        __syncwarp();
     }
 }
 
@@ -1097,42 +1345,96 @@ struct Setup {
         int *cnt = c.arena.alloc<int>(A.n + 1);
         C.rp = c.arena.alloc<int>(A.n + 1);
         zero(c.iscratch + 4, sizeof(int));
-        zero(c.iscratch + 10, 2 * sizeof(int));
-        // one wavefront per row, or four when the rows are too few to fill the chip
+        zero(c.iscratch + 10, 3 * sizeof(int));
+        // rows too few to fill the chip: four wavefronts per row; otherwise
+        // groups of 16, 32 or 64 lanes per row, from the mean row length of A
         const bool wide = A.n < 8192;
-        const int NT = wide ? 256 : 64;
         const int gr = std::max(1, std::min(A.n, 32768));
-        if (wide)
-            hipLaunchKernelGGL(k_spgemm_count<4>, dim3(gr), dim3(256), 0, s, A.n, A.rp, A.ci, B.rp, B.ci, cnt,
-                               c.iscratch + 4, c.iscratch + 10);
-        else
-            hipLaunchKernelGGL(k_spgemm_count<1>, dim3(gr), dim3(64), 0, s, A.n, A.rp, A.ci, B.rp, B.ci, cnt,
-                               c.iscratch + 4, c.iscratch + 10);
+        const long mean = ceil_div(A.nnz, std::max(1, A.n));
+        const int lpr = mean <= 16 ? 16 : mean <= 32 ? 32 : 64;
+        const int grs = std::max(1, std::min(ceil_div(A.n, kBlock / lpr), 4096));
+        auto count = [&](auto kern, int recount) {
+            hipLaunchKernelGGL(kern, dim3(gr), dim3(wide ? 256 : 64), 0, s, A.n, A.rp, A.ci, B.rp, B.ci, cnt,
+                               c.iscratch + 4, c.iscratch + 10, recount);
+        };
+        auto count_sub = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(grs), dim3(kBlock), 0, s, A.n, A.rp, A.ci, B.rp, B.ci, cnt,
+                               c.iscratch + 10);
+        };
+        // first tier: small tables; rows that overflow half of one are counted
+        // again with kHS slots
+        if (wide) count(k_spgemm_count<4, 512>, 0);
+        else if (lpr == 16) count_sub(k_spgemm_count_sub<16, 128>);
+        else if (lpr == 32) count_sub(k_spgemm_count_sub<32, 256>);
+        else count_sub(k_spgemm_count_sub<64, 512>);
         check_kernels();
-        AMG_HIP(hipMemcpyAsync(c.hiscr, c.iscratch + 4, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipMemcpyAsync(c.hiscr, c.iscratch + 4, 9 * sizeof(int), hipMemcpyDeviceToHost, s));
         AMG_HIP(hipStreamSynchronize(s));
+        if (c.hiscr[8]) {
+            if (wide) count(k_spgemm_count<4, kHS>, 1);
+            else count(k_spgemm_count<1, kHS>, 1);
+            check_kernels();
+            AMG_HIP(hipMemcpyAsync(c.hiscr, c.iscratch + 4, 9 * sizeof(int), hipMemcpyDeviceToHost, s));
+            AMG_HIP(hipStreamSynchronize(s));
+        }
         if (c.hiscr[0])
             fail(AMG_ERR_CAPACITY, "sparse product row exceeds " + std::to_string(kMaxRowOut) + " columns");
         const int umax = c.hiscr[6], bmax = c.hiscr[7];
         C.nnz = scan(cnt, C.rp, A.n);
         C.ci = c.arena.alloc<int>(C.nnz);
         C.v = c.arena.alloc<double>(C.nnz);
-        // G rows of B per step when every row of B fits NT / G threads (groups of 8 at least)
-        int G = 1;
-        while (2 * G <= NT / 8 && NT / (2 * G) >= bmax) G *= 2;
-        auto fill = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3(gr), dim3(NT), 0, s, A.n, G, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci,
-                               C.v, c.iscratch + kFlagFill);
-        };
         if (wide) {
+            // G rows of B per step when every row of B fits 256 / G threads (groups of 8 at least)
+            int G = 1;
+            while (2 * G <= 256 / 8 && 256 / (2 * G) >= bmax) G *= 2;
+            auto fill = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(gr), dim3(256), 0, s, A.n, G, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp,
+                                   C.ci, C.v, c.iscratch + kFlagFill);
+            };
             if (umax <= 128) fill(k_spgemm_fill<256, 4>);
             else if (umax <= 256) fill(k_spgemm_fill<512, 4>);
             else if (umax <= 512) fill(k_spgemm_fill<1024, 4>);
             else fill(k_spgemm_fill<2048, 4>);
+        } else if (umax <= 256) {
+            // BL lanes per row of B (a power of two from 8 to 64); at least 16
+            // lanes per row of A, 32 with the largest tables (LDS per workgroup
+            // 14 HS kBlock / LPR bytes, at most 56 KiB)
+            const int bl = bmax <= 8 ? 8 : bmax <= 16 ? 16 : bmax <= 32 ? 32 : 64;
+            const int hs = umax <= 32 ? 64 : umax <= 64 ? 128 : umax <= 128 ? 256 : 512;
+            const int fl = std::max(hs == 512 ? 32 : 16, bl);
+            const int grf = std::max(1, std::min(ceil_div(A.n, kBlock / fl), 16384));
+            auto fill = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(grf), dim3(kBlock), 0, s, A.n, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp,
+                                   C.ci, C.v, c.iscratch + kFlagFill);
+            };
+            const int key = fl * 10000 + hs * 10 + bl / 8;
+            switch (key) {
+            case 160641: fill(k_spgemm_fill_sub<16, 64, 8>); break;
+            case 161281: fill(k_spgemm_fill_sub<16, 128, 8>); break;
+            case 162561: fill(k_spgemm_fill_sub<16, 256, 8>); break;
+            case 325121: fill(k_spgemm_fill_sub<32, 512, 8>); break;
+            case 160642: fill(k_spgemm_fill_sub<16, 64, 16>); break;
+            case 161282: fill(k_spgemm_fill_sub<16, 128, 16>); break;
+            case 162562: fill(k_spgemm_fill_sub<16, 256, 16>); break;
+            case 325122: fill(k_spgemm_fill_sub<32, 512, 16>); break;
+            case 320644: fill(k_spgemm_fill_sub<32, 64, 32>); break;
+            case 321284: fill(k_spgemm_fill_sub<32, 128, 32>); break;
+            case 322564: fill(k_spgemm_fill_sub<32, 256, 32>); break;
+            case 325124: fill(k_spgemm_fill_sub<32, 512, 32>); break;
+            case 640648: fill(k_spgemm_fill_sub<64, 64, 64>); break;
+            case 641288: fill(k_spgemm_fill_sub<64, 128, 64>); break;
+            case 642568: fill(k_spgemm_fill_sub<64, 256, 64>); break;
+            case 645128: fill(k_spgemm_fill_sub<64, 512, 64>); break;
+            default: fail(AMG_ERR_HIP, "sparse product: no fill kernel for this shape");
+            }
         } else {
-            if (umax <= 128) fill(k_spgemm_fill<256, 1>);
-            else if (umax <= 256) fill(k_spgemm_fill<512, 1>);
-            else if (umax <= 512) fill(k_spgemm_fill<1024, 1>);
+            int G = 1;
+            while (2 * G <= 64 / 8 && 64 / (2 * G) >= bmax) G *= 2;
+            auto fill = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(gr), dim3(64), 0, s, A.n, G, A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp,
+                                   C.ci, C.v, c.iscratch + kFlagFill);
+            };
+            if (umax <= 512) fill(k_spgemm_fill<1024, 1>);
             else fill(k_spgemm_fill<2048, 1>);
         }
         check_kernels();
