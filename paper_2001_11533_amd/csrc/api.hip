@@ -235,7 +235,9 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
         AMG_HIP(hipHostMalloc((void **)&c.hiscr, 64 * sizeof(int), hipHostMallocDefault));
         AMG_HIP(hipHostMalloc((void **)&c.mails, 64 * sizeof(Mail), hipHostMallocDefault));
         AMG_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+        AMG_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
         for (auto &e : c.poll_ev) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (auto &e : c.side_ev) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         build_hierarchy(c, *A, *M, dirichlet);
         form_dense_hessian(c, o.hess_levels > 0 ? o.hess_levels : c.L);
         alloc_workspaces(c);
@@ -254,6 +256,7 @@ int amg_destroy(amg_ctx *ctx) {
     if (!ctx) return AMG_OK;
     Ctx &c = ctx->c;
     if (c.stream) (void)hipStreamSynchronize(c.stream);
+    if (c.side) (void)hipStreamSynchronize(c.side);  // setup that failed before joining it
     c.arena.free_all();
     if (c.hsc) (void)hipHostFree(c.hsc);
     if (c.hscr) (void)hipHostFree(c.hscr);
@@ -262,7 +265,10 @@ int amg_destroy(amg_ctx *ctx) {
     for (auto g : c.graphs) (void)hipGraphExecDestroy(g);
     for (auto e : c.poll_ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto e : c.side_ev)
+        if (e) (void)hipEventDestroy(e);
     if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
+    if (c.side) (void)hipStreamDestroy(c.side);
     delete ctx;
     return AMG_OK;
 }

@@ -73,6 +73,8 @@ struct Stats {
 struct Ctx {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
+    hipStream_t side = nullptr;         // setup work that overlaps the main stream (dense inverses)
+    hipEvent_t side_ev[2] = {nullptr, nullptr};  // fork and join of the side stream
     std::vector<hipGraphExec_t> graphs; // every instantiated graph (freed with the context)
     static constexpr int kPollRing = 4;
     hipEvent_t poll_ev[kPollRing] = {nullptr, nullptr, nullptr, nullptr};

@@ -948,104 +948,14 @@ __global__ __launch_bounds__(kBlock) void k_densify(int n, const int *rp, const 
 }
 
 // Tiled right-looking Cholesky of the lower triangle (tiles of kTB): per tile
-// column kb, factor the diagonal tile in LDS, solve the panel below it, then
-// update the trailing lower tiles.  Only the lower triangle is read later.
+// column, factor the diagonal tile and solve the panel below it (one launch),
+// then update the trailing lower tiles.  Only the lower triangle is read later.
 // Every dense kernel below works on a batch of matrices of one order n stored
 // back to back (matrix blockIdx.z at D + blockIdx.z * n * n).
 constexpr int kTB = 32;
 
 __device__ __forceinline__ double *bat(double *D, int n) { return D + (size_t)blockIdx.z * n * n; }
 __device__ __forceinline__ const double *bat(const double *D, int n) { return D + (size_t)blockIdx.z * n * n; }
-
-// Diagonal tile, padded with the identity; per column k the scaled column is
-// formed in a separate LDS vector so that one barrier separates it from the
-// trailing update, which in turn ends with the second barrier of the step.
-__global__ __launch_bounds__(kBlock) void k_potrf_tile(int n, double *Db, int k0, int *bad) {
-    __shared__ double T[kTB][kTB + 1];
-    __shared__ double col[kTB];
-    double *D = bat(Db, n);
-    const int tb = min(kTB, n - k0);
-    const int t = threadIdx.x;
-    for (int e = t; e < kTB * kTB; e += kBlock) {
-        const int i = e / kTB, j = e % kTB;
-        T[i][j] = (i < tb && j < tb) ? D[(size_t)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
-    }
-    __syncthreads();
-    for (int k = 0; k < tb; ++k) {
-        if (t < kTB) {
-            const double a = T[k][k];
-            const double piv = a > 0.0 ? sqrt(a) : 1.0;
-            if (t == k && !(a > 0.0)) atomicOr(bad, 1);
-            col[t] = t == k ? piv : t > k ? T[t][k] / piv : 0.0;
-        }
-        __syncthreads();
-        for (int e = t; e < kTB * kTB; e += kBlock) {
-            const int i = e / kTB, j = e % kTB;
-            if (j == k && i >= k) T[i][j] = col[i];
-            else if (j > k && j <= i) T[i][j] -= col[i] * col[j];
-        }
-        __syncthreads();
-    }
-    for (int e = t; e < kTB * kTB; e += kBlock) {
-        const int i = e / kTB, j = e % kTB;
-        if (i < tb && j <= i) D[(size_t)(k0 + i) * n + k0 + j] = T[i][j];
-    }
-}
-
-// panel: rows below the diagonal tile, X = A_ik L_kk^{-T}, one wavefront per row tile
-__global__ __launch_bounds__(64) void k_trsm_tile(int n, double *Db, int k0) {
-    __shared__ double Lk[kTB][kTB + 1];
-    double *D = bat(Db, n);
-    const int tb = min(kTB, n - k0);
-    const int t = threadIdx.x;
-    for (int e = t; e < tb * tb; e += 64) Lk[e / tb][e % tb] = D[(size_t)(k0 + e / tb) * n + k0 + e % tb];
-    __syncthreads();
-    const int r = k0 + tb + blockIdx.x * kTB + t;
-    if (t >= kTB || r >= n) return;
-    double x[kTB];
-#pragma unroll
-    for (int j = 0; j < kTB; ++j) x[j] = j < tb ? D[(size_t)r * n + k0 + j] : 0.0;
-#pragma unroll
-    for (int j = 0; j < kTB; ++j) {
-        if (j < tb) {
-            double v = x[j];
-            for (int m = 0; m < j; ++m) v -= x[m] * Lk[j][m];
-            x[j] = v / Lk[j][j];
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < kTB; ++j)
-        if (j < tb) D[(size_t)r * n + k0 + j] = x[j];
-}
-
-// trailing update A_ij -= L_ik L_jk^T for tile pairs i >= j after tile column k0
-__global__ __launch_bounds__(kBlock) void k_syrk_tile(int n, double *Db, int k0) {
-    __shared__ double Li[kTB][kTB + 1], Lj[kTB][kTB + 1];
-    double *D = bat(Db, n);
-    const int tb = min(kTB, n - k0);
-    const int s0 = k0 + tb;  // first trailing row
-    const long p = blockIdx.x;
-    long ti = (long)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-    while (ti * (ti + 1) / 2 > p) --ti;
-    while ((ti + 1) * (ti + 2) / 2 <= p) ++ti;
-    const long tj = p - ti * (ti + 1) / 2;
-    const int r0 = s0 + (int)ti * kTB, c0 = s0 + (int)tj * kTB;
-    const int t = threadIdx.x;
-    for (int e = t; e < kTB * kTB; e += kBlock) {
-        const int a = e / kTB, m = e % kTB;
-        Li[a][m] = (r0 + a < n && m < tb) ? D[(size_t)(r0 + a) * n + k0 + m] : 0.0;
-        Lj[a][m] = (c0 + a < n && m < tb) ? D[(size_t)(c0 + a) * n + k0 + m] : 0.0;
-    }
-    __syncthreads();
-    for (int e = t; e < kTB * kTB; e += kBlock) {
-        const int a = e / kTB, b = e % kTB;
-        const int i = r0 + a, j = c0 + b;
-        if (i >= n || j >= n || j > i) continue;
-        double acc = 0.0;
-        for (int m = 0; m < tb; ++m) acc += Li[a][m] * Lj[b][m];
-        D[(size_t)i * n + j] -= acc;
-    }
-}
 
 // ---- inverse from the Cholesky factor: A^{-1} = W^T W with W = L^{-1} ----
 // kTB x kTB tiles in LDS, zero outside the matrix; 256 threads each own a 2x2
@@ -1073,6 +983,121 @@ __device__ __forceinline__ void tile_mac(const Tile &P, const Tile &Q, double ac
         acc[1][0] += a1 * b0;
         acc[1][1] += a1 * b1;
     }
+}
+
+// Value of v in lane l of the wavefront (an FP64 register read through two
+// 32-bit lane reads).
+__device__ __forceinline__ double lane_read(double v, int l) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Diagonal tile factor and panel solve of tile column k0 in one launch, one
+// wavefront per workgroup.  Every workgroup factors the diagonal tile in
+// registers: lane i < kTB holds row i (padded with the identity past n), and
+// at step k the pivot and the entries of column k reach the other lanes by
+// lane reads, so the factorization needs neither LDS nor barriers; the upper
+// triangle of the registers holds garbage that no lower entry reads.
+// Workgroup 0 stores L_kk; workgroup b > 0 puts it in LDS and solves
+// X L_kk^T = A_ik for the b-th block of 64 rows below the tile, one row per
+// lane.  Every entry takes its updates in ascending k as in an unblocked
+// column Cholesky.
+__global__ __launch_bounds__(64) void k_potrf_panel(int n, double *Db, int k0, int *bad) {
+    __shared__ double T[kTB][kTB + 1];
+    double *D = bat(Db, n);
+    const int tb = min(kTB, n - k0);
+    const int t = threadIdx.x;
+    for (int e = t; e < kTB * kTB; e += 64) {
+        const int i = e / kTB, j = e % kTB;
+        T[i][j] = (i < tb && j < tb) ? D[(size_t)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    double r[kTB];
+#pragma unroll
+    for (int m = 0; m < kTB; ++m) r[m] = t < kTB ? T[t][m] : 0.0;
+    // (the uniform branch per step also keeps the compiler from hoisting the
+    // reads of every step to the top, which spills registers)
+#pragma unroll
+    for (int k = 0; k < kTB; ++k) {
+        if (k < tb) {
+            const double a = lane_read(r[k], k);
+            if (!(a > 0.0) && blockIdx.x == 0 && t == 0) atomicOr(bad, 1);
+            const double piv = a > 0.0 ? sqrt(a) : 1.0;
+            r[k] = t == k ? piv : t > k ? r[k] / piv : r[k];
+#pragma unroll
+            for (int j = k + 1; j < kTB; ++j) r[j] -= r[k] * lane_read(r[k], j);
+        }
+    }
+    if (blockIdx.x == 0) {
+        if (t < tb) {
+#pragma unroll
+            for (int m = 0; m < kTB; ++m)
+                if (m <= t) D[(size_t)(k0 + t) * n + k0 + m] = r[m];
+        }
+        return;
+    }
+    if (t < kTB) {
+#pragma unroll
+        for (int m = 0; m < kTB; ++m) T[t][m] = r[m];
+    }
+    __syncthreads();
+    const int row = k0 + tb + (blockIdx.x - 1) * 64 + t;
+    const bool live = row < n;
+    double x[kTB];
+    const double *src = D + (size_t)min(row, n - 1) * n + k0;  // a valid address for every lane
+#pragma unroll
+    for (int m = 0; m < kTB; ++m) {
+        const double v = src[min(m, tb - 1)];
+        x[m] = (live && m < tb) ? v : 0.0;
+    }
+    // by columns of L_kk: x[m] takes x[j] L_mj for j = 0, 1, ... before its division
+#pragma unroll
+    for (int j = 0; j < kTB; ++j) {
+        if (j < tb) {
+            x[j] = x[j] / T[j][j];
+#pragma unroll
+            for (int m = j + 1; m < kTB; ++m) x[m] -= x[j] * T[m][j];
+        }
+    }
+    if (live) {
+#pragma unroll
+        for (int m = 0; m < kTB; ++m)
+            if (m < tb) D[(size_t)row * n + k0 + m] = x[m];
+    }
+}
+
+// Trailing update A_ij -= L_ik L_jk^T for tile pairs i >= j after tile column
+// k0: L_ik in P, L_jk transposed in Q, 2 x 2 entries per thread; every entry
+// subtracts its sum over the tile column in ascending order.
+__global__ __launch_bounds__(kBlock) void k_syrk_tile(int n, double *Db, int k0) {
+    __shared__ Tile P, Q;
+    double *D = bat(Db, n);
+    const int tb = min(kTB, n - k0);
+    const int s0 = k0 + tb;  // first trailing row
+    const long p = blockIdx.x;
+    long ti = (long)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while (ti * (ti + 1) / 2 > p) --ti;
+    while ((ti + 1) * (ti + 2) / 2 <= p) ++ti;
+    const long tj = p - ti * (ti + 1) / 2;
+    const int r0 = s0 + (int)ti * kTB, c0 = s0 + (int)tj * kTB;
+    const int t = threadIdx.x, ra = (t / 16) * 2, cb = (t % 16) * 2;
+    for (int e = t; e < kTB * kTB; e += kBlock) {
+        const int a = e / kTB, m = e % kTB;
+        P[a][m] = (r0 + a < n && m < tb) ? D[(size_t)(r0 + a) * n + k0 + m] : 0.0;
+        Q[m][a] = (c0 + a < n && m < tb) ? D[(size_t)(c0 + a) * n + k0 + m] : 0.0;
+    }
+    __syncthreads();
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    tile_mac<false>(P, Q, acc);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int i = r0 + ra + u, j = c0 + cb + v;
+            if (i < n && j < n && j <= i) D[(size_t)i * n + j] -= acc[u][v];
+        }
 }
 
 // Lam[z][k] = inverse of the lower-triangular diagonal tile L_kk (padded rows
@@ -1273,6 +1298,7 @@ struct Setup {
     Ctx &c;
     hipStream_t s;
     explicit Setup(Ctx &cc) : c(cc), s(cc.stream) {}
+    Setup(Ctx &cc, hipStream_t st) : c(cc), s(st) {}
 
     int read_int(const int *d) {
         AMG_HIP(hipMemcpyAsync(c.hiscr, d, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1630,7 +1656,7 @@ struct Setup {
 
     // dense inverses of nb sparse SPD matrices of one order, returned back to
     // back (inverse b at the result + b * n * n)
-    double *dense_inverse(std::initializer_list<const DCsr *> mats) {
+    double *dense_inverse(std::initializer_list<const DCsr *> mats, std::vector<void *> *defer = nullptr) {
         const int nb = (int)mats.size();
         const int n = (*mats.begin())->n;
         const size_t nn = (size_t)n * n;
@@ -1642,19 +1668,21 @@ struct Setup {
                                (const uint8_t *)nullptr, (const uint8_t *)nullptr, D + b * nn);
             ++b;
         }
-        return factor_invert(D, n, nb);
+        return factor_invert(D, n, nb, defer);
     }
 
     // Cholesky factors of the nb matrices in D (overwritten), then their
-    // inverses W^T W, W = L^{-1}, in a new buffer
-    double *factor_invert(double *D, int n, int nb = 1) {
+    // inverses W^T W, W = L^{-1}, in a new buffer.  The temporaries (D
+    // included) go back to the arena, or to *defer when the work runs on a
+    // stream that the arena's reuse does not follow.
+    double *factor_invert(double *D, int n, int nb = 1, std::vector<void *> *defer = nullptr) {
         const size_t nn = (size_t)n * n;
         for (int k0 = 0; k0 < n; k0 += kTB) {
-            hipLaunchKernelGGL(k_potrf_tile, dim3(1, 1, nb), dim3(kBlock), 0, s, n, D, k0, c.iscratch + kFlagChol);
-            const int rest = n - (k0 + kTB);
+            const int rest = std::max(0, n - (k0 + kTB));
+            hipLaunchKernelGGL(k_potrf_panel, dim3(1 + ceil_div(rest, 64), 1, nb), dim3(64), 0, s, n, D, k0,
+                               c.iscratch + kFlagChol);
             if (rest <= 0) break;
             const int tiles = ceil_div(rest, kTB);
-            hipLaunchKernelGGL(k_trsm_tile, dim3(tiles, 1, nb), dim3(64), 0, s, n, D, k0);
             hipLaunchKernelGGL(k_syrk_tile, dim3(tiles * (tiles + 1) / 2, 1, nb), dim3(kBlock), 0, s, n, D, k0);
         }
         check_kernels();
@@ -1671,7 +1699,10 @@ struct Setup {
         double *inv = c.arena.alloc<double>(nb * nn);
         hipLaunchKernelGGL(k_wtw, dim3(T0 * (T0 + 1) / 2, 1, nb), dim3(kBlock), 0, s, n, W, inv);
         check_kernels();
-        for (void *p : {(void *)D, (void *)lam, (void *)acc, (void *)W}) c.arena.release(p);
+        for (void *p : {(void *)D, (void *)lam, (void *)acc, (void *)W}) {
+            if (defer) defer->push_back(p);
+            else c.arena.release(p);
+        }
         return inv;
     }
 };
@@ -1718,12 +1749,40 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
     }
     c.lev.clear();
     c.lev.push_back(l0);
+    // The dense inverses of small levels (j >= 1, at most dense_solve_max rows)
+    // are built on a side stream as soon as the level exists, while the main
+    // stream builds the levels below it.  The side stream starts behind
+    // everything queued on the main stream so far (the arena may hand it
+    // blocks released there), allocates only when it is started, and its
+    // temporaries return to the arena only after the main stream has joined it.
+    struct Early {
+        double *inv = nullptr;
+        DenseOp dA, dM;
+    };
+    std::vector<Early> early(c.lev.capacity());
+    std::vector<void *> deferred;
+    Setup sd(c, c.side);
+    bool forked = false;
+    auto fork_dense = [&](int jl, bool with_mass) {
+        AMG_HIP(hipEventRecord(c.side_ev[0], s));
+        AMG_HIP(hipStreamWaitEvent(c.side, c.side_ev[0], 0));
+        forked = true;
+        Level &Lv = c.lev[jl];
+        Early &e = early[jl];
+        e.inv = with_mass ? sd.dense_inverse({&Lv.A, &Lv.M}, &deferred) : sd.dense_inverse({&Lv.A}, &deferred);
+        e.dA = sd.dense_op(e.inv, Lv.n);
+        if (with_mass) e.dM = sd.dense_op(e.inv + (size_t)Lv.n * Lv.n, Lv.n);
+        su.check_kernels();
+    };
     int j = 0;
     while (true) {
         Level &L = c.lev[j];
         L.n = L.A.n;
         L.dl1inv = c.arena.alloc<double>(L.n);
-        if (L.n <= c.o.max_coarse || j + 1 >= c.o.max_levels) break;
+        const bool last = L.n <= c.o.max_coarse || j + 1 >= c.o.max_levels;
+        // (a level that is not known to be the coarsest may still turn out to be)
+        if (j >= 1 && L.n <= c.o.dense_solve_max) fork_dense(j, !last);
+        if (last) break;
         if (!su.coarsen(j)) break;
         ++j;
     }
@@ -1754,16 +1813,28 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
     if (Lc.n > c.o.dense_max)
         fail(AMG_ERR_DENSE_TOO_LARGE, "coarsest level has " + std::to_string(Lc.n) + " rows");
     c.nAinv = Lc.n;
-    c.Ainv = su.dense_inverse({&Lc.A});
-    c.dAc = su.dense_op(c.Ainv, Lc.n);
+    if (early[c.L - 1].inv) {
+        c.Ainv = early[c.L - 1].inv;
+        c.dAc = early[c.L - 1].dA;
+    } else {
+        c.Ainv = su.dense_inverse({&Lc.A});
+        c.dAc = su.dense_op(c.Ainv, Lc.n);
+    }
     // small coarse levels above the coarsest: exact dense A_j and M_j solves
     for (int j = 1; j + 1 < c.L; ++j) {
         Level &Lv = c.lev[j];
         if (Lv.n > c.o.dense_solve_max) continue;
-        Lv.Ainv = su.dense_inverse({&Lv.A, &Lv.M});
+        Early &e = early[j];
+        if (!e.inv || !e.dM.m64) fail(AMG_ERR_HIP, "dense inverse of a small level was not started");
+        Lv.Ainv = e.inv;
         Lv.Minv = Lv.Ainv + (size_t)Lv.n * Lv.n;
-        Lv.dA = su.dense_op(Lv.Ainv, Lv.n);
-        Lv.dM = su.dense_op(Lv.Minv, Lv.n);
+        Lv.dA = e.dA;
+        Lv.dM = e.dM;
+    }
+    if (forked) {  // join the side stream
+        AMG_HIP(hipEventRecord(c.side_ev[1], c.side));
+        AMG_HIP(hipStreamWaitEvent(s, c.side_ev[1], 0));
+        for (void *p : deferred) c.arena.release(p);
     }
     su.check_flags();
 }
