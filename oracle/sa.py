@@ -35,8 +35,10 @@ operation order (readings recorded with the design notes):
   small      on coarse levels (j >= 1) with n_j <= dense_solve_max the
              A_j- and M_j-solves are exact (dense Cholesky) instead of
              iterative; they return what the iterative solves approximate.
-             A V-cycle that reaches such a level solves there exactly and
-             goes no deeper (the levels below serve the Hessian levels only)
+             This includes the M-solves of the coarsest level (whose A-solves
+             are always dense).  A V-cycle that reaches such a level solves
+             there exactly and goes no deeper (the levels below serve the
+             Hessian levels only)
 """
 from __future__ import annotations
 
@@ -326,6 +328,8 @@ def build(A0: CSR, M: CSR, dirichlet: np.ndarray, opts: Opts) -> Hierarchy:
     if last.n > opts.dense_max:
         raise RuntimeError("coarsest level too large for the dense factor")
     h.chol_A = sla.cho_factor(last.A.dense(), lower=True)
+    if len(levels) > 1 and last.n <= opts.dense_solve_max:
+        last.chol_M = sla.cho_factor(last.M.dense(), lower=True)
     set_hessian_levels(h, opts.hess_levels or h.L)
     return h
 

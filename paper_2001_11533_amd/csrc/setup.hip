@@ -1763,7 +1763,7 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
     std::vector<void *> deferred;
     Setup sd(c, c.side);
     bool forked = false;
-    auto fork_dense = [&](int jl, bool with_mass) {
+    auto fork_dense = [&](int jl, bool with_mass) {  // with_mass: also M_j^{-1}
         AMG_HIP(hipEventRecord(c.side_ev[0], s));
         AMG_HIP(hipStreamWaitEvent(c.side, c.side_ev[0], 0));
         forked = true;
@@ -1780,8 +1780,9 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
         L.n = L.A.n;
         L.dl1inv = c.arena.alloc<double>(L.n);
         const bool last = L.n <= c.o.max_coarse || j + 1 >= c.o.max_levels;
-        // (a level that is not known to be the coarsest may still turn out to be)
-        if (j >= 1 && L.n <= c.o.dense_solve_max) fork_dense(j, !last);
+        // exact A_j and M_j solves (the coarsest level included: its A_j is
+        // dense in any case, and its mass solves become exact too)
+        if (j >= 1 && L.n <= c.o.dense_solve_max) fork_dense(j, true);
         if (last) break;
         if (!su.coarsen(j)) break;
         ++j;
@@ -1816,6 +1817,8 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
     if (early[c.L - 1].inv) {
         c.Ainv = early[c.L - 1].inv;
         c.dAc = early[c.L - 1].dA;
+        Lc.Minv = c.Ainv + (size_t)Lc.n * Lc.n;
+        Lc.dM = early[c.L - 1].dM;
     } else {
         c.Ainv = su.dense_inverse({&Lc.A});
         c.dAc = su.dense_op(c.Ainv, Lc.n);
