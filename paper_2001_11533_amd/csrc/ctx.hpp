@@ -22,6 +22,9 @@ struct DenseOp {
 struct Level {
     int n = 0;
     DCsr A, S, St, M;           // A_j, S_j (n_j x n_{j+1}), S_j^T, mass M_j
+    DCsr T;                     // A_j S_j (level < L-1; its pattern contains that of S_j)
+    double *Ts = nullptr;       // S_j's values on T's pattern (zero where S_j has no entry)
+    float *Ts32 = nullptr;
     double *dl1inv = nullptr;   // 1 / sum_k |a_ik|
     float *dl1inv32 = nullptr;
     double *mdinv = nullptr;    // 1 / diag(M_j)
@@ -122,6 +125,10 @@ void form_dense_hessian(Ctx &c, int ell);
 template <typename T> inline const T *avals(const DCsr &A) {
     if constexpr (std::is_same_v<T, double>) return A.v;
     else return A.v32;
+}
+template <typename T> inline const T *tsvals(const Level &L) {
+    if constexpr (std::is_same_v<T, float>) return L.Ts32;
+    else return L.Ts;
 }
 template <typename T> inline const T *dl1inv(const Level &L) {
     if constexpr (std::is_same_v<T, double>) return L.dl1inv;

@@ -750,6 +750,120 @@ template <typename T, int NB, bool DOT> struct EPost {
     }
 };
 
+// Prolongation fused into the first post-smoothing step.  The corrected
+// iterate x + S e and the residual it leaves, b - A (x + S e) = r - T e with
+// r = b - A x from the pre-smoothing and T = A S (the Galerkin intermediate,
+// whose pattern contains that of S), come from one pass over T's pattern that
+// carries S's values aligned to it (zero where S has no entry): per row i and
+// column c, se = (S e)_i and te = (T e)_i, both gathered from the coarse
+// vector e.  LPR = G NB lanes per row: G groups over the entries, one lane per
+// column; the epilogue receives both sums.
+template <typename T, int NB, int NV, class EP>
+__global__ __launch_bounds__(kBlock) void tpro_kernel(int nrows, const int *__restrict__ rp,
+                                                      const int *__restrict__ ci, const T *__restrict__ tv,
+                                                      const T *__restrict__ sv, const T *__restrict__ e, EP ep,
+                                                      int llpr, Reducer<(NV > 0 ? NV : 1), NB> red,
+                                                      const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    const int t = threadIdx.x, LPR = 1 << llpr, RPB = kBlock >> llpr, G = LPR / NB;
+    const int lane = t & (LPR - 1), c = lane % NB, g = lane / NB, rl = t >> llpr;
+    const int nblk = gridDim.x, b = xcd_block(blockIdx.x, nblk);
+    const int span = ceil_div_dev(nrows, nblk * RPB) * RPB;
+    const int r0 = b * span, r1 = min(nrows, r0 + span);
+    EP epv = ep;
+    epv.prep(c);
+    constexpr int NVA = NV > 0 ? NV : 1;
+    double acc[NVA];
+#pragma unroll
+    for (int q = 0; q < NVA; ++q) acc[q] = 0.0;
+    constexpr int U = kSpmvUnroll;
+    for (int base = r0; base < r1; base += RPB) {
+        const int row = base + rl;
+        const bool live = row < r1;
+        typename EP::P pr{};
+        if (live && g == 0) pr = epv.load(row, c);
+        T se = T(0), te = T(0);
+        if (live) {
+            const int p1 = rp[row + 1];
+            for (int p = rp[row] + g; p < p1; p += U * G) {
+                int kk[U];
+                T ta[U], sa[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int q = p + u * G;
+                    const bool ok = q < p1;
+                    kk[u] = ok ? ci[q] : -1;
+                    ta[u] = ok ? tv[q] : T(0);
+                    sa[u] = ok ? sv[q] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (kk[u] >= 0) {
+                        const T ev = e[(size_t)kk[u] * NB + c];
+                        se += sa[u] * ev;
+                        te += ta[u] * ev;
+                    }
+            }
+        }
+        for (int off = NB; off < LPR; off <<= 1) {  // the G groups of a row and column
+            se += __shfl_xor(se, off);
+            te += __shfl_xor(te, off);
+        }
+        if (live && g == 0) epv(row, c, se, te, pr, acc);
+    }
+    if constexpr (NV > 0) block_partials<NV, NB>(acc, red);
+}
+
+// Chebyshev, first post step: y0 = t + S e (in place of t),
+// y1 = y0 + (dinv (r - T e)) s0, i.e. y0 + (dinv (b - A y0)) s0
+template <typename T, int NB> struct EProCheb {
+    T *t;
+    const T *r;
+    const T *dinv;
+    T *y1;
+    T s0;
+    struct P {
+        T t, r, d;
+    };
+    __device__ void prep(int) {}
+    __device__ P load(int i, int c) const {
+        const size_t o = (size_t)i * NB + c;
+        return {t[o], r[o], dinv[i]};
+    }
+    template <int NV>
+    __device__ void operator()(int i, int c, T se, T te, const P &pr, double (&)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        const T y0 = pr.t + se;
+        t[o] = y0;
+        y1[o] = y0 + (pr.d * (pr.r - te)) * s0;
+    }
+};
+
+// l1-Jacobi post-sweep: out = (x + S e) + dinv (r - T e), i.e.
+// x1 + dinv (b - A x1) with x1 = x + S e; optionally acc += b out
+template <typename T, int NB, bool DOT> struct EProJac {
+    const T *x;
+    const T *r;
+    const T *b;
+    const T *dinv;
+    T *out;
+    struct P {
+        T x, r, b, d;
+    };
+    __device__ void prep(int) {}
+    __device__ P load(int i, int c) const {
+        const size_t o = (size_t)i * NB + c;
+        return {x[o], r[o], DOT ? b[o] : T(0), dinv[i]};
+    }
+    template <int NV>
+    __device__ void operator()(int i, int c, T se, T te, const P &pr, double (&acc)[NV]) const {
+        const T x1 = pr.x + se;
+        const T v = x1 + pr.d * (pr.r - te);
+        out[(size_t)i * NB + c] = v;
+        if constexpr (DOT) acc[0] += (double)pr.b * (double)v;
+    }
+};
+
 // CG search direction and operator: p_i = z_i + beta pold_i, q_i = (A p)_i, acc p.q
 template <typename T, int NB, typename TZ = T> struct ECgQ {
     const TZ *z;

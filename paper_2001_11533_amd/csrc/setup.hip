@@ -899,6 +899,27 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_fill_sub(int n, const int *ar
     }
 }
 
+// out[p] = S[i, ci[p]] over row i of T (zero where S has no entry), both rows
+// sorted; a row of S with an entry outside T's row sets *bad
+__global__ void k_align(int n, const int *trp, const int *tci, const int *srp, const int *sci, const double *sv,
+                        double *out, int *bad) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        int q = srp[i];
+        const int qe = srp[i + 1];
+        for (int p = trp[i]; p < trp[i + 1]; ++p) {
+            const int k = tci[p];
+            while (q < qe && sci[q] < k) ++q;
+            out[p] = (q < qe && sci[q] == k) ? sv[q] : 0.0;
+        }
+        int hit = 0;  // entries of S's row found in T's
+        for (int p = trp[i], q2 = srp[i]; p < trp[i + 1] && q2 < qe; ++p) {
+            while (q2 < qe && sci[q2] < tci[p]) ++q2;
+            if (q2 < qe && sci[q2] == tci[p]) ++hit;
+        }
+        if (hit != qe - srp[i]) atomicOr(bad, 1);
+    }
+}
+
 // lower triangle := upper triangle (symbolically symmetric pattern)
 // one wavefront per row, lanes over the row's entries left of the diagonal
 __global__ __launch_bounds__(kBlock) void k_mirror(int n, const int *rp, const int *ci, double *v, int *bad) {
@@ -1000,11 +1021,14 @@ __device__ __forceinline__ double lane_read(double v, int l) {
 // at step k the pivot and the entries of column k reach the other lanes by
 // lane reads, so the factorization needs neither LDS nor barriers; the upper
 // triangle of the registers holds garbage that no lower entry reads.
-// Workgroup 0 stores L_kk; workgroup b > 0 puts it in LDS and solves
-// X L_kk^T = A_ik for the b-th block of 64 rows below the tile, one row per
-// lane.  Every entry takes its updates in ascending k as in an unblocked
+// Workgroup 0 stores L_kk in the tile buffer Ldb (tile k0 / kTB of matrix z at
+// Ldb + (z T0 + k0 / kTB) kTB^2, row-major lower triangle), never in D: the
+// other workgroups of the launch read the unfactored tile from D and may
+// start after workgroup 0 has finished.  Workgroup b > 0 puts L_kk in LDS and
+// solves X L_kk^T = A_ik for the b-th block of 64 rows below the tile, one row
+// per lane.  Every entry takes its updates in ascending k as in an unblocked
 // column Cholesky.
-__global__ __launch_bounds__(64) void k_potrf_panel(int n, double *Db, int k0, int *bad) {
+__global__ __launch_bounds__(64) void k_potrf_panel(int n, double *Db, double *Ldb, int k0, int *bad) {
     __shared__ double T[kTB][kTB + 1];
     double *D = bat(Db, n);
     const int tb = min(kTB, n - k0);
@@ -1031,10 +1055,11 @@ __global__ __launch_bounds__(64) void k_potrf_panel(int n, double *Db, int k0, i
         }
     }
     if (blockIdx.x == 0) {
+        double *Ld = Ldb + ((size_t)blockIdx.z * ceil_div(n, kTB) + k0 / kTB) * kTB * kTB;
         if (t < tb) {
 #pragma unroll
             for (int m = 0; m < kTB; ++m)
-                if (m <= t) D[(size_t)(k0 + t) * n + k0 + m] = r[m];
+                if (m <= t) Ld[t * kTB + m] = r[m];
         }
         return;
     }
@@ -1100,19 +1125,20 @@ __global__ __launch_bounds__(kBlock) void k_syrk_tile(int n, double *Db, int k0)
         }
 }
 
-// Lam[z][k] = inverse of the lower-triangular diagonal tile L_kk (padded rows
-// and columns of a ragged last tile act as the identity); one wavefront per
-// tile, lane j < kTB solves L_kk x = e_j by forward substitution.
-__global__ __launch_bounds__(64) void k_trtri_tile(int n, const double *Db, double *Lamb) {
+// Lam[z][k] = inverse of the lower-triangular diagonal tile L_kk, read from
+// the tile buffer of k_potrf_panel (padded rows and columns of a ragged last
+// tile act as the identity); one wavefront per tile, lane j < kTB solves
+// L_kk x = e_j by forward substitution.
+__global__ __launch_bounds__(64) void k_trtri_tile(int n, const double *Ldb, double *Lamb) {
     __shared__ double T[kTB][kTB + 1];
-    const double *D = bat(Db, n);
     const int T0 = ceil_div(n, kTB);
+    const double *Ld = Ldb + ((size_t)blockIdx.z * T0 + blockIdx.x) * kTB * kTB;
     double *Lam = Lamb + ((size_t)blockIdx.z * T0 + blockIdx.x) * kTB * kTB;
     const int k0 = blockIdx.x * kTB;
     for (int e = threadIdx.x; e < kTB * kTB; e += 64) {
         const int a = e / kTB, b = e % kTB;
         const bool in = k0 + a < n && k0 + b < n;
-        T[a][b] = b > a ? 0.0 : in ? D[(size_t)(k0 + a) * n + k0 + b] : (a == b ? 1.0 : 0.0);
+        T[a][b] = b > a ? 0.0 : in ? Ld[a * kTB + b] : (a == b ? 1.0 : 0.0);
     }
     __syncthreads();
     const int j = threadIdx.x;
@@ -1313,13 +1339,16 @@ struct Setup {
     // cleared once per phase and read at its end in one transfer.
     static constexpr int kFlag0 = 16, kFlagN = 32;
     static constexpr int kFlagFill = 16, kFlagMirror = 17, kFlagChol = 18, kFlagMassDiag = 19, kFlagDiag = 20;
+    static constexpr int kFlagAlign = kFlag0 + kFlagN - 1;  // the level flags end before it
+    static constexpr int kFlagDiagN = kFlagAlign - kFlagDiag;
     void clear_flags() { zero(c.iscratch + kFlag0, kFlagN * sizeof(int)); }
     void check_flags() {
         AMG_HIP(hipMemcpyAsync(c.hiscr, c.iscratch + kFlag0, kFlagN * sizeof(int), hipMemcpyDeviceToHost, s));
         AMG_HIP(hipStreamSynchronize(s));
         const int *f = c.hiscr - kFlag0;
-        for (int j = 0; j < kFlag0 + kFlagN - kFlagDiag; ++j)
+        for (int j = 0; j < kFlagDiagN; ++j)
             if (f[kFlagDiag + j]) fail(AMG_ERR_NOT_SPD, "non-positive diagonal at level " + std::to_string(j));
+        if (f[kFlagAlign]) fail(AMG_ERR_ARG, "prolongator entry missing from A S");
         if (f[kFlagMassDiag]) fail(AMG_ERR_NOT_SPD, "mass matrix has a non-positive diagonal");
         if (f[kFlagChol]) fail(AMG_ERR_NOT_SPD, "dense Cholesky met a non-positive pivot");
         if (f[kFlagMirror]) fail(AMG_ERR_ARG, "coarse matrix pattern is not symmetric");
@@ -1496,15 +1525,20 @@ struct Setup {
         return T;
     }
 
-    DCsr galerkin(const DCsr &S, const DCsr &St, const DCsr &A) {
+    // S^T (A S); with keep, A S is handed back instead of released
+    DCsr galerkin(const DCsr &S, const DCsr &St, const DCsr &A, DCsr *keep = nullptr) {
         DCsr T = spgemm(A, S);
         DCsr C = spgemm(St, T);
         hipLaunchKernelGGL(k_mirror, dim3(gwave(C.n)), dim3(kBlock), 0, s, C.n, C.rp, C.ci, C.v,
                            c.iscratch + kFlagMirror);
         check_kernels();
-        c.arena.release(T.rp);
-        c.arena.release(T.ci);
-        c.arena.release(T.v);
+        if (keep) {
+            *keep = T;
+        } else {
+            c.arena.release(T.rp);
+            c.arena.release(T.ci);
+            c.arena.release(T.v);
+        }
         return C;
     }
 
@@ -1516,7 +1550,7 @@ struct Setup {
         const uint8_t *mask = L0.mask;
         double *d = c.arena.alloc<double>(n);
         hipLaunchKernelGGL(k_diag, dim3(gsz(n)), dim3(kBlock), 0, s, n, A.rp, A.ci, A.v, mask, d,
-                           c.iscratch + kFlagDiag + std::min(j, kFlag0 + kFlagN - kFlagDiag - 1));
+                           c.iscratch + kFlagDiag + std::min(j, kFlagDiagN - 1));
         // the input matrix is checked before anything is built on it
         if (j == 0 && read_int(c.iscratch + kFlagDiag))
             fail(AMG_ERR_NOT_SPD, "non-positive diagonal at level 0");
@@ -1603,7 +1637,7 @@ struct Setup {
         L0.St = transpose(S);
         Level nx;
         nx.n = nc;
-        nx.A = galerkin(L0.S, L0.St, A);
+        nx.A = galerkin(L0.S, L0.St, A, &L0.T);
         nx.M = galerkin(L0.S, L0.St, L0.M);
         c.lev.push_back(nx);
         return true;
@@ -1677,29 +1711,30 @@ struct Setup {
     // stream that the arena's reuse does not follow.
     double *factor_invert(double *D, int n, int nb = 1, std::vector<void *> *defer = nullptr) {
         const size_t nn = (size_t)n * n;
+        const int T0 = ceil_div(n, kTB);
+        double *ld = c.arena.alloc<double>((size_t)nb * T0 * kTB * kTB);  // factored diagonal tiles
         for (int k0 = 0; k0 < n; k0 += kTB) {
             const int rest = std::max(0, n - (k0 + kTB));
-            hipLaunchKernelGGL(k_potrf_panel, dim3(1 + ceil_div(rest, 64), 1, nb), dim3(64), 0, s, n, D, k0,
+            hipLaunchKernelGGL(k_potrf_panel, dim3(1 + ceil_div(rest, 64), 1, nb), dim3(64), 0, s, n, D, ld, k0,
                                c.iscratch + kFlagChol);
             if (rest <= 0) break;
             const int tiles = ceil_div(rest, kTB);
             hipLaunchKernelGGL(k_syrk_tile, dim3(tiles * (tiles + 1) / 2, 1, nb), dim3(kBlock), 0, s, n, D, k0);
         }
         check_kernels();
-        const int T0 = ceil_div(n, kTB);
         double *lam = c.arena.alloc<double>((size_t)nb * T0 * kTB * kTB);
         double *acc = c.arena.alloc<double>(nb * nn);
         double *W = c.arena.alloc<double>(nb * nn);
         zero(acc, sizeof(double) * nb * nn);
         zero(W, sizeof(double) * nb * nn);
-        hipLaunchKernelGGL(k_trtri_tile, dim3(T0, 1, nb), dim3(64), 0, s, n, D, lam);
+        hipLaunchKernelGGL(k_trtri_tile, dim3(T0, 1, nb), dim3(64), 0, s, n, ld, lam);
         for (int k = 0; k < T0; ++k)
             hipLaunchKernelGGL(k_trinv_step, dim3(std::max(1, T0 - k - 1), k + 1, nb), dim3(kBlock), 0, s, n, k,
                                D, lam, acc, W);
         double *inv = c.arena.alloc<double>(nb * nn);
         hipLaunchKernelGGL(k_wtw, dim3(T0 * (T0 + 1) / 2, 1, nb), dim3(kBlock), 0, s, n, W, inv);
         check_kernels();
-        for (void *p : {(void *)D, (void *)lam, (void *)acc, (void *)W}) {
+        for (void *p : {(void *)D, (void *)ld, (void *)lam, (void *)acc, (void *)W}) {
             if (defer) defer->push_back(p);
             else c.arena.release(p);
         }
@@ -1800,6 +1835,16 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
         if (L.S.v) {
             f32(L.S);
             f32(L.St);
+        }
+        if (L.T.v) {
+            // S's values on the pattern of T = A S, for the fused coarse
+            // correction (after the level loop: off the path to the side stream)
+            L.Ts = c.arena.alloc<double>(L.T.nnz);
+            hipLaunchKernelGGL(k_align, dim3(gsz(L.n)), dim3(kBlock), 0, s, L.n, L.T.rp, L.T.ci, L.S.rp, L.S.ci,
+                               L.S.v, L.Ts, c.iscratch + Setup::kFlagAlign);
+            f32(L.T);
+            L.Ts32 = c.arena.alloc<float>(L.T.nnz);
+            hipLaunchKernelGGL(k_to_f32, dim3(gsz(L.T.nnz)), dim3(kBlock), 0, s, (long)L.T.nnz, L.Ts, L.Ts32);
         }
         L.dl1inv32 = c.arena.alloc<float>(L.n);
         hipLaunchKernelGGL(k_to_f32, dim3(gsz(L.n)), dim3(kBlock), 0, s, (long)L.n, L.dl1inv, L.dl1inv32);

@@ -82,6 +82,21 @@ template <int NB> struct Solver {
         finish<NV>(pbuf, fin, stop);
     }
 
+    // fused prolongation + first post-smoothing step at level Lv (tpro_kernel)
+    template <typename T, int NV, class EP>
+    void tpro(const Level &Lv, const T *e, EP ep, const int *stop, int pbuf = 0) {
+        const DCsr &Tm = Lv.T;
+        const double m = Tm.n > 0 ? (double)Tm.nnz / (double)Tm.n : 1.0;
+        int G = 1;
+        while (G * NB < 64 && G < m / kSpmvUnroll) G <<= 1;
+        const int llpr = ilog2(G * NB);
+        const int g = grid_rows(Tm.n, kBlock >> llpr, NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
+        Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
+        if (NV > 0) c.pgrid[pbuf] = g;
+        hipLaunchKernelGGL((tpro_kernel<T, NB, NV, EP>), dim3(g), dim3(kBlock), 0, s, Tm.n, Tm.rp, Tm.ci,
+                           avals<T>(Tm), tsvals<T>(Lv), e, ep, llpr, red, stop);
+    }
+
     template <int NV, class OP, class FIN> void elem(int n, OP op, FIN fin, const int *stop, int pbuf = 0) {
         const int g = grid_rows((long)n * NB, kBlock, NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
         Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
@@ -192,17 +207,31 @@ template <int NB> struct Solver {
             const T *e = (l + 1 == Lc) ? vcws<T>(c.ws[Lc]).x : vcws<T>(c.ws[l + 1]).x2;
             const T *bb = (l == j) ? b : v.b;
             T *out = (l == j) ? z : v.x2;
+            // the coarse correction and the first post step in one pass over
+            // T = A S (residual r - T e), when the level keeps T
+            const bool fuse = Lv.T.rp && avals<T>(Lv.T) && tsvals<T>(Lv);
             if (cheb) {
                 // the iterate is t; the first post step writes x, the second out
-                spmv<T, 0>(Lv.S, avals<T>(Lv.S), GPlain<T, NB>{e}, EAdd<T, NB>{v.t}, NoFin{}, stop);
-                spmv<T, 0>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.t},
-                           EChebPost1<T, NB>{bb, dl1inv<T>(Lv), v.t, v.x, s0}, NoFin{}, stop);
+                if (fuse) {
+                    tpro<T, 0>(Lv, e, EProCheb<T, NB>{v.t, v.r, dl1inv<T>(Lv), v.x, s0}, stop);
+                } else {
+                    spmv<T, 0>(Lv.S, avals<T>(Lv.S), GPlain<T, NB>{e}, EAdd<T, NB>{v.t}, NoFin{}, stop);
+                    spmv<T, 0>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.t},
+                               EChebPost1<T, NB>{bb, dl1inv<T>(Lv), v.t, v.x, s0}, NoFin{}, stop);
+                }
                 if (l == j && dot)
                     spmv<T, 1>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x},
                                EChebPost2<T, NB, true>{bb, dl1inv<T>(Lv), v.t, v.x, out, c1, c2}, NoFin{}, stop, 2);
                 else
                     spmv<T, 0>(Lv.A, avals<T>(Lv.A), GPlain<T, NB>{v.x},
                                EChebPost2<T, NB, false>{bb, dl1inv<T>(Lv), v.t, v.x, out, c1, c2}, NoFin{}, stop);
+                continue;
+            }
+            if (fuse) {
+                if (l == j && dot)
+                    tpro<T, 1>(Lv, e, EProJac<T, NB, true>{v.x, v.r, bb, dl1inv<T>(Lv), out}, stop, 2);
+                else
+                    tpro<T, 0>(Lv, e, EProJac<T, NB, false>{v.x, v.r, bb, dl1inv<T>(Lv), out}, stop);
                 continue;
             }
             spmv<T, 0>(Lv.S, avals<T>(Lv.S), GPlain<T, NB>{e}, EAdd<T, NB>{v.x}, NoFin{}, stop);

@@ -1,0 +1,46 @@
+"""Fresh setups and solves of the 64^3 workload (the configuration the
+benchmark times: float32 V-cycles with the Chebyshev smoother inside FP64 CG)
+give bit-identical results: every reduction sums its partials in a fixed
+order, and no kernel may read data that another part of the same setup is
+still writing.  In particular the dense coarse inverses, which are built on a
+side stream while the main stream builds the coarser levels, must not depend
+on how the two streams interleave (a diagonal tile written back while other
+workgroups of the same launch still read it once made the preconditioner,
+and so the outer iteration count, vary from run to run)."""
+import numpy as np
+import pytest
+
+import inputs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.mark.timeout(600)
+def test_repeated_setup_and_solve_are_bit_identical():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2001_11533_amd as amg
+    p = inputs.config("c3")
+    rp, ci, va, vm = amg.assemble_p1(p.mesh.coords, p.mesh.elems, p.kappa)
+    dev = torch.device("cuda:0")
+    A = tuple(torch.as_tensor(x).to(dev) for x in (rp, ci, va))
+    M = tuple(torch.as_tensor(x).to(dev) for x in (rp, ci, vm))
+    mask = torch.as_tensor(p.dirichlet).to(dev)
+    yd = torch.as_tensor(np.ascontiguousarray(p.yd[:, 0])).to(dev)
+    ref = None
+    for rep in range(6):
+        g = amg.HessianSolver(A, M, mask, beta=p.beta, inner_precision=32, smoother=1)
+        u, info = g.reduced_solve(yd, rtol=1e-8)
+        Ainv = g.dense(0)
+        Hinv = g.dense(2)
+        g.close()
+        got = (info[0]["outer_iters"], info[0]["inner_iters_total"], u.cpu().numpy(), Ainv, Hinv)
+        print(f"rep {rep}: outer {got[0]} inner {got[1]}", flush=True)
+        if ref is None:
+            ref = got
+            continue
+        assert got[0] == ref[0] and got[1] == ref[1]
+        assert np.array_equal(got[2].view(np.uint64), ref[2].view(np.uint64))
+        assert np.array_equal(got[3].view(np.uint64), ref[3].view(np.uint64))
+        assert np.array_equal(got[4].view(np.uint64), ref[4].view(np.uint64))
