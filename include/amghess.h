@@ -156,8 +156,15 @@ int amg_p1_assemble(int dim, int32_t nv, const double *coords, int32_t ne, const
 int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet,
               const amg_opts *opts, void *stream, amg_ctx **out);
 
-/* Free every device allocation of the context.  NULL is accepted. */
+/* End the context: waits for its streams, then gives its device memory to a
+ * process-wide cache that later contexts on the same device draw from (so a
+ * context starts and ends without device allocation calls, which wait for the
+ * device).  NULL is accepted. */
 int amg_destroy(amg_ctx *ctx);
+
+/* Hand every device block held in that cache back to the driver (all
+ * devices).  Contexts still alive are not affected.  Returns AMG_OK. */
+int amg_release_memory(void);
 
 /* y = K_j u = A_j^{-1} M_{yu,j} u  (eq. solutionopdef at level j; level 0 is the fine
  * problem).  u, y: [n_j x nb].  info may be NULL. */

@@ -273,6 +273,11 @@ int amg_destroy(amg_ctx *ctx) {
     return AMG_OK;
 }
 
+int amg_release_memory(void) {
+    DevPool::get().release(-1);
+    return AMG_OK;
+}
+
 int state_solve(amg_ctx *ctx, int level, const double *u, double *y, int nb, amg_info *info) {
     if (int e = check_vec_call(ctx ? &ctx->c : nullptr, level, nb)) return e;
     if (!u || !y) return AMG_ERR_ARG;

@@ -7,7 +7,9 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "amghess.h"
@@ -29,6 +31,63 @@ struct Error {
                         std::string(#call) + ": " + hipGetErrorString(e_));                \
     } while (0)
 
+// Device blocks that ended contexts give back, kept per device for later
+// contexts of the process (what a framework's caching allocator does): a
+// context then starts and ends without hipMalloc / hipFree calls, each of
+// which waits for the device.  A request takes the smallest cached block of
+// its device that is at least as large and at most a third larger;
+// amg_release_memory hands every cached block back to the driver.
+struct DevPool {
+    struct Blk {
+        int dev;
+        size_t bytes;
+        void *p;
+    };
+    std::mutex m;
+    std::vector<Blk> blks;
+    size_t held = 0;
+    static constexpr size_t kMaxHeld = size_t(32) << 30;
+    // never destroyed: no hipFree may run after the runtime has shut down
+    static DevPool &get() {
+        static DevPool *pool = new DevPool();
+        return *pool;
+    }
+    // a cached block (and its size) or {nullptr, 0}
+    std::pair<void *, size_t> take(int dev, size_t bytes) {
+        std::lock_guard<std::mutex> g(m);
+        int best = -1;
+        for (size_t i = 0; i < blks.size(); ++i)
+            if (blks[i].dev == dev && blks[i].bytes >= bytes && blks[i].bytes <= bytes + bytes / 3 &&
+                (best < 0 || blks[i].bytes < blks[best].bytes))
+                best = (int)i;
+        if (best < 0) return {nullptr, 0};
+        const Blk b = blks[best];
+        blks.erase(blks.begin() + best);
+        held -= b.bytes;
+        return {b.p, b.bytes};
+    }
+    // false: not kept (the cache is full), the caller frees it
+    bool give(int dev, void *p, size_t bytes) {
+        std::lock_guard<std::mutex> g(m);
+        if (held + bytes > kMaxHeld) return false;
+        blks.push_back({dev, bytes, p});
+        held += bytes;
+        return true;
+    }
+    // every cached block of device dev (all devices when dev < 0) to the driver
+    void release(int dev) {
+        std::vector<Blk> out;
+        {
+            std::lock_guard<std::mutex> g(m);
+            std::vector<Blk> keep;
+            for (const Blk &b : blks) (dev < 0 || b.dev == dev ? out : keep).push_back(b);
+            blks.swap(keep);
+            for (const Blk &b : out) held -= b.bytes;
+        }
+        for (const Blk &b : out) (void)hipFree(b.p);
+    }
+};
+
 // Every device allocation of a context goes through one arena so that a
 // failure anywhere in setup releases everything.  Requests up to a quarter of a
 // chunk are carved from large chunks (few hipMalloc calls, and few hipFree
@@ -43,23 +102,34 @@ struct Arena {
         size_t bytes;
         bool live;
     };
-    std::vector<Blk> blks;      // every block handed out
-    std::vector<void *> chunks; // what hipMalloc returned
+    std::vector<Blk> blks;                         // every block handed out
+    std::vector<std::pair<void *, size_t>> chunks; // device allocations (cached or new) and sizes
+    int dev = -1;                                  // device of the allocations
     char *cur = nullptr;
     size_t cur_left = 0, next_chunk = size_t(8) << 20;
     size_t bytes = 0;
     static constexpr size_t kMaxChunk = size_t(128) << 20;
 
     void *dev_malloc(size_t b) {
-        void *p = nullptr;
-        hipError_t e = hipMalloc(&p, b);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            fail(AMG_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+        if (dev < 0 && hipGetDevice(&dev) != hipSuccess) fail(AMG_ERR_HIP, "hipGetDevice failed");
+        auto got = DevPool::get().take(dev, b);
+        if (!got.first) {
+            void *p = nullptr;
+            hipError_t e = hipMalloc(&p, b);
+            if (e != hipSuccess) {  // once more without the cache's blocks of this device
+                (void)hipGetLastError();
+                DevPool::get().release(dev);
+                e = hipMalloc(&p, b);
+            }
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                fail(AMG_ERR_OOM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+            }
+            got = {p, b};
         }
-        chunks.push_back(p);
-        bytes += b;
-        return p;
+        chunks.push_back(got);
+        bytes += got.second;
+        return got.first;
     }
     template <class T> T *alloc(size_t n) {
         if (n == 0) n = 1;
@@ -92,8 +162,10 @@ struct Arena {
         for (auto &b : blks)
             if (b.p == p) b.live = false;
     }
+    // back to the process's cache (the context's streams have drained)
     void free_all() {
-        for (void *p : chunks) (void)hipFree(p);
+        for (auto &ch : chunks)
+            if (!DevPool::get().give(dev, ch.first, ch.second)) (void)hipFree(ch.first);
         chunks.clear();
         blks.clear();
         cur = nullptr;

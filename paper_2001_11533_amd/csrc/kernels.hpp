@@ -1399,6 +1399,50 @@ template <> struct Vec16<float> {
     }
 };
 
+// One column with b of the matrix's type and 16-byte aligned: b is read in the
+// same 16-byte vectors as the matrix rows, eight vectors of each in flight per
+// lane (a float32 row of up to 2048 entries is one round).  The last vector of
+// a ragged row is read element by element (the row is zero-padded to ld, b is
+// not).
+template <typename TM>
+__global__ __launch_bounds__(kBlock) void dense_apply1_kernel(int n, int ld, const TM *__restrict__ inv,
+                                                              const TM *__restrict__ b, TM *__restrict__ x,
+                                                              const int *__restrict__ stop) {
+    if (stop && *stop) return;
+    using V = Vec16<TM>;
+    using VT = typename V::type;
+    constexpr int W = V::n, D = 8;
+    const int lane = threadIdx.x % 64;
+    const int w = (blockIdx.x * kBlock + threadIdx.x) / 64;
+    const int nw = gridDim.x * kBlock / 64;
+    for (int i = w; i < n; i += nw) {
+        double acc = 0.0;
+        const TM *row = inv + (size_t)i * ld;
+        for (int k0 = lane * W; k0 < n; k0 += 64 * W * D) {
+            VT m[D], bv[D];
+#pragma unroll
+            for (int u = 0; u < D; ++u) {
+                const int k = k0 + u * 64 * W;
+                m[u] = k < n ? *reinterpret_cast<const VT *>(row + k) : VT{};
+                if (k + W <= n) {
+                    bv[u] = *reinterpret_cast<const VT *>(b + k);
+                } else {
+                    TM t[W];
+#pragma unroll
+                    for (int e = 0; e < W; ++e) t[e] = k + e < n ? b[k + e] : TM(0);
+                    bv[u] = *reinterpret_cast<const VT *>(t);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < D; ++u)
+#pragma unroll
+                for (int e = 0; e < W; ++e) acc += V::get(m[u], e) * V::get(bv[u], e);
+        }
+        for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) x[i] = (TM)acc;
+    }
+}
+
 template <typename T, typename TM, int NB>
 __global__ __launch_bounds__(kBlock) void dense_apply_kernel(int n, int ld, const TM *__restrict__ inv,
                                                              const T *__restrict__ b, T *__restrict__ x,

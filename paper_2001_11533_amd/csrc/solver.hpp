@@ -134,6 +134,13 @@ template <int NB> struct Solver {
 
     template <typename T> void dense_apply(const DenseOp &d, const T *b, T *x, const int *stop) {
         const int g = ceil_div((long)d.n * 64, kBlock);
+        if (NB == 1 && reinterpret_cast<uintptr_t>(b) % 16 == 0) {
+            const T *m;
+            if constexpr (std::is_same_v<T, float>) m = d.m32;
+            else m = d.m64;
+            hipLaunchKernelGGL((dense_apply1_kernel<T>), dim3(g), dim3(kBlock), 0, s, d.n, d.ld, m, b, x, stop);
+            return;
+        }
         if constexpr (std::is_same_v<T, float>)
             hipLaunchKernelGGL((dense_apply_kernel<T, float, NB>), dim3(g), dim3(kBlock), 0, s, d.n, d.ld, d.m32, b,
                                x, stop);

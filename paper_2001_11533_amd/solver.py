@@ -39,6 +39,12 @@ def assemble_p1(coords: np.ndarray, elems: np.ndarray, kappa: np.ndarray):
     return rowptr, col, valA, valM
 
 
+def release_memory() -> None:
+    """Return the device memory that ended contexts keep cached for later ones
+    to the driver (amg_release_memory)."""
+    check(lib().amg_release_memory(), None)
+
+
 def default_opts(**kw) -> Opts:
     o = Opts()
     check(lib().amg_opts_default(C.byref(o)))
