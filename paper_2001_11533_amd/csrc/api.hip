@@ -37,18 +37,27 @@ template <class F> int guarded(Ctx *c, F &&f) {
     }
 }
 
-// a mailbox from the pinned pool, its device view stored in the device-side struct
-Mail *take_mail(Ctx &c, Mail **dev_slot) {
+// a mailbox from the pinned pool (zeroed) and its device view
+Mail *take_mail(Ctx &c, Mail **dev_view) {
     if (c.nmail >= 64) fail(AMG_ERR_OOM, "mailbox pool exhausted");
     Mail *h = &c.mails[c.nmail++];
     std::memset(h, 0, sizeof(Mail));
     void *d = nullptr;
     AMG_HIP(hipHostGetDevicePointer(&d, h, 0));
-    AMG_HIP(hipMemcpy(dev_slot, &d, sizeof(void *), hipMemcpyHostToDevice));
+    *dev_view = static_cast<Mail *>(d);
     return h;
 }
 
-template <typename T> void alloc_cg(Ctx &c, CgWs<T> &w, size_t m) {
+// The scalar blocks of all CG workspaces sit in one device array that a single
+// copy initialises (zeroed, each with its mailbox's device view): one transfer
+// instead of a blocking memset and copy per workspace.
+struct ScalSetup {
+    CgScal *dev = nullptr;
+    std::vector<CgScal> host;
+    size_t used = 0;
+};
+
+template <typename T> void alloc_cg(Ctx &c, CgWs<T> &w, size_t m, ScalSetup &ss) {
     Arena &a = c.arena;
     w.x = a.alloc<T>(m);
     w.r = a.alloc<T>(m);
@@ -56,9 +65,10 @@ template <typename T> void alloc_cg(Ctx &c, CgWs<T> &w, size_t m) {
     w.p0 = a.alloc<T>(m);
     w.p1 = a.alloc<T>(m);
     w.q = a.alloc<T>(m);
-    w.sc = a.alloc<CgScal>(1);
-    AMG_HIP(hipMemset(w.sc, 0, sizeof(CgScal)));
-    w.hmail = take_mail(c, &w.sc->mail);
+    if (ss.used >= ss.host.size()) fail(AMG_ERR_HIP, "CG scalar blocks miscounted");
+    w.sc = ss.dev + ss.used;
+    w.hmail = take_mail(c, &ss.host[ss.used].mail);
+    ++ss.used;
 }
 
 template <typename T> void alloc_vc(Arena &a, VcWs<T> &v, size_t m) {
@@ -75,16 +85,19 @@ void alloc_workspaces(Ctx &c) {
     const int nbp = c.nbp;
     c.ws.assign(c.L, LevelWs{});
     const bool mixed = c.o.inner_precision == 32;
+    ScalSetup ss;
+    ss.host.assign((size_t)c.L * (mixed ? 5 : 3) + 1, CgScal{});
+    ss.dev = a.alloc<CgScal>(ss.host.size());
     for (int l = 0; l < c.L; ++l) {
         LevelWs &w = c.ws[l];
         const size_t m = (size_t)c.lev[l].n * nbp;
-        alloc_cg(c, w.in64, m);
-        alloc_cg(c, w.mass, m);
-        alloc_cg(c, w.hcg, m);
+        alloc_cg(c, w.in64, m, ss);
+        alloc_cg(c, w.mass, m, ss);
+        alloc_cg(c, w.hcg, m, ss);
         alloc_vc(a, w.vc64, m);
         if (mixed) {
-            alloc_cg(c, w.inmx, m);
-            alloc_cg(c, w.in32, m);
+            alloc_cg(c, w.inmx, m, ss);
+            alloc_cg(c, w.in32, m, ss);
             alloc_vc(a, w.vc32, m);
             w.rr = a.alloc<double>(m);
             w.b32 = a.alloc<float>(m);
@@ -102,15 +115,18 @@ void alloc_workspaces(Ctx &c) {
         w.ml_t = a.alloc<double>(m);
     }
     const size_t m0 = (size_t)c.N * nbp;
-    alloc_cg(c, c.outer, m0);
+    alloc_cg(c, c.outer, m0, ss);
+    AMG_HIP(hipMemcpyAsync(ss.dev, ss.host.data(), ss.used * sizeof(CgScal), hipMemcpyHostToDevice, c.stream));
     c.ox = a.alloc<double>(m0);
     c.ob = a.alloc<double>(m0);
     c.obq = a.alloc<double>(m0);
     c.pk_in = a.alloc<double>(m0);
     c.pk_out = a.alloc<double>(m0);
     c.rsd = a.alloc<RefScal>(1);
-    AMG_HIP(hipMemset(c.rsd, 0, sizeof(RefScal)));
-    c.rmail = take_mail(c, &c.rsd->mail);
+    RefScal rs{};
+    c.rmail = take_mail(c, &rs.mail);
+    AMG_HIP(hipMemcpyAsync(c.rsd, &rs, sizeof(RefScal), hipMemcpyHostToDevice, c.stream));
+    AMG_HIP(hipStreamSynchronize(c.stream));  // the host sources of the copies end with this call
 }
 
 void fill_info(Ctx &c, amg_info *info, int n, double ms, int outer_it) {

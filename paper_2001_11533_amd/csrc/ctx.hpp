@@ -31,7 +31,6 @@ struct Level {
     int *agg = nullptr;         // level < L-1
     uint8_t *root = nullptr;
     const uint8_t *mask = nullptr;  // Dirichlet flags, level 0 only
-    double omega = 0.0, rho = 0.0;
     double *Ainv = nullptr;     // small coarse levels: dense inverses of A_j and M_j
     double *Minv = nullptr;
     DenseOp dA, dM;             // their padded apply copies

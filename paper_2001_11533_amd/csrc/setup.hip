@@ -23,7 +23,11 @@
 //              copied from the upper one
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
 #include <initializer_list>
+#include <mutex>
+#include <thread>
 
 #include "ctx.hpp"
 
@@ -388,8 +392,10 @@ __global__ void k_ptent_fill(int n, const int *agg, const int *rp, int *ci, doub
 }
 
 // S[i,J] = [agg(i)=J] - (omega * s_iJ) / a_ii, s_iJ = (A P_tent)[i,J]
+// omega = (4/3) / rho with rho the bit pattern k_rho left in *rhobits
 __global__ void k_smooth(int n, const int *rp, const int *ci, double *v, const int *agg, const double *d,
-                         double omega) {
+                         const unsigned long long *rhobits) {
+    const double omega = (4.0 / 3.0) / __longlong_as_double((long long)*rhobits);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         for (int p = rp[i]; p < rp[i + 1]; ++p) {
             const double t = omega * v[p];
@@ -1320,6 +1326,117 @@ int gwave(long rows) {
     return gsz(rows * 64);
 }
 
+// A batch of nb dense inverses of order n (see Setup::plan_dense): the sparse
+// inputs (densified into D) or none (D filled by the caller), the work buffers,
+// the inverses (back to back) and optionally their padded apply copies.
+struct DenseJob {
+    int n = 0, nb = 0;
+    const DCsr *mats[2] = {nullptr, nullptr};
+    double *D = nullptr, *ld = nullptr, *lam = nullptr, *acc = nullptr, *W = nullptr, *inv = nullptr;
+    DenseOp op[2];
+    int *bad = nullptr;
+};
+
+// The launches of a dense job on stream st: densify, tiled Cholesky (factor
+// and panel per tile column, trailing update), inverses of the diagonal tiles,
+// block forward substitution for W = L^{-1}, A^{-1} = W^T W, apply copies.
+// Touches no host state but the job, so it may run on another host thread.
+void launch_dense(const DenseJob &j, hipStream_t st) {
+    const int n = j.n, nb = j.nb;
+    const size_t nn = (size_t)n * n;
+    if (j.mats[0]) {
+        AMG_HIP(hipMemsetAsync(j.D, 0, sizeof(double) * nb * nn, st));
+        for (int b = 0; b < nb; ++b)
+            hipLaunchKernelGGL(k_densify, dim3(gwave(n)), dim3(kBlock), 0, st, n, j.mats[b]->rp, j.mats[b]->ci,
+                               j.mats[b]->v, (const uint8_t *)nullptr, (const uint8_t *)nullptr, j.D + b * nn);
+    }
+    for (int k0 = 0; k0 < n; k0 += kTB) {
+        const int rest = std::max(0, n - (k0 + kTB));
+        hipLaunchKernelGGL(k_potrf_panel, dim3(1 + ceil_div(rest, 64), 1, nb), dim3(64), 0, st, n, j.D, j.ld, k0,
+                           j.bad);
+        if (rest <= 0) break;
+        const int tiles = ceil_div(rest, kTB);
+        hipLaunchKernelGGL(k_syrk_tile, dim3(tiles * (tiles + 1) / 2, 1, nb), dim3(kBlock), 0, st, n, j.D, k0);
+    }
+    AMG_HIP(hipGetLastError());
+    const int T0 = ceil_div(n, kTB);
+    AMG_HIP(hipMemsetAsync(j.acc, 0, sizeof(double) * nb * nn, st));
+    AMG_HIP(hipMemsetAsync(j.W, 0, sizeof(double) * nb * nn, st));
+    hipLaunchKernelGGL(k_trtri_tile, dim3(T0, 1, nb), dim3(64), 0, st, n, j.ld, j.lam);
+    for (int k = 0; k < T0; ++k)
+        hipLaunchKernelGGL(k_trinv_step, dim3(std::max(1, T0 - k - 1), k + 1, nb), dim3(kBlock), 0, st, n, k, j.D,
+                           j.lam, j.acc, j.W);
+    hipLaunchKernelGGL(k_wtw, dim3(T0 * (T0 + 1) / 2, 1, nb), dim3(kBlock), 0, st, n, j.W, j.inv);
+    for (int b = 0; b < nb; ++b)
+        if (j.op[b].m64)
+            hipLaunchKernelGGL(k_pad_dense, dim3(gsz((long)n * j.op[b].ld)), dim3(kBlock), 0, st, n, j.op[b].ld,
+                               j.inv + b * nn, j.op[b].m64, j.op[b].m32);
+    AMG_HIP(hipGetLastError());
+}
+
+// Host thread that issues the side stream's launches, job after job, so that
+// the calling thread keeps feeding the main stream.  A job first makes the
+// side stream wait for the event that the calling thread recorded on the
+// main stream when it handed the job over.
+struct SideWorker {
+    std::mutex m;
+    std::condition_variable cv;
+    std::deque<std::pair<hipEvent_t, DenseJob>> q;
+    bool done = false;
+    std::thread th;
+    hipStream_t st = nullptr;
+    int code = 0;
+    std::string err;
+
+    void push(hipEvent_t ev, const DenseJob &j) {
+        if (!th.joinable()) {
+            int dev = 0;
+            AMG_HIP(hipGetDevice(&dev));
+            th = std::thread([this, dev] { run(dev); });
+        }
+        {
+            std::lock_guard<std::mutex> g(m);
+            q.emplace_back(ev, j);
+        }
+        cv.notify_one();
+    }
+    void run(int dev) {
+        (void)hipSetDevice(dev);
+        for (;;) {
+            std::pair<hipEvent_t, DenseJob> job;
+            {
+                std::unique_lock<std::mutex> lk(m);
+                cv.wait(lk, [&] { return done || !q.empty(); });
+                if (q.empty()) return;
+                job = q.front();
+                q.pop_front();
+            }
+            if (code) continue;  // after a failure the rest is skipped
+            try {
+                AMG_HIP(hipStreamWaitEvent(st, job.first, 0));
+                launch_dense(job.second, st);
+            } catch (const Error &e) {
+                code = e.code;
+                err = e.msg;
+            }
+        }
+    }
+    // every job issued (the thread ends); reports the first failure
+    void finish() {
+        stop();
+        if (code) fail(code, err);
+    }
+    void stop() {
+        {
+            std::lock_guard<std::mutex> g(m);
+            done = true;
+        }
+        cv.notify_one();
+        if (th.joinable()) th.join();
+    }
+    ~SideWorker() { stop(); }
+};
+
 struct Setup {
     Ctx &c;
     hipStream_t s;
@@ -1355,14 +1472,15 @@ struct Setup {
         if (f[kFlagFill]) fail(AMG_ERR_CAPACITY, "sparse product: output column lost in the fill");
     }
 
-    // out[0..n] exclusive scan of cnt[0..n-1]; returns the total
-    int scan(const int *cnt, int *out, int n) {
+    // out[0..n] exclusive scan of cnt[0..n-1]; the total is left in
+    // iscratch[8] and returned when read (else -1: no wait for the device)
+    int scan(const int *cnt, int *out, int n, bool read = true) {
         const int nb = std::max(1, ceil_div(n, kScanPer));
         int *bsum = c.arena.alloc<int>(nb);
         hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum);
         hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, nb, bsum, c.iscratch + 8);
         hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum, out, c.iscratch + 8);
-        const int total = read_int(c.iscratch + 8);
+        const int total = read ? read_int(c.iscratch + 8) : -1;
         c.arena.release(bsum);
         return total;
     }
@@ -1423,19 +1541,24 @@ struct Setup {
         else if (lpr == 32) count_sub(k_spgemm_count_sub<32, 256>);
         else count_sub(k_spgemm_count_sub<64, 512>);
         check_kernels();
+        // the row offsets before the one read of the pass's results: the
+        // total (iscratch[8]) arrives with the maxima (a row counted again
+        // below makes the first scan moot and it is redone)
+        scan(cnt, C.rp, A.n, false);
         AMG_HIP(hipMemcpyAsync(c.hiscr, c.iscratch + 4, 9 * sizeof(int), hipMemcpyDeviceToHost, s));
         AMG_HIP(hipStreamSynchronize(s));
         if (c.hiscr[8]) {
             if (wide) count(k_spgemm_count<4, kHS>, 1);
             else count(k_spgemm_count<1, kHS>, 1);
             check_kernels();
+            scan(cnt, C.rp, A.n, false);
             AMG_HIP(hipMemcpyAsync(c.hiscr, c.iscratch + 4, 9 * sizeof(int), hipMemcpyDeviceToHost, s));
             AMG_HIP(hipStreamSynchronize(s));
         }
         if (c.hiscr[0])
             fail(AMG_ERR_CAPACITY, "sparse product row exceeds " + std::to_string(kMaxRowOut) + " columns");
         const int umax = c.hiscr[6], bmax = c.hiscr[7];
-        C.nnz = scan(cnt, C.rp, A.n);
+        C.nnz = c.hiscr[4];
         C.ci = c.arena.alloc<int>(C.nnz);
         C.v = c.arena.alloc<double>(C.nnz);
         if (wide) {
@@ -1512,7 +1635,7 @@ struct Setup {
         int *tci = c.arena.alloc<int>(T.nnz);
         double *tv = c.arena.alloc<double>(T.nnz);
         hipLaunchKernelGGL(k_t_count, dim3(gsz(A.n)), dim3(kBlock), 0, s, A.n, A.rp, A.ci, cnt);
-        scan(cnt, T.rp, T.n);
+        scan(cnt, T.rp, T.n, false);  // the total is A.nnz
         hipLaunchKernelGGL(k_t_place, dim3(gsz(A.n)), dim3(kBlock), 0, s, A.n, A.rp, A.ci, A.v, T.rp, fill, tci,
                            tv);
         const int waves_g = std::min(4096, std::max(1, ceil_div(T.n, 4)));
@@ -1614,10 +1737,6 @@ struct Setup {
         zero(mb, sizeof(unsigned long long));
         hipLaunchKernelGGL(k_rho, dim3(gsz(n)), dim3(kBlock), 0, s, n, dl1, d, mask, mb);
         check_kernels();
-        AMG_HIP(hipMemcpyAsync(c.hscr, c.dscratch, sizeof(double), hipMemcpyDeviceToHost, s));
-        AMG_HIP(hipStreamSynchronize(s));
-        L0.rho = c.hscr[0];
-        L0.omega = (4.0 / 3.0) / L0.rho;
         c.arena.release(dl1);
         // tentative prolongator, then S = (I - omega D^{-1} A) P_tent
         DCsr P;
@@ -1625,12 +1744,14 @@ struct Setup {
         P.m = nc;
         P.rp = c.arena.alloc<int>(n + 1);
         hipLaunchKernelGGL(k_ptent_count, dim3(gsz(n)), dim3(kBlock), 0, s, n, L0.agg, cnt);
-        P.nnz = scan(cnt, P.rp, n);
+        scan(cnt, P.rp, n, false);
+        P.nnz = n;  // at most one entry per row: an upper bound is enough here
         P.ci = c.arena.alloc<int>(P.nnz);
         P.v = c.arena.alloc<double>(P.nnz);
         hipLaunchKernelGGL(k_ptent_fill, dim3(gsz(n)), dim3(kBlock), 0, s, n, L0.agg, P.rp, P.ci, P.v);
         DCsr S = spgemm(A, P);
-        hipLaunchKernelGGL(k_smooth, dim3(gsz(n)), dim3(kBlock), 0, s, n, S.rp, S.ci, S.v, L0.agg, d, L0.omega);
+        hipLaunchKernelGGL(k_smooth, dim3(gsz(n)), dim3(kBlock), 0, s, n, S.rp, S.ci, S.v, L0.agg, d,
+                           (const unsigned long long *)mb);
         check_kernels();
         for (void *p : {(void *)P.rp, (void *)P.ci, (void *)P.v, (void *)cnt, (void *)d}) c.arena.release(p);
         L0.S = S;
@@ -1688,57 +1809,69 @@ struct Setup {
         return d;
     }
 
-    // dense inverses of nb sparse SPD matrices of one order, returned back to
-    // back (inverse b at the result + b * n * n)
-    double *dense_inverse(std::initializer_list<const DCsr *> mats, std::vector<void *> *defer = nullptr) {
-        const int nb = (int)mats.size();
-        const int n = (*mats.begin())->n;
-        const size_t nn = (size_t)n * n;
-        double *D = c.arena.alloc<double>(nb * nn);
-        zero(D, sizeof(double) * nb * nn);
+    // A batch of dense inverses: its buffers come from the arena here, on the
+    // calling thread; launch_dense issues its work on any stream, from any
+    // host thread.
+    DenseJob plan_dense(std::initializer_list<const DCsr *> mats, bool ops) {
+        DenseJob j;
+        j.nb = (int)mats.size();
+        j.n = (*mats.begin())->n;
         int b = 0;
-        for (const DCsr *A : mats) {
-            hipLaunchKernelGGL(k_densify, dim3(gwave(n)), dim3(kBlock), 0, s, n, A->rp, A->ci, A->v,
-                               (const uint8_t *)nullptr, (const uint8_t *)nullptr, D + b * nn);
-            ++b;
-        }
-        return factor_invert(D, n, nb, defer);
+        for (const DCsr *A : mats) j.mats[b++] = A;
+        j.D = c.arena.alloc<double>((size_t)j.nb * j.n * j.n);
+        plan_rest(j, ops);
+        return j;
     }
-
-    // Cholesky factors of the nb matrices in D (overwritten), then their
-    // inverses W^T W, W = L^{-1}, in a new buffer.  The temporaries (D
-    // included) go back to the arena, or to *defer when the work runs on a
-    // stream that the arena's reuse does not follow.
-    double *factor_invert(double *D, int n, int nb = 1, std::vector<void *> *defer = nullptr) {
-        const size_t nn = (size_t)n * n;
-        const int T0 = ceil_div(n, kTB);
-        double *ld = c.arena.alloc<double>((size_t)nb * T0 * kTB * kTB);  // factored diagonal tiles
-        for (int k0 = 0; k0 < n; k0 += kTB) {
-            const int rest = std::max(0, n - (k0 + kTB));
-            hipLaunchKernelGGL(k_potrf_panel, dim3(1 + ceil_div(rest, 64), 1, nb), dim3(64), 0, s, n, D, ld, k0,
-                               c.iscratch + kFlagChol);
-            if (rest <= 0) break;
-            const int tiles = ceil_div(rest, kTB);
-            hipLaunchKernelGGL(k_syrk_tile, dim3(tiles * (tiles + 1) / 2, 1, nb), dim3(kBlock), 0, s, n, D, k0);
-        }
-        check_kernels();
-        double *lam = c.arena.alloc<double>((size_t)nb * T0 * kTB * kTB);
-        double *acc = c.arena.alloc<double>(nb * nn);
-        double *W = c.arena.alloc<double>(nb * nn);
-        zero(acc, sizeof(double) * nb * nn);
-        zero(W, sizeof(double) * nb * nn);
-        hipLaunchKernelGGL(k_trtri_tile, dim3(T0, 1, nb), dim3(64), 0, s, n, ld, lam);
-        for (int k = 0; k < T0; ++k)
-            hipLaunchKernelGGL(k_trinv_step, dim3(std::max(1, T0 - k - 1), k + 1, nb), dim3(kBlock), 0, s, n, k,
-                               D, lam, acc, W);
-        double *inv = c.arena.alloc<double>(nb * nn);
-        hipLaunchKernelGGL(k_wtw, dim3(T0 * (T0 + 1) / 2, 1, nb), dim3(kBlock), 0, s, n, W, inv);
-        check_kernels();
-        for (void *p : {(void *)D, (void *)ld, (void *)lam, (void *)acc, (void *)W}) {
+    DenseJob plan_factor(double *D, int n) {  // D holds the matrix already
+        DenseJob j;
+        j.nb = 1;
+        j.n = n;
+        j.D = D;
+        plan_rest(j, false);
+        return j;
+    }
+    void plan_rest(DenseJob &j, bool ops) {
+        const size_t nn = (size_t)j.n * j.n;
+        const int T0 = ceil_div(j.n, kTB);
+        j.ld = c.arena.alloc<double>((size_t)j.nb * T0 * kTB * kTB);
+        j.lam = c.arena.alloc<double>((size_t)j.nb * T0 * kTB * kTB);
+        j.acc = c.arena.alloc<double>(j.nb * nn);
+        j.W = c.arena.alloc<double>(j.nb * nn);
+        j.inv = c.arena.alloc<double>(j.nb * nn);
+        j.bad = c.iscratch + kFlagChol;
+        if (ops)
+            for (int b = 0; b < j.nb; ++b) {
+                DenseOp &d = j.op[b];
+                d.n = j.n;
+                d.ld = ceil_div(j.n, 64) * 64;
+                d.m64 = c.arena.alloc<double>((size_t)j.n * d.ld);
+                d.m32 = c.arena.alloc<float>((size_t)j.n * d.ld);
+            }
+    }
+    // the temporaries (D included) back to the arena, or to *defer when the
+    // work runs on a stream that the arena's reuse does not follow
+    void release_job(DenseJob &j, std::vector<void *> *defer) {
+        for (void *p : {(void *)j.D, (void *)j.ld, (void *)j.lam, (void *)j.acc, (void *)j.W}) {
             if (defer) defer->push_back(p);
             else c.arena.release(p);
         }
-        return inv;
+    }
+
+    // dense inverses of nb sparse SPD matrices of one order, returned back to
+    // back (inverse b at the result + b * n * n), on this stream
+    double *dense_inverse(std::initializer_list<const DCsr *> mats) {
+        DenseJob j = plan_dense(mats, false);
+        launch_dense(j, s);
+        release_job(j, nullptr);
+        return j.inv;
+    }
+
+    // inverse of the SPD matrix in D (overwritten by its factor)
+    double *factor_invert(double *D, int n) {
+        DenseJob j = plan_factor(D, n);
+        launch_dense(j, s);
+        release_job(j, nullptr);
+        return j.inv;
     }
 };
 
@@ -1796,18 +1929,27 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
     };
     std::vector<Early> early(c.lev.capacity());
     std::vector<void *> deferred;
-    Setup sd(c, c.side);
-    bool forked = false;
-    auto fork_dense = [&](int jl, bool with_mass) {  // with_mass: also M_j^{-1}
-        AMG_HIP(hipEventRecord(c.side_ev[0], s));
-        AMG_HIP(hipStreamWaitEvent(c.side, c.side_ev[0], 0));
-        forked = true;
+    struct EvList {  // destroyed after the worker below has ended
+        std::vector<hipEvent_t> v;
+        ~EvList() {
+            for (hipEvent_t e : v) (void)hipEventDestroy(e);
+        }
+    } fork_ev;
+    SideWorker side;
+    side.st = c.side;
+    auto fork_dense = [&](int jl) {  // A_j^{-1} and M_j^{-1}
         Level &Lv = c.lev[jl];
+        DenseJob job = su.plan_dense({&Lv.A, &Lv.M}, true);
+        hipEvent_t ev = nullptr;
+        AMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        fork_ev.v.push_back(ev);
+        AMG_HIP(hipEventRecord(ev, s));
+        side.push(ev, job);
+        su.release_job(job, &deferred);
         Early &e = early[jl];
-        e.inv = with_mass ? sd.dense_inverse({&Lv.A, &Lv.M}, &deferred) : sd.dense_inverse({&Lv.A}, &deferred);
-        e.dA = sd.dense_op(e.inv, Lv.n);
-        if (with_mass) e.dM = sd.dense_op(e.inv + (size_t)Lv.n * Lv.n, Lv.n);
-        su.check_kernels();
+        e.inv = job.inv;
+        e.dA = job.op[0];
+        e.dM = job.op[1];
     };
     int j = 0;
     while (true) {
@@ -1817,7 +1959,7 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
         const bool last = L.n <= c.o.max_coarse || j + 1 >= c.o.max_levels;
         // exact A_j and M_j solves (the coarsest level included: its A_j is
         // dense in any case, and its mass solves become exact too)
-        if (j >= 1 && L.n <= c.o.dense_solve_max) fork_dense(j, true);
+        if (j >= 1 && L.n <= c.o.dense_solve_max) fork_dense(j);
         if (last) break;
         if (!su.coarsen(j)) break;
         ++j;
@@ -1879,7 +2021,8 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
         Lv.dA = e.dA;
         Lv.dM = e.dM;
     }
-    if (forked) {  // join the side stream
+    if (!fork_ev.v.empty()) {  // join the side stream
+        side.finish();
         AMG_HIP(hipEventRecord(c.side_ev[1], c.side));
         AMG_HIP(hipStreamWaitEvent(s, c.side_ev[1], 0));
         for (void *p : deferred) c.arena.release(p);
