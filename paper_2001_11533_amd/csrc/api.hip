@@ -86,7 +86,7 @@ void alloc_workspaces(Ctx &c) {
     c.ws.assign(c.L, LevelWs{});
     const bool mixed = c.o.inner_precision == 32;
     ScalSetup ss;
-    ss.host.assign((size_t)c.L * (mixed ? 5 : 3) + 1, CgScal{});
+    ss.host.assign((size_t)c.L * (mixed ? 6 : 4) + 1, CgScal{});
     ss.dev = a.alloc<CgScal>(ss.host.size());
     for (int l = 0; l < c.L; ++l) {
         LevelWs &w = c.ws[l];
@@ -94,6 +94,7 @@ void alloc_workspaces(Ctx &c) {
         alloc_cg(c, w.in64, m, ss);
         alloc_cg(c, w.mass, m, ss);
         alloc_cg(c, w.hcg, m, ss);
+        alloc_cg(c, w.mass2, m, ss);
         alloc_vc(a, w.vc64, m);
         if (mixed) {
             alloc_cg(c, w.inmx, m, ss);
@@ -244,6 +245,7 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
     int rc = guarded(nullptr, [&]() {
         c.lev.reserve(o.max_levels + 1);
         for (auto &p : c.part) p = c.arena.alloc<double>((size_t)2 * 16 * kMaxGrid);
+        for (auto &p : c.part2) p = c.arena.alloc<double>((size_t)2 * 16 * kMaxGrid);
         c.dscratch = c.arena.alloc<double>(64);
         c.iscratch = c.arena.alloc<int>(64);
         AMG_HIP(hipHostMalloc((void **)&c.hsc, sizeof(CgScal), hipHostMallocDefault));
@@ -254,6 +256,8 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
         AMG_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
         for (auto &e : c.poll_ev) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         for (auto &e : c.side_ev) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (auto &e : c.poll_ev2) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        for (auto &e : c.mass_ev) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         build_hierarchy(c, *A, *M, dirichlet);
         form_dense_hessian(c, o.hess_levels > 0 ? o.hess_levels : c.L);
         alloc_workspaces(c);
@@ -282,6 +286,10 @@ int amg_destroy(amg_ctx *ctx) {
     for (auto e : c.poll_ev)
         if (e) (void)hipEventDestroy(e);
     for (auto e : c.side_ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto e : c.poll_ev2)
+        if (e) (void)hipEventDestroy(e);
+    for (auto e : c.mass_ev)
         if (e) (void)hipEventDestroy(e);
     if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
     if (c.side) (void)hipStreamDestroy(c.side);

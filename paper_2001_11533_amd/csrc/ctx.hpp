@@ -41,9 +41,11 @@ template <typename T> struct CgWs {
     CgScal *sc = nullptr;
     Mail *hmail = nullptr;  // host view of the mailbox the finalize kernels write
     int pred = 0;  // iteration count of the previous solve (poll schedule)
+    int run_it = 0; // iterations launched by a started (phase 1) solve
     int fused = -1; // 1: each iteration's finalize runs in the next iteration's first kernel
     // captured graphs: first preconditioner application, iteration p0->p1, iteration p1->p0
     hipGraphExec_t g0 = nullptr, ga = nullptr, gb = nullptr;
+    hipGraphExec_t g8 = nullptr;  // Jacobi CG: eight iterations (ga gb ga gb ...) in one launch
 };
 
 template <typename T> struct VcWs {
@@ -53,6 +55,7 @@ template <typename T> struct VcWs {
 
 struct LevelWs {
     CgWs<double> in64, mass, hcg;  // inner A-solves, mass solves, coarsest-Hessian CG
+    CgWs<double> mass2;            // mass solves run on the side stream
     CgWs<double> inmx;             // inner A-solves preconditioned by the float32 V-cycle
     CgWs<float> in32;
     VcWs<double> vc64;
@@ -80,6 +83,13 @@ struct Ctx {
     std::vector<hipGraphExec_t> graphs; // every instantiated graph (freed with the context)
     static constexpr int kPollRing = 4;
     hipEvent_t poll_ev[kPollRing] = {nullptr, nullptr, nullptr, nullptr};
+    // solve phase: a mass solve on the side stream beside the main work, with
+    // its own reduction partials and polling events; its fork and join events
+    double *part2[3] = {nullptr, nullptr, nullptr};
+    int pgrid2[3] = {0, 0, 0};
+    hipEvent_t poll_ev2[kPollRing] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t mass_ev[2] = {nullptr, nullptr};
+    bool side_busy = false;
     amg_opts o{};
     Arena arena;
     int N = 0;

@@ -35,15 +35,22 @@ constexpr long kFusedPartials = 4096;
 template <int NB> struct Solver {
     Ctx &c;
     hipStream_t s;
-    explicit Solver(Ctx &cc) : c(cc), s(cc.stream) {}
+    // reduction partials and polling events of this solver's stream (a solver
+    // on the side stream has its own, so its CGs can run beside the main one)
+    double **part;
+    int *pgrid;
+    hipEvent_t *pev;
+    explicit Solver(Ctx &cc) : c(cc), s(cc.stream), part(cc.part), pgrid(cc.pgrid), pev(cc.poll_ev) {}
+    Solver(Ctx &cc, hipStream_t st, double **pt, int *pg, hipEvent_t *ev)
+        : c(cc), s(st), part(pt), pgrid(pg), pev(ev) {}
 
     // ---------------- launch helpers ----------------
     // Reductions write their partials into one of three buffers (pbuf) so that
     // a finalize kernel can combine the partials of two earlier kernels.
     template <int NV, class FIN> void finish(int pbuf, FIN fin, const int *stop) {
         if constexpr (NV > 0 && !std::is_same_v<FIN, NoFin>)
-            hipLaunchKernelGGL((fin_kernel<NV, NB, FIN>), dim3(1), dim3(kFinBlock), 0, s, c.part[pbuf],
-                               c.pgrid[pbuf], fin, stop);
+            hipLaunchKernelGGL((fin_kernel<NV, NB, FIN>), dim3(1), dim3(kFinBlock), 0, s, part[pbuf],
+                               pgrid[pbuf], fin, stop);
     }
 
     // workgroups of a reducing product with A (the partials it leaves)
@@ -61,8 +68,8 @@ template <int NB> struct Solver {
             else sv = vals == A.v ? A.sl_v : nullptr;
             if (A.sl_off && sv) {
                 const int g = grid_rows(A.nsl, kBlock / 64, NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
-                Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
-                if (NV > 0) c.pgrid[pbuf] = g;
+                Reducer<(NV > 0 ? NV : 1), NB> red{part[pbuf]};
+                if (NV > 0) pgrid[pbuf] = g;
                 hipLaunchKernelGGL((sell_kernel<T, NV, GX, EP, PRO>), dim3(g), dim3(kBlock), 0, s, A.n, A.nsl,
                                    A.sl_off, A.sl_ci, sv, gx, ep, red, stop, pro);
                 finish<NV>(pbuf, fin, stop);
@@ -71,8 +78,8 @@ template <int NB> struct Solver {
         }
         const Geo geo = make_geo<NB>(A.nnz, A.n);
         const int g = grid_rows(A.n, geo.rpb(), NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
-        Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
-        if (NV > 0) c.pgrid[pbuf] = g;
+        Reducer<(NV > 0 ? NV : 1), NB> red{part[pbuf]};
+        if (NV > 0) pgrid[pbuf] = g;
         if (A.n == c.N)
             hipLaunchKernelGGL((spmv_kernel<T, NB, NV, GX, EP, 1, PRO>), dim3(g), dim3(kBlock), 0, s, A.n, A.rp,
                                A.ci, vals, gx, ep, geo, red, stop, pro);
@@ -91,16 +98,16 @@ template <int NB> struct Solver {
         while (G * NB < 64 && G < m / kSpmvUnroll) G <<= 1;
         const int llpr = ilog2(G * NB);
         const int g = grid_rows(Tm.n, kBlock >> llpr, NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
-        Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
-        if (NV > 0) c.pgrid[pbuf] = g;
+        Reducer<(NV > 0 ? NV : 1), NB> red{part[pbuf]};
+        if (NV > 0) pgrid[pbuf] = g;
         hipLaunchKernelGGL((tpro_kernel<T, NB, NV, EP>), dim3(g), dim3(kBlock), 0, s, Tm.n, Tm.rp, Tm.ci,
                            avals<T>(Tm), tsvals<T>(Lv), e, ep, llpr, red, stop);
     }
 
     template <int NV, class OP, class FIN> void elem(int n, OP op, FIN fin, const int *stop, int pbuf = 0) {
         const int g = grid_rows((long)n * NB, kBlock, NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
-        Reducer<(NV > 0 ? NV : 1), NB> red{c.part[pbuf]};
-        if (NV > 0) c.pgrid[pbuf] = g;
+        Reducer<(NV > 0 ? NV : 1), NB> red{part[pbuf]};
+        if (NV > 0) pgrid[pbuf] = g;
         if (n == c.N)
             hipLaunchKernelGGL((elem_kernel<NB, NV, OP, 1>), dim3(g), dim3(kBlock), 0, s, n, op, red, stop);
         else
@@ -115,21 +122,21 @@ template <int NB> struct Solver {
                    const int *stop, float *r32 = nullptr, float *x32 = nullptr, const float *d32 = nullptr,
                    double s0 = 1.0, int fused = 0) {
         const int g = grid_rows((long)n * NB, kBlock, red_grid_max<NB>());
-        Reducer<JAC ? 2 : 1, NB> red{c.part[1]};
+        Reducer<JAC ? 2 : 1, NB> red{part[1]};
         // alpha: every workgroup sums the p.q partials itself when they are few,
         // else one finalize kernel forms it first
-        int nblk_pq = c.pgrid[0];
+        int nblk_pq = pgrid[0];
         if ((long)nblk_pq * NB > 2048) {
             finish<1>(0, FinAlpha<NB>{sc, outer, fused}, stop);
             nblk_pq = 0;
         }
-        c.pgrid[1] = g;
+        pgrid[1] = g;
         if (n == c.N)
             hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 1>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, x32, d32, s0, fused, p, q, dinv,
-                               sc, c.part[0], nblk_pq, outer, red, stop);
+                               sc, part[0], nblk_pq, outer, red, stop);
         else
             hipLaunchKernelGGL((cg_update_kernel<T, NB, JAC, 0>), dim3(g), dim3(kBlock), 0, s, n, x, r, z, r32, x32, d32, s0, fused, p, q, dinv,
-                               sc, c.part[0], nblk_pq, outer, red, stop);
+                               sc, part[0], nblk_pq, outer, red, stop);
     }
 
     template <typename T> void dense_apply(const DenseOp &d, const T *b, T *x, const int *stop) {
@@ -155,8 +162,8 @@ template <int NB> struct Solver {
     }
 
     void wait_mail() {
-        AMG_HIP(hipEventRecord(c.poll_ev[0], s));
-        AMG_HIP(hipEventSynchronize(c.poll_ev[0]));
+        AMG_HIP(hipEventRecord(pev[0], s));
+        AMG_HIP(hipEventSynchronize(pev[0]));
     }
 
     template <typename T> CgWs<T> &inws(int l) {
@@ -282,10 +289,10 @@ template <int NB> struct Solver {
 
     // The finalize kernels write each CG's mailbox in pinned host memory; an
     // event marks how far the stream has run, so no copy is enqueued.
-    void post_flag(int slot) { AMG_HIP(hipEventRecord(c.poll_ev[slot], s)); }
+    void post_flag(int slot) { AMG_HIP(hipEventRecord(pev[slot], s)); }
 
     template <typename T> bool wait_flag(int slot, const CgWs<T> &w) {
-        AMG_HIP(hipEventSynchronize(c.poll_ev[slot]));
+        AMG_HIP(hipEventSynchronize(pev[slot]));
         return __atomic_load_n(&w.hmail->all_conv, __ATOMIC_ACQUIRE) != 0;
     }
 
@@ -306,7 +313,7 @@ template <int NB> struct Solver {
         const int n = A.n;
         const int *stop = &w.sc->all_conv;
         const int fused = w.fused;
-        const FusedFin<NB, JAC> pro{w.sc, c.part[1], c.pgrid[1], c.part[2], c.pgrid[2]};
+        const FusedFin<NB, JAC> pro{w.sc, part[1], pgrid[1], part[2], pgrid[2]};
         // the first kernel: (fused: the previous finalize,) p = z + beta pold, q = A p, p.q partials
         auto first = [&](auto gx, auto ep) {
             if (fused) spmv<T, 1>(A, vals, gx, ep, NoFin{}, stop, 0, pro);
@@ -320,8 +327,8 @@ template <int NB> struct Solver {
                                 vcws<float>(c.ws[j]).x, c.lev[j].dl1inv32, first_scale(), fused);
             vcycle<float>(j, r32, z32, true, stop);
             if (!fused)
-                hipLaunchKernelGGL((fin2_kernel<NB, FinUB<NB>>), dim3(1), dim3(kFinBlock), 0, s, c.part[1],
-                                   c.pgrid[1], c.part[2], c.pgrid[2], FinUB<NB>{w.sc}, stop);
+                hipLaunchKernelGGL((fin2_kernel<NB, FinUB<NB>>), dim3(1), dim3(kFinBlock), 0, s, part[1],
+                                   pgrid[1], part[2], pgrid[2], FinUB<NB>{w.sc}, stop);
             return;
         }
         first(GZBP<T, NB>{w.z, pold, w.sc}, ECgQ<T, NB>{w.z, pold, pnew, w.q, w.sc});
@@ -336,8 +343,8 @@ template <int NB> struct Solver {
         } else {
             vcycle<T>(j, w.r, w.z, true, stop);
             if (!fused)
-                hipLaunchKernelGGL((fin2_kernel<NB, FinUB<NB>>), dim3(1), dim3(kFinBlock), 0, s, c.part[1],
-                                   c.pgrid[1], c.part[2], c.pgrid[2], FinUB<NB>{w.sc}, stop);
+                hipLaunchKernelGGL((fin2_kernel<NB, FinUB<NB>>), dim3(1), dim3(kFinBlock), 0, s, part[1],
+                                   pgrid[1], part[2], pgrid[2], FinUB<NB>{w.sc}, stop);
         }
     }
 
@@ -346,17 +353,21 @@ template <int NB> struct Solver {
     template <bool JAC> void fused_tail(CgWs<float> &w) { fused_tail_impl<JAC>(w.sc); }
     template <bool JAC> void fused_tail_impl(CgScal *sc) {
         if constexpr (JAC)
-            hipLaunchKernelGGL((fin_kernel<2, NB, FinFusedTail<NB, true>>), dim3(1), dim3(kFinBlock), 0, s, c.part[1],
-                               c.pgrid[1], FinFusedTail<NB, true>{sc}, &sc->all_conv);
+            hipLaunchKernelGGL((fin_kernel<2, NB, FinFusedTail<NB, true>>), dim3(1), dim3(kFinBlock), 0, s, part[1],
+                               pgrid[1], FinFusedTail<NB, true>{sc}, &sc->all_conv);
         else
             hipLaunchKernelGGL((fin2_kernel<NB, FinFusedTail<NB, false>>), dim3(1), dim3(kFinBlock), 0, s,
-                               c.part[1], c.pgrid[1], c.part[2], c.pgrid[2], FinFusedTail<NB, false>{sc},
+                               part[1], pgrid[1], part[2], pgrid[2], FinFusedTail<NB, false>{sc},
                                &sc->all_conv);
     }
 
+    // phase 0: the whole solve; 1: start only (initialisation and the first
+    // batch, margin more iterations than the previous solve needed, no wait
+    // for the device); 2: finish a started solve (the polling loop from where
+    // phase 1 left it, on the same solver's stream)
     template <typename T, bool JAC, bool MIX = false>
     int cg(int j, const DCsr &A, const T *vals, const double *mdinv, CgWs<T> &w, const T *b, T *x, double rtol,
-           int maxit, int nlive) {
+           int maxit, int nlive, int phase = 0, int margin = 0) {
         const int n = A.n;
         const int *stop = &w.sc->all_conv;
         const T *dinv = nullptr;
@@ -382,8 +393,9 @@ template <int NB> struct Solver {
             w.fused = q <= kFusedPartials ? 1 : 0;
         }
         const int fused = w.fused;
-        elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, w.p0, z0, d0, r32, x32, d32, first_scale()},
-                          FinInit<NB, JAC>{w.sc, rtol, nlive, (void *)x, fused}, nullptr, fused ? 1 : 0);
+        if (phase != 2)
+            elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, w.p0, z0, d0, r32, x32, d32, first_scale()},
+                              FinInit<NB, JAC>{w.sc, rtol, nlive, (void *)x, fused}, nullptr, fused ? 1 : 0);
         const bool graphs = c.o.use_graphs != 0;
         auto first_precond = [&] {
             if constexpr (MIX) vcycle<float>(j, c.ws[j].b32, c.ws[j].d32, true, stop);
@@ -394,12 +406,23 @@ template <int NB> struct Solver {
             if constexpr (!JAC) w.g0 = capture(first_precond);
             w.ga = capture([&] { cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p0, w.p1); });
             w.gb = capture([&] { cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p1, w.p0); });
+            // a mass iteration is two small kernels, faster than the host issues
+            // one launch per iteration: its first batch goes out eight at a time
+            if constexpr (JAC)
+                w.g8 = capture([&] {
+                    for (int k = 0; k < 8; k += 2) {
+                        cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p0, w.p1);
+                        cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p1, w.p0);
+                    }
+                });
         }
         if constexpr (!JAC) {
-            if (graphs) launch(w.g0);
-            else first_precond();
+            if (phase != 2) {
+                if (graphs) launch(w.g0);
+                else first_precond();
+            }
         }
-        int it = 0;
+        int it = phase == 2 ? w.run_it : 0;
         auto step = [&]() {
             if (graphs) launch((it & 1) ? w.gb : w.ga);
             else if (it & 1) cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p1, w.p0);
@@ -411,17 +434,30 @@ template <int NB> struct Solver {
         // out at once; then the host keeps kAhead iterations in flight beyond
         // the last one it has seen, reading the mailbox after an event.
         constexpr int kAhead = 1, kRing = Ctx::kPollRing;
-        const int first = std::min(std::max(1, w.pred + (fused ? 1 : 0)), maxit);
-        while (it < first) step();
-        post_flag(0);
         int posted = 1, seen = 0;
+        if (phase != 2) {
+            const int first = std::min(std::max(1, w.pred + (fused ? 1 : 0) + margin), maxit);
+            while (it < first) {
+                if (graphs && w.g8 && (it & 1) == 0 && first - it >= 8) {
+                    launch(w.g8);
+                    it += 8;
+                } else {
+                    step();
+                }
+            }
+            post_flag(0);
+            if (phase == 1) {
+                w.run_it = it;
+                return 0;
+            }
+        }
         bool done = false;
         while (!done) {
             if (it >= maxit) {
                 if (fused) fused_tail<JAC>(w);
                 post_flag(posted % kRing);
                 ++posted;
-                AMG_HIP(hipEventSynchronize(c.poll_ev[(posted - 1) % kRing]));
+                AMG_HIP(hipEventSynchronize(pev[(posted - 1) % kRing]));
                 done = __atomic_load_n(&w.hmail->all_conv, __ATOMIC_ACQUIRE) != 0;
                 break;
             }
@@ -435,7 +471,7 @@ template <int NB> struct Solver {
             ++seen;
         }
         // the last posted event covers every launch: the mailbox is final
-        AMG_HIP(hipEventSynchronize(c.poll_ev[(posted - 1) % kRing]));
+        AMG_HIP(hipEventSynchronize(pev[(posted - 1) % kRing]));
         const Mail &m = *w.hmail;
         if (!m.all_conv) {
             w.pred = it;
@@ -508,6 +544,21 @@ template <int NB> struct Solver {
         c.st.mass_iters += it;
     }
 
+    // An iterative mass solve split in two on this (side) solver, in its own
+    // workspace: mass_start enqueues the initialisation and two more iterations
+    // than the previous such solve needed, without waiting; mass_finish
+    // iterates on until the mailbox reports convergence (usually it already
+    // has), so x is final once it returns and this stream has run.
+    void mass_start(int j, const double *b, double *x) {
+        Level &L = c.lev[j];
+        cg<double, true>(j, L.M, L.M.v, L.mdinv, c.ws[j].mass2, b, x, c.o.mass_rtol, c.o.mass_maxit, NB, 1, 2);
+    }
+    void mass_finish(int j, const double *b, double *x) {
+        Level &L = c.lev[j];
+        c.st.mass_iters +=
+            cg<double, true>(j, L.M, L.M.v, L.mdinv, c.ws[j].mass2, b, x, c.o.mass_rtol, c.o.mass_maxit, NB, 2);
+    }
+
     // y = M_which x at level j (0: M_u, 1: M_y = DMD, 2: M_yu = DM, 3: M_yu^T = MD);
     // with dotx, dots[c] = dotx_c . y_c (device)
     void mass_apply(int j, int which, const double *x, double *y, const double *dotx, double *dots) {
@@ -563,10 +614,32 @@ template <int NB> struct Solver {
         Level &Lv = c.lev[l];
         LevelWs &w1 = c.ws[l + 1];
         LevelWs &w0 = c.ws[l];
+        // M_l^{-1} r does not depend on the coarser work below: an iterative one
+        // runs on the side stream meanwhile (one such solve at a time)
+        const bool side = !mself && !Lv.Minv && !c.side_busy;
+        Solver<NB> S2(c, c.side, c.part2, c.pgrid2, c.poll_ev2);
+        struct Busy {  // released on every way out (the side solve writes only its own buffers)
+            bool &b;
+            bool on;
+            ~Busy() {
+                if (on) b = false;
+            }
+        } busy{c.side_busy, side};
+        if (side) {
+            c.side_busy = true;
+            AMG_HIP(hipEventRecord(c.mass_ev[0], s));
+            AMG_HIP(hipStreamWaitEvent(c.side, c.mass_ev[0], 0));
+            S2.mass_start(l, r, w0.ml_mself);
+        }
         spmv<double, 0>(Lv.St, Lv.St.v, GPlain<double, NB>{r}, EStore<double, NB>{w1.ml_in}, NoFin{}, nullptr);
         mass_solve(l + 1, w1.ml_in, w1.ml_mup);
         Bop(l + 1, w1.ml_in, w1.ml_out);
-        if (!mself) {
+        if (side) {
+            S2.mass_finish(l, r, w0.ml_mself);
+            AMG_HIP(hipEventRecord(c.mass_ev[1], c.side));
+            AMG_HIP(hipStreamWaitEvent(s, c.mass_ev[1], 0));
+            mself = w0.ml_mself;
+        } else if (!mself) {
             mass_solve(l, r, w0.ml_mself);
             mself = w0.ml_mself;
         }
