@@ -583,6 +583,14 @@ template <typename T, int NB, typename TZ = T> struct GZBP {  // p_k = z_k + bet
     }
 };
 
+// z_k alone: the CG product formed as A z + beta q_old (ECgQR)
+template <typename T, int NB, typename TZ = T> struct GZ {
+    const TZ *z;
+    __device__ void prep(int) {}
+    __device__ void set_beta(double) {}
+    __device__ T operator()(int k, int c) const { return (T)z[(size_t)k * NB + c]; }
+};
+
 // x_k = keep_k a_k + s b_k with keep_k = (mask == null || mask[k] == 0)
 template <int NB> struct GLin {
     const double *a;
@@ -887,6 +895,36 @@ template <typename T, int NB, typename TZ = T> struct ECgQ {
         p[o] = pi;
         q[o] = s;
         acc[0] += (double)pi * (double)s;
+    }
+};
+
+// CG direction and its product without gathering the direction:
+// p_i = z_i + beta pold_i and q_i = (A z)_i + beta qold_i, which is (A p)_i
+// since qold = A pold; q is updated in place (row i reads and writes only its
+// own entry), and beta = 0 takes (A z)_i alone; acc p.q
+template <typename T, int NB, typename TZ = T> struct ECgQR {
+    const TZ *z;
+    const T *pold;
+    T *p;
+    T *q;
+    const CgScal *sc;
+    T beta;
+    struct P {
+        T z, po, qo;
+    };
+    __device__ void prep(int c) { beta = (T)sc->s[c].beta; }
+    __device__ void set_beta(double b) { beta = (T)b; }
+    __device__ P load(int i, int c) const {
+        const size_t o = (size_t)i * NB + c;
+        return {(T)z[o], pold[o], q[o]};
+    }
+    template <int NV> __device__ void operator()(int i, int c, T s, const P &pr, double (&acc)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        const T pi = pr.z + beta * pr.po;
+        const T qi = beta != T(0) ? s + beta * pr.qo : s;
+        p[o] = pi;
+        q[o] = qi;
+        acc[0] += (double)pi * (double)qi;
     }
 };
 

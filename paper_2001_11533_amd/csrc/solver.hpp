@@ -322,7 +322,7 @@ template <int NB> struct Solver {
         if constexpr (MIX) {
             static_assert(std::is_same_v<T, double> && !JAC, "float32 preconditioning of the FP64 CG only");
             float *r32 = c.ws[j].b32, *z32 = c.ws[j].d32;
-            first(GZBP<T, NB, float>{z32, pold, w.sc}, ECgQ<T, NB, float>{z32, pold, pnew, w.q, w.sc});
+            first(GZ<T, NB, float>{z32}, ECgQR<T, NB, float>{z32, pold, pnew, w.q, w.sc});
             cg_update<T, false>(n, nullptr, w.r, nullptr, pnew, w.q, nullptr, w.sc, 0, stop, r32,
                                 vcws<float>(c.ws[j]).x, c.lev[j].dl1inv32, first_scale(), fused);
             vcycle<float>(j, r32, z32, true, stop);
@@ -331,7 +331,7 @@ template <int NB> struct Solver {
                                    pgrid[1], part[2], pgrid[2], FinUB<NB>{w.sc}, stop);
             return;
         }
-        first(GZBP<T, NB>{w.z, pold, w.sc}, ECgQ<T, NB>{w.z, pold, pnew, w.q, w.sc});
+        first(GZ<T, NB>{w.z}, ECgQR<T, NB>{w.z, pold, pnew, w.q, w.sc});
         if constexpr (JAC)
             cg_update<T, JAC>(n, nullptr, w.r, w.z, pnew, w.q, dinv, w.sc, 0, stop, nullptr, nullptr, nullptr, 1.0,
                               fused);
