@@ -22,6 +22,7 @@
 //              over ascending k, then S^T T over ascending i, lower triangle
 //              copied from the upper one
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <condition_variable>
 #include <deque>
@@ -429,12 +430,46 @@ constexpr int kSortLds = 1024;  // keys of a row staged in LDS (longer rows read
 __global__ __launch_bounds__(kBlock) void k_row_sort(int m, const int *rp, const int *ci_in, const double *v_in,
                                                      int *ci_out, double *v_out) {
     __shared__ int keys[kBlock / 64][kSortLds];
+    __shared__ int pos[kBlock / 64][kSortLds];
     const int lane = threadIdx.x % 64, wl = threadIdx.x / 64;
     const int w = (blockIdx.x * kBlock + threadIdx.x) / 64;
     const int nw = gridDim.x * kBlock / 64;
     for (int r = w; r < m; r += nw) {
         const int s = rp[r], e = rp[r + 1], len = e - s;
-        if (len <= kSortLds) {
+        if (len > 64 && len <= kSortLds) {
+            // bitonic sort of (key, position) by the wavefront, padded with
+            // INT_MAX keys to a power of two; the keys of a row are distinct
+            int P = 128;
+            while (P < len) P <<= 1;
+            int *kk = keys[wl], *pp = pos[wl];
+            for (int a = lane; a < P; a += 64) {
+                kk[a] = a < len ? ci_in[s + a] : INT_MAX;
+                pp[a] = a;
+            }
+            __syncwarp();
+            for (int k = 2; k <= P; k <<= 1)
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    for (int i = lane; i < P; i += 64) {
+                        const int ij = i ^ j;
+                        if (ij > i) {
+                            const int a = kk[i], b = kk[ij];
+                            if ((a > b) == ((i & k) == 0)) {
+                                kk[i] = b;
+                                kk[ij] = a;
+                                const int t = pp[i];
+                                pp[i] = pp[ij];
+                                pp[ij] = t;
+                            }
+                        }
+                    }
+                    __syncwarp();
+                }
+            for (int a = lane; a < len; a += 64) {
+                ci_out[s + a] = kk[a];
+                v_out[s + a] = v_in[s + pp[a]];
+            }
+            __syncwarp();
+        } else if (len <= kSortLds) {
             for (int a = lane; a < len; a += 64) keys[wl][a] = ci_in[s + a];
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
