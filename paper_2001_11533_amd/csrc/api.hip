@@ -248,12 +248,16 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
         for (auto &p : c.part2) p = c.arena.alloc<double>((size_t)2 * 16 * kMaxGrid);
         c.dscratch = c.arena.alloc<double>(64);
         c.iscratch = c.arena.alloc<int>(64);
+        c.iscratch2 = c.arena.alloc<int>(64);
         AMG_HIP(hipHostMalloc((void **)&c.hsc, sizeof(CgScal), hipHostMallocDefault));
         AMG_HIP(hipHostMalloc((void **)&c.hscr, 64 * sizeof(double), hipHostMallocDefault));
         AMG_HIP(hipHostMalloc((void **)&c.hiscr, 64 * sizeof(int), hipHostMallocDefault));
+        AMG_HIP(hipHostMalloc((void **)&c.hiscr2, 64 * sizeof(int), hipHostMallocDefault));
         AMG_HIP(hipHostMalloc((void **)&c.mails, 64 * sizeof(Mail), hipHostMallocDefault));
         AMG_HIP(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
         AMG_HIP(hipStreamCreateWithFlags(&c.side, hipStreamNonBlocking));
+        AMG_HIP(hipStreamCreateWithFlags(&c.gal, hipStreamNonBlocking));
+        for (auto &e : c.gal_ev) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         for (auto &e : c.poll_ev) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         for (auto &e : c.side_ev) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         for (auto &e : c.poll_ev2) AMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -277,10 +281,12 @@ int amg_destroy(amg_ctx *ctx) {
     Ctx &c = ctx->c;
     if (c.stream) (void)hipStreamSynchronize(c.stream);
     if (c.side) (void)hipStreamSynchronize(c.side);  // setup that failed before joining it
+    if (c.gal) (void)hipStreamSynchronize(c.gal);
     c.arena.free_all();
     if (c.hsc) (void)hipHostFree(c.hsc);
     if (c.hscr) (void)hipHostFree(c.hscr);
     if (c.hiscr) (void)hipHostFree(c.hiscr);
+    if (c.hiscr2) (void)hipHostFree(c.hiscr2);
     if (c.mails) (void)hipHostFree(c.mails);
     for (auto g : c.graphs) (void)hipGraphExecDestroy(g);
     for (auto e : c.poll_ev)
@@ -293,6 +299,9 @@ int amg_destroy(amg_ctx *ctx) {
         if (e) (void)hipEventDestroy(e);
     if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
     if (c.side) (void)hipStreamDestroy(c.side);
+    if (c.gal) (void)hipStreamDestroy(c.gal);
+    for (auto e : c.gal_ev)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
     return AMG_OK;
 }

@@ -79,6 +79,10 @@ struct Ctx {
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only to capture graphs
     hipStream_t side = nullptr;         // setup work that overlaps the main stream (dense inverses)
+    hipStream_t gal = nullptr;          // setup: the mass matrices' Galerkin products beside the stiffness ones
+    hipEvent_t gal_ev[2] = {nullptr, nullptr};
+    int *iscratch2 = nullptr;           // scratch words of the products on gal (device, pinned host)
+    int *hiscr2 = nullptr;
     hipEvent_t side_ev[2] = {nullptr, nullptr};  // fork and join of the side stream
     std::vector<hipGraphExec_t> graphs; // every instantiated graph (freed with the context)
     static constexpr int kPollRing = 4;

@@ -1475,13 +1475,25 @@ struct SideWorker {
 struct Setup {
     Ctx &c;
     hipStream_t s;
-    explicit Setup(Ctx &cc) : c(cc), s(cc.stream) {}
-    Setup(Ctx &cc, hipStream_t st) : c(cc), s(st) {}
+    // scratch words of this stream's sparse products and scans (device, pinned host)
+    int *isc;
+    int *hisc;
+    // when set, released blocks wait here until the caller has joined the streams
+    std::vector<void *> *defer = nullptr;
+    explicit Setup(Ctx &cc) : c(cc), s(cc.stream), isc(cc.iscratch), hisc(cc.hiscr) {}
+    Setup(Ctx &cc, hipStream_t st) : c(cc), s(st), isc(cc.iscratch), hisc(cc.hiscr) {}
+    Setup(Ctx &cc, hipStream_t st, int *is, int *his, std::vector<void *> *df)
+        : c(cc), s(st), isc(is), hisc(his), defer(df) {}
+
+    void rel(void *p) {
+        if (defer) defer->push_back(p);
+        else c.arena.release(p);
+    }
 
     int read_int(const int *d) {
-        AMG_HIP(hipMemcpyAsync(c.hiscr, d, sizeof(int), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipMemcpyAsync(hisc, d, sizeof(int), hipMemcpyDeviceToHost, s));
         AMG_HIP(hipStreamSynchronize(s));
-        return c.hiscr[0];
+        return hisc[0];
     }
 
     void zero(void *p, size_t bytes) { AMG_HIP(hipMemsetAsync(p, 0, bytes, s)); }
@@ -1507,16 +1519,16 @@ struct Setup {
         if (f[kFlagFill]) fail(AMG_ERR_CAPACITY, "sparse product: output column lost in the fill");
     }
 
-    // out[0..n] exclusive scan of cnt[0..n-1]; the total is left in
-    // iscratch[8] and returned when read (else -1: no wait for the device)
+    // out[0..n] exclusive scan of cnt[0..n-1]; the total is left in isc[8]
+    // and returned when read (else -1: no wait for the device)
     int scan(const int *cnt, int *out, int n, bool read = true) {
         const int nb = std::max(1, ceil_div(n, kScanPer));
         int *bsum = c.arena.alloc<int>(nb);
         hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum);
-        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, nb, bsum, c.iscratch + 8);
-        hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum, out, c.iscratch + 8);
-        const int total = read ? read_int(c.iscratch + 8) : -1;
-        c.arena.release(bsum);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, nb, bsum, isc + 8);
+        hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum, out, isc + 8);
+        const int total = read ? read_int(isc + 8) : -1;
+        rel(bsum);
         return total;
     }
 
@@ -1546,28 +1558,44 @@ struct Setup {
         if (c.hiscr[0]) fail(AMG_ERR_NOT_SYMMETRIC, std::string(name) + " is not exactly symmetric");
     }
 
-    DCsr spgemm(const DCsr &A, const DCsr &B) {
+    // A sparse product in three phases so that two can run on two streams with
+    // one wait between them: prod_count issues the symbolic pass, the scan and
+    // the read of its results without waiting; prod_wait waits (and counts
+    // again the rows that overflowed the first tier); prod_fill allocates the
+    // output and issues the numeric pass.
+    struct Prod {
+        const DCsr *A = nullptr, *B = nullptr;
         DCsr C;
+        int *cnt = nullptr;
+        bool wide = false;
+        int gr = 0, umax = 0, bmax = 0;
+    };
+
+    Prod prod_count(const DCsr &A, const DCsr &B) {
+        Prod pr;
+        pr.A = &A;
+        pr.B = &B;
+        DCsr &C = pr.C;
         C.n = A.n;
         C.m = B.m;
-        int *cnt = c.arena.alloc<int>(A.n + 1);
+        pr.cnt = c.arena.alloc<int>(A.n + 1);
         C.rp = c.arena.alloc<int>(A.n + 1);
-        zero(c.iscratch + 4, sizeof(int));
-        zero(c.iscratch + 10, 3 * sizeof(int));
+        int *cnt = pr.cnt;
+        zero(isc + 4, sizeof(int));
+        zero(isc + 10, 3 * sizeof(int));
         // rows too few to fill the chip: four wavefronts per row; otherwise
         // groups of 16, 32 or 64 lanes per row, from the mean row length of A
-        const bool wide = A.n < 8192;
-        const int gr = std::max(1, std::min(A.n, 32768));
+        const bool wide = pr.wide = A.n < 8192;
+        const int gr = pr.gr = std::max(1, std::min(A.n, 32768));
         const long mean = ceil_div(A.nnz, std::max(1, A.n));
         const int lpr = mean <= 16 ? 16 : mean <= 32 ? 32 : 64;
         const int grs = std::max(1, std::min(ceil_div(A.n, kBlock / lpr), 4096));
         auto count = [&](auto kern, int recount) {
             hipLaunchKernelGGL(kern, dim3(gr), dim3(wide ? 256 : 64), 0, s, A.n, A.rp, A.ci, B.rp, B.ci, cnt,
-                               c.iscratch + 4, c.iscratch + 10, recount);
+                               isc + 4, isc + 10, recount);
         };
         auto count_sub = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3(grs), dim3(kBlock), 0, s, A.n, A.rp, A.ci, B.rp, B.ci, cnt,
-                               c.iscratch + 10);
+            hipLaunchKernelGGL(kern, dim3(grs), dim3(kBlock), 0, s, A.n, A.rp, A.ci, B.rp, B.ci, cnt, isc + 10);
         };
         // first tier: small tables; rows that overflow half of one are counted
         // again with kHS slots
@@ -1577,23 +1605,40 @@ struct Setup {
         else count_sub(k_spgemm_count_sub<64, 512>);
         check_kernels();
         // the row offsets before the one read of the pass's results: the
-        // total (iscratch[8]) arrives with the maxima (a row counted again
-        // below makes the first scan moot and it is redone)
+        // total (isc[8]) arrives with the maxima (a row counted again makes
+        // the first scan moot and it is redone)
         scan(cnt, C.rp, A.n, false);
-        AMG_HIP(hipMemcpyAsync(c.hiscr, c.iscratch + 4, 9 * sizeof(int), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipMemcpyAsync(hisc, isc + 4, 9 * sizeof(int), hipMemcpyDeviceToHost, s));
+        return pr;
+    }
+
+    void prod_wait(Prod &pr) {
+        const DCsr &A = *pr.A, &B = *pr.B;
         AMG_HIP(hipStreamSynchronize(s));
-        if (c.hiscr[8]) {
-            if (wide) count(k_spgemm_count<4, kHS>, 1);
-            else count(k_spgemm_count<1, kHS>, 1);
+        if (hisc[8]) {
+            if (pr.wide)
+                hipLaunchKernelGGL((k_spgemm_count<4, kHS>), dim3(pr.gr), dim3(256), 0, s, A.n, A.rp, A.ci, B.rp,
+                                   B.ci, pr.cnt, isc + 4, isc + 10, 1);
+            else
+                hipLaunchKernelGGL((k_spgemm_count<1, kHS>), dim3(pr.gr), dim3(64), 0, s, A.n, A.rp, A.ci, B.rp,
+                                   B.ci, pr.cnt, isc + 4, isc + 10, 1);
             check_kernels();
-            scan(cnt, C.rp, A.n, false);
-            AMG_HIP(hipMemcpyAsync(c.hiscr, c.iscratch + 4, 9 * sizeof(int), hipMemcpyDeviceToHost, s));
+            scan(pr.cnt, pr.C.rp, A.n, false);
+            AMG_HIP(hipMemcpyAsync(hisc, isc + 4, 9 * sizeof(int), hipMemcpyDeviceToHost, s));
             AMG_HIP(hipStreamSynchronize(s));
         }
-        if (c.hiscr[0])
+        if (hisc[0])
             fail(AMG_ERR_CAPACITY, "sparse product row exceeds " + std::to_string(kMaxRowOut) + " columns");
-        const int umax = c.hiscr[6], bmax = c.hiscr[7];
-        C.nnz = c.hiscr[4];
+        pr.umax = hisc[6];
+        pr.bmax = hisc[7];
+        pr.C.nnz = hisc[4];
+    }
+
+    DCsr prod_fill(Prod &pr) {
+        const DCsr &A = *pr.A, &B = *pr.B;
+        DCsr &C = pr.C;
+        const bool wide = pr.wide;
+        const int gr = pr.gr, umax = pr.umax, bmax = pr.bmax;
         C.ci = c.arena.alloc<int>(C.nnz);
         C.v = c.arena.alloc<double>(C.nnz);
         if (wide) {
@@ -1651,8 +1696,14 @@ struct Setup {
             else fill(k_spgemm_fill<2048, 1>);
         }
         check_kernels();
-        c.arena.release(cnt);
+        rel(pr.cnt);
         return C;
+    }
+
+    DCsr spgemm(const DCsr &A, const DCsr &B) {
+        Prod pr = prod_count(A, B);
+        prod_wait(pr);
+        return prod_fill(pr);
     }
 
     DCsr transpose(const DCsr &A) {
@@ -1683,21 +1734,42 @@ struct Setup {
         return T;
     }
 
-    // S^T (A S); with keep, A S is handed back instead of released
-    DCsr galerkin(const DCsr &S, const DCsr &St, const DCsr &A, DCsr *keep = nullptr) {
-        DCsr T = spgemm(A, S);
-        DCsr C = spgemm(St, T);
-        hipLaunchKernelGGL(k_mirror, dim3(gwave(C.n)), dim3(kBlock), 0, s, C.n, C.rp, C.ci, C.v,
+    // The Galerkin products of A (this stream) and M (the context's second
+    // setup stream, with its own scratch words) side by side: the products run
+    // in pairs whose count read-backs share one wait, the M side starts behind
+    // everything issued here so far, and every block released meanwhile (by
+    // either side) returns to the arena only after this stream has joined the
+    // other.  With keep, A S is handed back.
+    void galerkin_pair(const DCsr &S, const DCsr &St, const DCsr &A, const DCsr &M, DCsr &CA, DCsr &CM,
+                       DCsr *keep) {
+        std::vector<void *> deferred;
+        Setup g(c, c.gal, c.iscratch2, c.hiscr2, &deferred);
+        std::vector<void *> *saved = defer;
+        defer = &deferred;
+        AMG_HIP(hipEventRecord(c.gal_ev[0], s));
+        AMG_HIP(hipStreamWaitEvent(c.gal, c.gal_ev[0], 0));
+        Prod pa = prod_count(A, S), pm = g.prod_count(M, S);
+        prod_wait(pa);
+        g.prod_wait(pm);
+        DCsr TA = prod_fill(pa), TM = g.prod_fill(pm);
+        Prod qa = prod_count(St, TA), qm = g.prod_count(St, TM);
+        prod_wait(qa);
+        g.prod_wait(qm);
+        CA = prod_fill(qa);
+        CM = g.prod_fill(qm);
+        hipLaunchKernelGGL(k_mirror, dim3(gwave(CA.n)), dim3(kBlock), 0, s, CA.n, CA.rp, CA.ci, CA.v,
+                           c.iscratch + kFlagMirror);
+        hipLaunchKernelGGL(k_mirror, dim3(gwave(CM.n)), dim3(kBlock), 0, c.gal, CM.n, CM.rp, CM.ci, CM.v,
                            c.iscratch + kFlagMirror);
         check_kernels();
-        if (keep) {
-            *keep = T;
-        } else {
-            c.arena.release(T.rp);
-            c.arena.release(T.ci);
-            c.arena.release(T.v);
-        }
-        return C;
+        for (void *p : {(void *)TM.rp, (void *)TM.ci, (void *)TM.v}) deferred.push_back(p);
+        if (keep) *keep = TA;
+        else
+            for (void *p : {(void *)TA.rp, (void *)TA.ci, (void *)TA.v}) deferred.push_back(p);
+        AMG_HIP(hipEventRecord(c.gal_ev[1], c.gal));
+        AMG_HIP(hipStreamWaitEvent(s, c.gal_ev[1], 0));
+        defer = saved;
+        for (void *p : deferred) rel(p);
     }
 
     // returns false when coarsening stops at level j
@@ -1793,8 +1865,7 @@ struct Setup {
         L0.St = transpose(S);
         Level nx;
         nx.n = nc;
-        nx.A = galerkin(L0.S, L0.St, A, &L0.T);
-        nx.M = galerkin(L0.S, L0.St, L0.M);
+        galerkin_pair(L0.S, L0.St, A, L0.M, nx.A, nx.M, &L0.T);
         c.lev.push_back(nx);
         return true;
     }
