@@ -57,9 +57,25 @@ template <class T> __device__ __forceinline__ void raise_max(T *dst, T v) {
     if (v > __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(dst, v);
 }
 
+// Per-row kernels with kRowLanes lanes per row: a row's entries are taken
+// kRowLanes at a time, one per lane; ballots keep the row's order where it
+// matters (compactions) and sequential sums fold the lanes' values in order.
+constexpr int kRowLanes = 16;
+__device__ __forceinline__ int row_lane() { return threadIdx.x % kRowLanes; }
+__device__ __forceinline__ int row_first() { return (int)((blockIdx.x * blockDim.x + threadIdx.x) / kRowLanes); }
+__device__ __forceinline__ int row_stride() { return (int)(gridDim.x * blockDim.x / kRowLanes); }
+// this lane's group's bits of a wavefront ballot (every lane of the group takes part)
+__device__ __forceinline__ unsigned group_bits(bool pred) {
+    const unsigned long long b = __ballot(pred);
+    return (unsigned)((b >> ((threadIdx.x % 64) / kRowLanes * kRowLanes)) & 0xFFFFull);
+}
+__device__ __forceinline__ unsigned lanes_below() { return (1u << row_lane()) - 1u; }
+
 __global__ void k_check_sym(int n, const int *rp, const int *ci, const double *v, int *bad) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+    const int gl = row_lane();
+    for (int i = row_first(); i < n; i += row_stride()) {
+        const int e = rp[i + 1];
+        for (int p = rp[i] + gl; p < e; p += kRowLanes) {
             const int k = ci[p];
             if (k < 0 || k >= n) {
                 atomicAdd(bad, 1);
@@ -85,43 +101,67 @@ __global__ void k_check_sym(int n, const int *rp, const int *ci, const double *v
 
 __global__ void k_diag(int n, const int *rp, const int *ci, const double *v, const uint8_t *mask,
                        double *d, int *bad) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int gl = row_lane();
+    for (int i = row_first(); i < n; i += row_stride()) {
         double di = 0.0;
-        for (int p = rp[i]; p < rp[i + 1]; ++p)
-            if (ci[p] == i) di = v[p];
-        d[i] = di;
-        if (!(di > 0.0) && !(mask && mask[i])) atomicAdd(bad, 1);
+        const int e = rp[i + 1];
+        for (int p0 = rp[i]; p0 < e; p0 += kRowLanes) {  // the last stored diagonal entry, as a serial loop
+            const int p = p0 + gl;
+            const bool hit = p < e && ci[p] == i;
+            const double x = hit ? v[p] : 0.0;
+            const unsigned b = group_bits(hit);
+            const double y = __shfl(x, b ? 31 - __clz(b) : 0, kRowLanes);
+            if (b) di = y;
+        }
+        if (gl == 0) {
+            d[i] = di;
+            if (!(di > 0.0) && !(mask && mask[i])) atomicAdd(bad, 1);
+        }
     }
 }
 
 // A_0 = D A D + (I - D): Dirichlet rows and columns leave the pattern, the
 // Dirichlet diagonal is one.
 __global__ void k_a0_count(int n, const int *rp, const int *ci, const uint8_t *mask, int *cnt) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int gl = row_lane();
+    for (int i = row_first(); i < n; i += row_stride()) {
         if (mask[i]) {
-            cnt[i] = 1;
+            if (gl == 0) cnt[i] = 1;
             continue;
         }
         int c = 0;
-        for (int p = rp[i]; p < rp[i + 1]; ++p) c += mask[ci[p]] ? 0 : 1;
-        cnt[i] = c;
+        const int e = rp[i + 1];
+        for (int p0 = rp[i]; p0 < e; p0 += kRowLanes) {
+            const int p = p0 + gl;
+            c += __popc(group_bits(p < e && !mask[ci[p]]));
+        }
+        if (gl == 0) cnt[i] = c;
     }
 }
 
 __global__ void k_a0_fill(int n, const int *rp, const int *ci, const double *v, const uint8_t *mask,
                           const int *rp0, int *ci0, double *v0) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int gl = row_lane();
+    for (int i = row_first(); i < n; i += row_stride()) {
         int o = rp0[i];
         if (mask[i]) {
-            ci0[o] = i;
-            v0[o] = 1.0;
+            if (gl == 0) {
+                ci0[o] = i;
+                v0[o] = 1.0;
+            }
             continue;
         }
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
-            if (mask[ci[p]]) continue;
-            ci0[o] = ci[p];
-            v0[o] = v[p];
-            ++o;
+        const int e = rp[i + 1];
+        for (int p0 = rp[i]; p0 < e; p0 += kRowLanes) {
+            const int p = p0 + gl;
+            const bool keep = p < e && !mask[ci[p]];
+            const unsigned b = group_bits(keep);
+            if (keep) {
+                const int r = __popc(b & lanes_below());
+                ci0[o + r] = ci[p];
+                v0[o + r] = v[p];
+            }
+            o += __popc(b);
         }
     }
 }
@@ -182,11 +222,20 @@ __global__ void k_scan_final(int n, const int *in, const int *bsum, int *out, co
 }
 
 __global__ void k_l1(int n, const int *rp, const double *v, double *dl1inv, double *dl1) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int gl = row_lane();
+    for (int i = row_first(); i < n; i += row_stride()) {
         double s = 0.0;
-        for (int p = rp[i]; p < rp[i + 1]; ++p) s = s + fabs(v[p]);
-        dl1[i] = s;
-        dl1inv[i] = 1.0 / s;
+        const int e = rp[i + 1];
+        for (int p0 = rp[i]; p0 < e; p0 += kRowLanes) {
+            const int p = p0 + gl;
+            const double x = p < e ? fabs(v[p]) : 0.0;
+            const int cn = min(kRowLanes, e - p0);
+            for (int j = 0; j < cn; ++j) s = s + __shfl(x, j, kRowLanes);  // in the row's order
+        }
+        if (gl == 0) {
+            dl1[i] = s;
+            dl1inv[i] = 1.0 / s;
+        }
     }
 }
 
@@ -197,36 +246,49 @@ __global__ void k_inv(int n, const double *d, double *dinv) {
 
 __global__ void k_strength(int n, const int *rp, const int *ci, const double *v, const double *d,
                            const uint8_t *mask, double t, uint8_t *flag, int *cnt) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int gl = row_lane();
+    for (int i = row_first(); i < n; i += row_stride()) {
         int c = 0;
         const bool mi = mask && mask[i];
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
-            const int k = ci[p];
+        const double di = d[i];
+        const int e = rp[i + 1];
+        for (int p0 = rp[i]; p0 < e; p0 += kRowLanes) {
+            const int p = p0 + gl;
             bool s = false;
-            if (k != i && !mi && !(mask && mask[k])) {
-                const double a = v[p];
-                const double lhs = a * a;
-                const double dd = d[i] * d[k];
-                const double rhs = t * dd;
-                s = lhs >= rhs;
+            if (p < e) {
+                const int k = ci[p];
+                if (k != i && !mi && !(mask && mask[k])) {
+                    const double a = v[p];
+                    const double lhs = a * a;
+                    const double dd = di * d[k];
+                    const double rhs = t * dd;
+                    s = lhs >= rhs;
+                }
+                flag[p] = s;
             }
-            flag[p] = s;
-            c += s;
+            c += __popc(group_bits(s));
         }
-        cnt[i] = c;
+        if (gl == 0) cnt[i] = c;
     }
 }
 
 __global__ void k_strong_fill(int n, const int *rp, const int *ci, const double *v, const uint8_t *flag,
                               const int *srp, int *sci, double *sabs) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int gl = row_lane();
+    for (int i = row_first(); i < n; i += row_stride()) {
         int o = srp[i];
-        for (int p = rp[i]; p < rp[i + 1]; ++p)
-            if (flag[p]) {
-                sci[o] = ci[p];
-                sabs[o] = fabs(v[p]);
-                ++o;
+        const int e = rp[i + 1];
+        for (int p0 = rp[i]; p0 < e; p0 += kRowLanes) {
+            const int p = p0 + gl;
+            const bool f = p < e && flag[p];
+            const unsigned b = group_bits(f);
+            if (f) {
+                const int r = __popc(b & lanes_below());
+                sci[o + r] = ci[p];
+                sabs[o + r] = fabs(v[p]);
             }
+            o += __popc(b);
+        }
     }
 }
 
@@ -944,20 +1006,33 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_fill_sub(int n, const int *ar
 // sorted; a row of S with an entry outside T's row sets *bad
 __global__ void k_align(int n, const int *trp, const int *tci, const int *srp, const int *sci, const double *sv,
                         double *out, int *bad) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        int q = srp[i];
-        const int qe = srp[i + 1];
-        for (int p = trp[i]; p < trp[i + 1]; ++p) {
-            const int k = tci[p];
-            while (q < qe && sci[q] < k) ++q;
-            out[p] = (q < qe && sci[q] == k) ? sv[q] : 0.0;
-        }
+    const int gl = row_lane();
+    for (int i = row_first(); i < n; i += row_stride()) {
+        const int qb = srp[i], qe = srp[i + 1];
+        const int e = trp[i + 1];
         int hit = 0;  // entries of S's row found in T's
-        for (int p = trp[i], q2 = srp[i]; p < trp[i + 1] && q2 < qe; ++p) {
-            while (q2 < qe && sci[q2] < tci[p]) ++q2;
-            if (q2 < qe && sci[q2] == tci[p]) ++hit;
+        for (int p0 = trp[i]; p0 < e; p0 += kRowLanes) {
+            const int p = p0 + gl;
+            bool h = false;
+            if (p < e) {
+                const int k = tci[p];
+                int lo = qb, hi = qe - 1, found = -1;
+                while (lo <= hi) {
+                    const int mid = (lo + hi) >> 1;
+                    const int cm = sci[mid];
+                    if (cm == k) {
+                        found = mid;
+                        break;
+                    }
+                    if (cm < k) lo = mid + 1;
+                    else hi = mid - 1;
+                }
+                h = found >= 0;
+                out[p] = h ? sv[found] : 0.0;
+            }
+            hit += __popc(group_bits(h));
         }
-        if (hit != qe - srp[i]) atomicOr(bad, 1);
+        if (gl == 0 && hit != qe - qb) atomicOr(bad, 1);
     }
 }
 
@@ -1550,7 +1625,7 @@ struct Setup {
 
     void check_matrix(const DCsr &d, const char *name) {
         zero(c.iscratch, 2 * sizeof(int));
-        hipLaunchKernelGGL(k_check_sym, dim3(gsz(d.n)), dim3(kBlock), 0, s, d.n, d.rp, d.ci, d.v, c.iscratch);
+        hipLaunchKernelGGL(k_check_sym, dim3(gsz((long)(d.n) * kRowLanes)), dim3(kBlock), 0, s, d.n, d.rp, d.ci, d.v, c.iscratch);
         check_kernels();
         AMG_HIP(hipMemcpyAsync(c.hiscr, c.iscratch, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
         AMG_HIP(hipStreamSynchronize(s));
@@ -1779,7 +1854,7 @@ struct Setup {
         const int n = A.n;
         const uint8_t *mask = L0.mask;
         double *d = c.arena.alloc<double>(n);
-        hipLaunchKernelGGL(k_diag, dim3(gsz(n)), dim3(kBlock), 0, s, n, A.rp, A.ci, A.v, mask, d,
+        hipLaunchKernelGGL(k_diag, dim3(gsz((long)(n) * kRowLanes)), dim3(kBlock), 0, s, n, A.rp, A.ci, A.v, mask, d,
                            c.iscratch + kFlagDiag + std::min(j, kFlagDiagN - 1));
         // the input matrix is checked before anything is built on it
         if (j == 0 && read_int(c.iscratch + kFlagDiag))
@@ -1790,12 +1865,12 @@ struct Setup {
         uint8_t *flag = c.arena.alloc<uint8_t>(A.nnz);
         int *cnt = c.arena.alloc<int>(n + 1);
         int *srp = c.arena.alloc<int>(n + 1);
-        hipLaunchKernelGGL(k_strength, dim3(gsz(n)), dim3(kBlock), 0, s, n, A.rp, A.ci, A.v, d, mask, t, flag,
+        hipLaunchKernelGGL(k_strength, dim3(gsz((long)(n) * kRowLanes)), dim3(kBlock), 0, s, n, A.rp, A.ci, A.v, d, mask, t, flag,
                            cnt);
         const int snnz = scan(cnt, srp, n);
         int *sci = c.arena.alloc<int>(snnz);
         double *sabs = c.arena.alloc<double>(snnz);
-        hipLaunchKernelGGL(k_strong_fill, dim3(gsz(n)), dim3(kBlock), 0, s, n, A.rp, A.ci, A.v, flag, srp, sci,
+        hipLaunchKernelGGL(k_strong_fill, dim3(gsz((long)(n) * kRowLanes)), dim3(kBlock), 0, s, n, A.rp, A.ci, A.v, flag, srp, sci,
                            sabs);
         c.arena.release(flag);
         // distance-2 independent set by fixed-priority rounds
@@ -1839,7 +1914,7 @@ struct Setup {
         }
         // omega = (4/3) / max_i (sum_k |a_ik|) / a_ii
         double *dl1 = c.arena.alloc<double>(n);
-        hipLaunchKernelGGL(k_l1, dim3(gsz(n)), dim3(kBlock), 0, s, n, A.rp, A.v, L0.dl1inv, dl1);
+        hipLaunchKernelGGL(k_l1, dim3(gsz((long)(n) * kRowLanes)), dim3(kBlock), 0, s, n, A.rp, A.v, L0.dl1inv, dl1);
         unsigned long long *mb = reinterpret_cast<unsigned long long *>(c.dscratch);
         zero(mb, sizeof(unsigned long long));
         hipLaunchKernelGGL(k_rho, dim3(gsz(n)), dim3(kBlock), 0, s, n, dl1, d, mask, mb);
@@ -1875,10 +1950,10 @@ struct Setup {
         L.n = n;
         if (!L.dl1inv) L.dl1inv = c.arena.alloc<double>(n);
         double *dl1 = c.arena.alloc<double>(n);
-        hipLaunchKernelGGL(k_l1, dim3(gsz(n)), dim3(kBlock), 0, s, n, L.A.rp, L.A.v, L.dl1inv, dl1);
+        hipLaunchKernelGGL(k_l1, dim3(gsz((long)(n) * kRowLanes)), dim3(kBlock), 0, s, n, L.A.rp, L.A.v, L.dl1inv, dl1);
         double *md = c.arena.alloc<double>(n);
         L.mdinv = c.arena.alloc<double>(n);
-        hipLaunchKernelGGL(k_diag, dim3(gsz(n)), dim3(kBlock), 0, s, n, L.M.rp, L.M.ci, L.M.v,
+        hipLaunchKernelGGL(k_diag, dim3(gsz((long)(n) * kRowLanes)), dim3(kBlock), 0, s, n, L.M.rp, L.M.ci, L.M.v,
                            (const uint8_t *)nullptr, md, c.iscratch + kFlagMassDiag);
         hipLaunchKernelGGL(k_inv, dim3(gsz(n)), dim3(kBlock), 0, s, n, md, L.mdinv);
         check_kernels();
@@ -2006,11 +2081,11 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
         A0.n = A0.m = N;
         int *cnt = c.arena.alloc<int>(N + 1);
         A0.rp = c.arena.alloc<int>(N + 1);
-        hipLaunchKernelGGL(k_a0_count, dim3(gsz(N)), dim3(kBlock), 0, s, N, A.rp, A.ci, c.mask0, cnt);
+        hipLaunchKernelGGL(k_a0_count, dim3(gsz((long)(N) * kRowLanes)), dim3(kBlock), 0, s, N, A.rp, A.ci, c.mask0, cnt);
         A0.nnz = su.scan(cnt, A0.rp, N);
         A0.ci = c.arena.alloc<int>(A0.nnz);
         A0.v = c.arena.alloc<double>(A0.nnz);
-        hipLaunchKernelGGL(k_a0_fill, dim3(gsz(N)), dim3(kBlock), 0, s, N, A.rp, A.ci, A.v, c.mask0, A0.rp,
+        hipLaunchKernelGGL(k_a0_fill, dim3(gsz((long)(N) * kRowLanes)), dim3(kBlock), 0, s, N, A.rp, A.ci, A.v, c.mask0, A0.rp,
                            A0.ci, A0.v);
         su.check_kernels();
         c.arena.release(cnt);
@@ -2088,7 +2163,7 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
             // S's values on the pattern of T = A S, for the fused coarse
             // correction (after the level loop: off the path to the side stream)
             L.Ts = c.arena.alloc<double>(L.T.nnz);
-            hipLaunchKernelGGL(k_align, dim3(gsz(L.n)), dim3(kBlock), 0, s, L.n, L.T.rp, L.T.ci, L.S.rp, L.S.ci,
+            hipLaunchKernelGGL(k_align, dim3(gsz((long)(L.n) * kRowLanes)), dim3(kBlock), 0, s, L.n, L.T.rp, L.T.ci, L.S.rp, L.S.ci,
                                L.S.v, L.Ts, c.iscratch + Setup::kFlagAlign);
             f32(L.T);
             L.Ts32 = c.arena.alloc<float>(L.T.nnz);
