@@ -235,13 +235,16 @@ int amg_hierarchy_quality(amg_ctx *ctx, int level, const double *v0, int iters, 
 const char *amg_last_error(amg_ctx *ctx);
 
 /* Average device time of `reps` back-to-back launches of one kernel on the context's
- * stream, measured with HIP events: which = 0: level-0 CSR SpMV (q = A_0 p), 1: the
+ * stream, measured with HIP events: which = 0: level-0 SpMV (q = A_0 p), 1: the
  * level-0 first l1-Jacobi sweep fused with the residual (x = D^{-1} b, r = b - A_0 x,
  * the V-cycle's first kernel), 2: a whole V-cycle from level 0.  The kernels see
  * zero vectors.  prec: 64 or 32 (32 needs inner_precision 32); nb as above.
  * *ms_avg receives milliseconds per launch and *bytes the algorithmic bytes one
  * launch moves (row pointers, column indices and values once, every vector it
- * reads or gathers once, every vector it writes once).
+ * reads or gathers once, every vector it writes once).  Level-0 products with one
+ * column run on a sliced-ELL copy whose columns are 16-bit offsets from a base
+ * per slice of 64 rows (built when every slice spans fewer than 65536 columns);
+ * their column indices count 2 bytes, all others 4.
  * Errors: ARG. */
 int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double *ms_avg,
                     double *bytes);

@@ -655,8 +655,10 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
             const double sz = prec == 64 ? 8.0 : 4.0;
             const double nbd = NB;
             // algorithmic bytes: row pointers, (col, val) per stored entry, x read
-            // once, y written once (per column)
-            const double spmv_b = 4.0 * (n + 1) + (4.0 + sz) * L0.A.nnz + 2.0 * sz * n * nbd;
+            // once, y written once (per column); a column takes 2 bytes in the
+            // level-0 sliced-ELL copy (single column), else 4
+            auto ib = [&](int l) { return l == 0 && NB == 1 && c.lev[0].A.sl_off ? 2.0 : 4.0; };
+            const double spmv_b = 4.0 * (n + 1) + (ib(0) + sz) * L0.A.nnz + 2.0 * sz * n * nbd;
             hipEvent_t e0, e1;
             AMG_HIP(hipEventCreate(&e0));
             AMG_HIP(hipEventCreate(&e1));
@@ -693,7 +695,7 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
             if (bytes) {
                 if (which == 0) *bytes = spmv_b;
                 else if (which == 1)  // gathers x once, reads b, writes r
-                    *bytes = 4.0 * (n + 1) + (4.0 + sz) * L0.A.nnz + 3.0 * sz * n * nbd;
+                    *bytes = 4.0 * (n + 1) + (ib(0) + sz) * L0.A.nnz + 3.0 * sz * n * nbd;
                 else {
                     // the cycle ends at the first level with a dense inverse
                     int Lc = c.L - 1;
@@ -706,7 +708,7 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                     for (int l = 0; l < Lc; ++l) {
                         const Level &Lv = c.lev[l];
                         const double nl = Lv.n, nc = c.lev[l + 1].n;
-                        const double a = 4.0 * (nl + 1) + (4.0 + sz) * Lv.A.nnz;
+                        const double a = 4.0 * (nl + 1) + (ib(l) + sz) * Lv.A.nnz;
                         if (c.o.smoother == 1) {
                             // Chebyshev: pre step (x, b, dinv in; t out), residual (t, b in; r
                             // out), post steps (t, b, dinv in; x out) and (x, t, b, dinv in; out)

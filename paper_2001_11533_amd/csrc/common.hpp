@@ -183,11 +183,14 @@ struct DCsr {
     double *v = nullptr;
     float *v32 = nullptr;
     // optional sliced-ELL copy (finest level): slices of 64 rows stored column
-    // by column, entry k of row 64 s + l at sl_off[s] + 64 k + l; the rows of a
-    // slice are padded to its longest with (column 0, value 0)
+    // by column, entry k of row 64 s + l at sl_off[s] + 64 k + l; a column is
+    // kept as a 16-bit offset from the slice's smallest column sl_base[s] (the
+    // copy exists only when every slice spans fewer than 65536 columns), and the
+    // rows of a slice are padded to its longest with (offset 0, value 0)
     int nsl = 0;
     int *sl_off = nullptr;  // [nsl + 1]
-    int *sl_ci = nullptr;
+    int *sl_base = nullptr; // [nsl]
+    uint16_t *sl_cd = nullptr;
     double *sl_v = nullptr;
     float *sl_v32 = nullptr;
 };

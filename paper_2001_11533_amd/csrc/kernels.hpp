@@ -404,10 +404,12 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__re
 
 // The same product over the sliced-ELL copy (single column): one wavefront
 // per slice of 64 rows, one lane per row; a lane issues the loads of up to 16
-// entries of its row at once, with no dependence on row pointers.
+// entries of its row at once, with no dependence on row pointers.  Columns are
+// 16-bit offsets from the slice's base column (6 bytes per float32 entry).
 template <typename T, int NV, class GX, class EP, class PRO = NoPro>
 __global__ __launch_bounds__(kBlock) void sell_kernel(int nrows, int nsl, const int *__restrict__ soff,
-                                                      const int *__restrict__ ci, const T *__restrict__ av, GX gx,
+                                                      const int *__restrict__ sbase,
+                                                      const uint16_t *__restrict__ cd, const T *__restrict__ av, GX gx,
                                                       EP ep, Reducer<(NV > 0 ? NV : 1), 1> red,
                                                       const int *__restrict__ stop, PRO pro = PRO{}) {
     if (stop && *stop) return;
@@ -434,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void sell_kernel(int nrows, int nsl, const 
         const bool live = row < nrows;
         typename EP::P pr{};
         if (live) pr = ep.load(row, 0);
-        const int o = soff[sl], w = (soff[sl + 1] - o) >> 6;
+        const int o = soff[sl], w = (soff[sl + 1] - o) >> 6, cb = sbase[sl];
         T sum = T(0);
         for (int k0 = 0; k0 < w; k0 += U) {
             int kk[U];
@@ -443,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void sell_kernel(int nrows, int nsl, const 
             for (int u = 0; u < U; ++u) {
                 const bool ok = k0 + u < w;
                 const size_t q = (size_t)o + (size_t)(k0 + u) * 64 + lane;
-                kk[u] = ok ? ci[q] : 0;
+                kk[u] = ok ? cb + (int)cd[q] : 0;
                 aa[u] = ok ? av[q] : T(0);
             }
 #pragma unroll

@@ -321,8 +321,14 @@ __global__ void k_mis_init(int n, const uint8_t *mask, int8_t *st) {
         st[i] = (mask && mask[i]) ? OUT : UNDEC;
 }
 
+// Each round's kernels take the undecided count its predecessor left (null in
+// the first round) and return at once when it is zero, so that rounds can be
+// issued in batches ahead of the one read that ends the loop.
+__device__ __forceinline__ bool mis_done(const int *prev) { return prev && *prev == 0; }
+
 __global__ void k_mis_m1(int n, const int *srp, const int *sci, const uint64_t *h, const int8_t *st,
-                         int *m1) {
+                         int *m1, const int *prev) {
+    if (mis_done(prev)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         int best = st[i] == UNDEC ? i : -1;
         for (int p = srp[i]; p < srp[i + 1]; ++p) {
@@ -334,7 +340,8 @@ __global__ void k_mis_m1(int n, const int *srp, const int *sci, const uint64_t *
 }
 
 __global__ void k_mis_m2(int n, const int *srp, const int *sci, const uint64_t *h, const int *m1,
-                         int8_t *st) {
+                         int8_t *st, const int *prev) {
+    if (mis_done(prev)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         if (st[i] != UNDEC) continue;
         int best = m1[i];
@@ -346,7 +353,9 @@ __global__ void k_mis_m2(int n, const int *srp, const int *sci, const uint64_t *
     }
 }
 
-__global__ void k_mis_r1(int n, const int *srp, const int *sci, const int8_t *st, uint8_t *r1) {
+__global__ void k_mis_r1(int n, const int *srp, const int *sci, const int8_t *st, uint8_t *r1,
+                         const int *prev) {
+    if (mis_done(prev)) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         uint8_t any = st[i] == ROOT;
         for (int p = srp[i]; p < srp[i + 1] && !any; ++p) any = st[sci[p]] == ROOT;
@@ -354,7 +363,9 @@ __global__ void k_mis_r1(int n, const int *srp, const int *sci, const int8_t *st
     }
 }
 
-__global__ void k_mis_r2(int n, const int *srp, const int *sci, const uint8_t *r1, int8_t *st, int *undec) {
+__global__ void k_mis_r2(int n, const int *srp, const int *sci, const uint8_t *r1, int8_t *st, int *undec,
+                         const int *prev) {
+    if (mis_done(prev)) return;
     int left = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         if (st[i] != UNDEC) continue;
@@ -1355,28 +1366,40 @@ __global__ __launch_bounds__(kBlock) void k_wtw(int n, const double *Wb, double 
 
 // sliced-ELL copy of a CSR matrix, one wavefront per slice of 64 rows:
 // widths (64 x the longest row of the slice), then the column-major fill
-__global__ void k_sell_width(int n, int nsl, const int *rp, int *cnt) {
+// per slice of 64 rows: 64 x the longest row, the smallest column (rows are
+// sorted) and a flag when the slice spans 65536 columns or more
+__global__ void k_sell_width(int n, int nsl, const int *rp, const int *ci, int *cnt, int *base, int *wide) {
     const int lane = threadIdx.x % 64;
     const int w = (blockIdx.x * blockDim.x + threadIdx.x) / 64, nw = gridDim.x * blockDim.x / 64;
     for (int sl = w; sl < nsl; sl += nw) {
         const int r = sl * 64 + lane;
-        int len = r < n ? rp[r + 1] - rp[r] : 0;
-        for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off));
-        if (lane == 0) cnt[sl] = len * 64;
+        const int p0 = r < n ? rp[r] : 0, p1 = r < n ? rp[r + 1] : 0;
+        int len = p1 - p0;
+        int lo = len ? ci[p0] : INT_MAX, hi = len ? ci[p1 - 1] : -1;
+        for (int off = 32; off > 0; off >>= 1) {
+            len = max(len, __shfl_xor(len, off));
+            lo = min(lo, __shfl_xor(lo, off));
+            hi = max(hi, __shfl_xor(hi, off));
+        }
+        if (lane == 0) {
+            cnt[sl] = len * 64;
+            base[sl] = hi >= lo ? lo : 0;
+            if (hi >= lo && hi - lo > 65535) *wide = 1;
+        }
     }
 }
 
 __global__ void k_sell_fill(int n, int nsl, const int *rp, const int *ci, const double *v, const int *soff,
-                            int *sci, double *sv) {
+                            const int *base, uint16_t *scd, double *sv) {
     const int lane = threadIdx.x % 64;
     const int w = (blockIdx.x * blockDim.x + threadIdx.x) / 64, nw = gridDim.x * blockDim.x / 64;
     for (int sl = w; sl < nsl; sl += nw) {
         const int r = sl * 64 + lane;
-        const int o = soff[sl], wd = (soff[sl + 1] - o) / 64;
+        const int o = soff[sl], wd = (soff[sl + 1] - o) / 64, b = base[sl];
         const int p0 = r < n ? rp[r] : 0, len = r < n ? rp[r + 1] - p0 : 0;
         for (int k = 0; k < wd; ++k) {
             const size_t q = (size_t)o + (size_t)k * 64 + lane;
-            sci[q] = k < len ? ci[p0 + k] : 0;
+            scd[q] = (uint16_t)(k < len ? ci[p0 + k] - b : 0);
             sv[q] = k < len ? v[p0 + k] : 0.0;
         }
     }
@@ -1867,9 +1890,11 @@ struct Setup {
         int *srp = c.arena.alloc<int>(n + 1);
         hipLaunchKernelGGL(k_strength, dim3(gsz((long)(n) * kRowLanes)), dim3(kBlock), 0, s, n, A.rp, A.ci, A.v, d, mask, t, flag,
                            cnt);
-        const int snnz = scan(cnt, srp, n);
-        int *sci = c.arena.alloc<int>(snnz);
-        double *sabs = c.arena.alloc<double>(snnz);
+        // the strong entries are a subset of A's: A.nnz bounds them with no
+        // wait for the count
+        scan(cnt, srp, n, false);
+        int *sci = c.arena.alloc<int>(A.nnz);
+        double *sabs = c.arena.alloc<double>(A.nnz);
         hipLaunchKernelGGL(k_strong_fill, dim3(gsz((long)(n) * kRowLanes)), dim3(kBlock), 0, s, n, A.rp, A.ci, A.v, flag, srp, sci,
                            sabs);
         c.arena.release(flag);
@@ -1881,29 +1906,41 @@ struct Setup {
         int *m1 = c.arena.alloc<int>(n);
         uint8_t *r1 = c.arena.alloc<uint8_t>(n);
         hipLaunchKernelGGL(k_mis_init, dim3(gsz(n)), dim3(kBlock), 0, s, n, mask, st);
-        for (int round = 0;; ++round) {
+        // rounds in batches with one read of the undecided count per batch;
+        // round r counts into und[r % kMisRing] (the ring holds whole batches)
+        constexpr int kMisRing = 64, kMisBatch = 4;
+        static_assert(kMisRing % kMisBatch == 0, "a batch must not wrap the ring");
+        int *und = c.arena.alloc<int>(kMisRing);
+        for (int round = 0;;) {
             if (round > n + 1) fail(AMG_ERR_ARG, "independent-set rounds did not terminate");
-            hipLaunchKernelGGL(k_mis_m1, dim3(gsz(n)), dim3(kBlock), 0, s, n, srp, sci, h, st, m1);
-            hipLaunchKernelGGL(k_mis_m2, dim3(gsz(n)), dim3(kBlock), 0, s, n, srp, sci, h, m1, st);
-            hipLaunchKernelGGL(k_mis_r1, dim3(gsz(n)), dim3(kBlock), 0, s, n, srp, sci, st, r1);
-            zero(c.iscratch + 6, sizeof(int));
-            hipLaunchKernelGGL(k_mis_r2, dim3(gsz(n)), dim3(kBlock), 0, s, n, srp, sci, r1, st, c.iscratch + 6);
+            zero(und + round % kMisRing, kMisBatch * sizeof(int));
+            for (int b = 0; b < kMisBatch; ++b, ++round) {
+                const int *prev = round ? und + (round - 1) % kMisRing : nullptr;
+                hipLaunchKernelGGL(k_mis_m1, dim3(gsz(n)), dim3(kBlock), 0, s, n, srp, sci, h, st, m1, prev);
+                hipLaunchKernelGGL(k_mis_m2, dim3(gsz(n)), dim3(kBlock), 0, s, n, srp, sci, h, m1, st, prev);
+                hipLaunchKernelGGL(k_mis_r1, dim3(gsz(n)), dim3(kBlock), 0, s, n, srp, sci, st, r1, prev);
+                hipLaunchKernelGGL(k_mis_r2, dim3(gsz(n)), dim3(kBlock), 0, s, n, srp, sci, r1, st,
+                                   und + round % kMisRing, prev);
+            }
             check_kernels();
-            if (read_int(c.iscratch + 6) == 0) break;
+            if (read_int(und + (round - 1) % kMisRing) == 0) break;
         }
+        c.arena.release(und);
         L0.root = c.arena.alloc<uint8_t>(n);
         int *cid = c.arena.alloc<int>(n + 1);
         hipLaunchKernelGGL(k_root_flags, dim3(gsz(n)), dim3(kBlock), 0, s, n, st, L0.root, cnt);
-        const int nc = scan(cnt, cid, n);
+        scan(cnt, cid, n, false);  // the aggregate count stays in isc[8], read with the check below
         L0.agg = c.arena.alloc<int>(n);
         uint8_t *p2 = c.arena.alloc<uint8_t>(n);
         hipLaunchKernelGGL(k_phase2, dim3(gsz(n)), dim3(kBlock), 0, s, n, srp, sci, sabs, L0.root, cid, mask,
                            L0.agg, p2);
-        zero(c.iscratch + 7, sizeof(int));
-        hipLaunchKernelGGL(k_phase3, dim3(gsz(n)), dim3(kBlock), 0, s, n, srp, sci, sabs, p2, L0.agg,
-                           c.iscratch + 7);
+        zero(isc + 7, sizeof(int));
+        hipLaunchKernelGGL(k_phase3, dim3(gsz(n)), dim3(kBlock), 0, s, n, srp, sci, sabs, p2, L0.agg, isc + 7);
         check_kernels();
-        if (read_int(c.iscratch + 7)) fail(AMG_ERR_ARG, "aggregation left a node unassigned");
+        AMG_HIP(hipMemcpyAsync(hisc + 7, isc + 7, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipStreamSynchronize(s));
+        if (hisc[7]) fail(AMG_ERR_ARG, "aggregation left a node unassigned");
+        const int nc = hisc[8];
         for (void *p : {(void *)h, (void *)st, (void *)m1, (void *)r1, (void *)p2, (void *)sci, (void *)sabs,
                         (void *)srp, (void *)cid})
             c.arena.release(p);
@@ -1964,20 +2001,34 @@ struct Setup {
     void make_sell(DCsr &A) {
         const int nsl = ceil_div(A.n, 64);
         int *cnt = c.arena.alloc<int>(nsl + 1);
-        A.sl_off = c.arena.alloc<int>(nsl + 1);
-        hipLaunchKernelGGL(k_sell_width, dim3(gwave(nsl)), dim3(kBlock), 0, s, A.n, nsl, A.rp, cnt);
-        const int tot = scan(cnt, A.sl_off, nsl);
-        A.sl_ci = c.arena.alloc<int>(tot);
+        int *off = c.arena.alloc<int>(nsl + 1);
+        int *base = c.arena.alloc<int>(nsl);
+        zero(isc + 13, sizeof(int));
+        hipLaunchKernelGGL(k_sell_width, dim3(gwave(nsl)), dim3(kBlock), 0, s, A.n, nsl, A.rp, A.ci, cnt, base,
+                           isc + 13);
+        scan(cnt, off, nsl, false);
+        // the total (isc[8]) and the wide-slice flag (isc[13]) in one read
+        AMG_HIP(hipMemcpyAsync(hisc + 8, isc + 8, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+        AMG_HIP(hipStreamSynchronize(s));
+        const int tot = hisc[8];
+        c.arena.release(cnt);
+        if (hisc[13]) {  // 16-bit column offsets do not reach: the CSR kernels serve this matrix
+            c.arena.release(off);
+            c.arena.release(base);
+            return;
+        }
+        A.sl_off = off;
+        A.sl_base = base;
+        A.sl_cd = c.arena.alloc<uint16_t>(tot);
         A.sl_v = c.arena.alloc<double>(tot);
         hipLaunchKernelGGL(k_sell_fill, dim3(gwave(nsl)), dim3(kBlock), 0, s, A.n, nsl, A.rp, A.ci, A.v, A.sl_off,
-                           A.sl_ci, A.sl_v);
+                           A.sl_base, A.sl_cd, A.sl_v);
         if (A.v32) {
             A.sl_v32 = c.arena.alloc<float>(tot);
             hipLaunchKernelGGL(k_to_f32, dim3(gsz(tot)), dim3(kBlock), 0, s, (long)tot, A.sl_v, A.sl_v32);
         }
         A.nsl = nsl;
         check_kernels();
-        c.arena.release(cnt);
     }
 
     DenseOp dense_op(const double *inv, int n) {

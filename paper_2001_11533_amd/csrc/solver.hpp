@@ -71,7 +71,7 @@ template <int NB> struct Solver {
                 Reducer<(NV > 0 ? NV : 1), NB> red{part[pbuf]};
                 if (NV > 0) pgrid[pbuf] = g;
                 hipLaunchKernelGGL((sell_kernel<T, NV, GX, EP, PRO>), dim3(g), dim3(kBlock), 0, s, A.n, A.nsl,
-                                   A.sl_off, A.sl_ci, sv, gx, ep, red, stop, pro);
+                                   A.sl_off, A.sl_base, A.sl_cd, sv, gx, ep, red, stop, pro);
                 finish<NV>(pbuf, fin, stop);
                 return;
             }
