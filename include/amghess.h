@@ -238,7 +238,10 @@ const char *amg_last_error(amg_ctx *ctx);
  * stream, measured with HIP events: which = 0: level-0 SpMV (q = A_0 p), 1: the
  * level-0 first l1-Jacobi sweep fused with the residual (x = D^{-1} b, r = b - A_0 x,
  * the V-cycle's first kernel), 2: a whole V-cycle from level 0.  The kernels see
- * zero vectors.  prec: 64 or 32 (32 needs inner_precision 32); nb as above.
+ * zero vectors.  For which 0 and 1, on the level-0 sliced-ELL copy, successive
+ * launches rotate which XCD serves which slices, so that no launch finds its
+ * share of the matrix in the L2 where the launch before left it (back to back
+ * it would; in a solve other work separates the launches).  prec: 64 or 32 (32 needs inner_precision 32); nb as above.
  * *ms_avg receives milliseconds per launch and *bytes the algorithmic bytes one
  * launch moves (row pointers, column indices and values once, every vector it
  * reads or gathers once, every vector it writes once).  Level-0 products with one

@@ -662,6 +662,12 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
             hipEvent_t e0, e1;
             AMG_HIP(hipEventCreate(&e0));
             AMG_HIP(hipEventCreate(&e1));
+            // single kernels (which 0, 1): launch r serves its slices from XCD
+            // ranges rotated by r mod 8, so that no launch finds its share of
+            // the level-0 matrix in the L2 of the XCD the launch before left it
+            // in (back to back it would, unlike the launches in a solve, which
+            // other work separates)
+            const bool rotate = which < 2;
             auto run = [&](auto tT) {
                 using T = decltype(tT);
                 VcWs<T> &v = vcws<T>(c.ws[0]);
@@ -681,7 +687,11 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                 once();
                 AMG_HIP(hipStreamSynchronize(c.stream));
                 AMG_HIP(hipEventRecord(e0, c.stream));
-                for (int r = 0; r < reps; ++r) once();
+                for (int r = 0; r < reps; ++r) {
+                    if (rotate) S.xrot = (r + 1) % kXcd;
+                    once();
+                }
+                S.xrot = 0;
                 AMG_HIP(hipEventRecord(e1, c.stream));
                 AMG_HIP(hipEventSynchronize(e1));
             };

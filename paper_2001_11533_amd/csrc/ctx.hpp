@@ -43,9 +43,10 @@ template <typename T> struct CgWs {
     int pred = 0;  // iteration count of the previous solve (poll schedule)
     int run_it = 0; // iterations launched by a started (phase 1) solve
     int fused = -1; // 1: each iteration's finalize runs in the next iteration's first kernel
-    // captured graphs: first preconditioner application, iteration p0->p1, iteration p1->p0
-    hipGraphExec_t g0 = nullptr, ga = nullptr, gb = nullptr;
-    hipGraphExec_t g8 = nullptr;  // Jacobi CG: eight iterations (ga gb ga gb ...) in one launch
+    // captured graphs: first preconditioner application, iteration p0->p1 (a
+    // last single step only), the pair p0->p1->p0
+    hipGraphExec_t g0 = nullptr, ga = nullptr, g2 = nullptr;
+    hipGraphExec_t g8 = nullptr;  // Jacobi CG: eight iterations (four pairs) in one launch
 };
 
 template <typename T> struct VcWs {

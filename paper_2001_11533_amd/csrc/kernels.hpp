@@ -406,15 +406,16 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__re
 // per slice of 64 rows, one lane per row; a lane issues the loads of up to 16
 // entries of its row at once, with no dependence on row pointers.  Columns are
 // 16-bit offsets from the slice's base column (6 bytes per float32 entry).
+// xrot rotates the XCD-contiguous block ranges by xrot XCDs (0 in solves).
 template <typename T, int NV, class GX, class EP, class PRO = NoPro>
 __global__ __launch_bounds__(kBlock) void sell_kernel(int nrows, int nsl, const int *__restrict__ soff,
                                                       const int *__restrict__ sbase,
                                                       const uint16_t *__restrict__ cd, const T *__restrict__ av, GX gx,
                                                       EP ep, Reducer<(NV > 0 ? NV : 1), 1> red,
-                                                      const int *__restrict__ stop, PRO pro = PRO{}) {
+                                                      const int *__restrict__ stop, PRO pro = PRO{}, int xrot = 0) {
     if (stop && *stop) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int nblk = gridDim.x, b = xcd_block(blockIdx.x, nblk);
+    const int nblk = gridDim.x, b = (xcd_block(blockIdx.x, nblk) + xrot * (nblk / kXcd)) % nblk;
     constexpr int WPB = kBlock / 64;
     const int per = ceil_div_dev(nsl, nblk * WPB) * WPB;  // contiguous slices per workgroup
     const int s0 = b * per, s1 = min(nsl, s0 + per);

@@ -40,6 +40,8 @@ template <int NB> struct Solver {
     double **part;
     int *pgrid;
     hipEvent_t *pev;
+    // XCD rotation of sliced-ELL launches (kernel timing only; 0 in solves)
+    int xrot = 0;
     explicit Solver(Ctx &cc) : c(cc), s(cc.stream), part(cc.part), pgrid(cc.pgrid), pev(cc.poll_ev) {}
     Solver(Ctx &cc, hipStream_t st, double **pt, int *pg, hipEvent_t *ev)
         : c(cc), s(st), part(pt), pgrid(pg), pev(ev) {}
@@ -71,7 +73,7 @@ template <int NB> struct Solver {
                 Reducer<(NV > 0 ? NV : 1), NB> red{part[pbuf]};
                 if (NV > 0) pgrid[pbuf] = g;
                 hipLaunchKernelGGL((sell_kernel<T, NV, GX, EP, PRO>), dim3(g), dim3(kBlock), 0, s, A.n, A.nsl,
-                                   A.sl_off, A.sl_base, A.sl_cd, sv, gx, ep, red, stop, pro);
+                                   A.sl_off, A.sl_base, A.sl_cd, sv, gx, ep, red, stop, pro, xrot);
                 finish<NV>(pbuf, fin, stop);
                 return;
             }
@@ -402,10 +404,16 @@ template <int NB> struct Solver {
             else vcycle<T>(j, w.r, w.z, true, stop);
             if (!fused) finish<1>(2, FinRho0<NB>{w.sc}, stop);
         };
-        if (graphs && !w.ga) {
+        // Iterations go out in pairs (p0 -> p1 -> p0), one graph launch per pair,
+        // so the iteration count before a launch is even; a single iteration is
+        // issued only as the last one before maxit.  Iterations past convergence
+        // return at once in every kernel.
+        if (graphs && !w.g2) {
             if constexpr (!JAC) w.g0 = capture(first_precond);
-            w.ga = capture([&] { cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p0, w.p1); });
-            w.gb = capture([&] { cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p1, w.p0); });
+            w.g2 = capture([&] {
+                cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p0, w.p1);
+                cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p1, w.p0);
+            });
             // a mass iteration is two small kernels, faster than the host issues
             // one launch per iteration: its first batch goes out eight at a time
             if constexpr (JAC)
@@ -424,21 +432,26 @@ template <int NB> struct Solver {
         }
         int it = phase == 2 ? w.run_it : 0;
         auto step = [&]() {
-            if (graphs) launch((it & 1) ? w.gb : w.ga);
-            else if (it & 1) cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p1, w.p0);
-            else cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p0, w.p1);
-            ++it;
+            const bool pair = maxit - it >= 2;
+            if (graphs) {
+                if (!pair && !w.ga) w.ga = capture([&] { cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p0, w.p1); });
+                launch(pair ? w.g2 : w.ga);
+            } else {
+                cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p0, w.p1);
+                if (pair) cg_iter<T, JAC, MIX>(j, A, vals, dinv, w, w.p1, w.p0);
+            }
+            it += pair ? 2 : 1;
         };
         // The iterations the previous solve at this level needed (one more when
         // fused: the convergence of update k is decided in iteration k + 1) go
-        // out at once; then the host keeps kAhead iterations in flight beyond
-        // the last one it has seen, reading the mailbox after an event.
+        // out at once; then the host keeps kAhead launches in flight beyond the
+        // last one it has seen, reading the mailbox after an event.
         constexpr int kAhead = 1, kRing = Ctx::kPollRing;
         int posted = 1, seen = 0;
         if (phase != 2) {
             const int first = std::min(std::max(1, w.pred + (fused ? 1 : 0) + margin), maxit);
             while (it < first) {
-                if (graphs && w.g8 && (it & 1) == 0 && first - it >= 8) {
+                if (graphs && w.g8 && first - it >= 8) {
                     launch(w.g8);
                     it += 8;
                 } else {
