@@ -89,7 +89,8 @@ typedef struct {
     int32_t nb_max;         /* widest batch used with this context (1..16) */
     int32_t precond;        /* 1: multilevel preconditioner, 0: plain outer CG */
     int32_t check_every;    /* inner CG: host convergence poll period after the predicted count (1) */
-    int32_t use_graphs;     /* 1: replay CG iterations from captured HIP graphs (default), 0: launch eagerly */
+    int32_t use_graphs;     /* 1: replay CG iterations from captured HIP graphs, 0: launch eagerly,
+                               2 (default): graphs for the mass-matrix (Jacobi) CGs only */
     double coarse_hess_rtol;/* coarsest Hessian level above dense_max: unpreconditioned CG to this
                                relative residual (1e-4, Section 5.2); at or below dense_max it is
                                inverted exactly (Section 3.2) */
@@ -237,7 +238,9 @@ const char *amg_last_error(amg_ctx *ctx);
 /* Average device time of `reps` back-to-back launches of one kernel on the context's
  * stream, measured with HIP events: which = 0: level-0 SpMV (q = A_0 p), 1: the
  * level-0 first l1-Jacobi sweep fused with the residual (x = D^{-1} b, r = b - A_0 x,
- * the V-cycle's first kernel), 2: a whole V-cycle from level 0.  The kernels see
+ * the V-cycle's first kernel), 2: a whole V-cycle from level 0, 3: the level-0
+ * coarse correction fused with the first post-smoothing step (one pass over
+ * T_0 = A_0 S_0; Chebyshev form; needs a hierarchy that keeps T_0).  The kernels see
  * zero vectors.  For which 0 and 1, on the level-0 sliced-ELL copy, successive
  * launches rotate which XCD serves which slices, so that no launch finds its
  * share of the matrix in the L2 where the launch before left it (back to back

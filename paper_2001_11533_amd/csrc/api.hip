@@ -200,7 +200,7 @@ int amg_opts_default(amg_opts *o) {
     o->nb_max = 1;
     o->precond = 1;
     o->check_every = 1;
-    o->use_graphs = 1;
+    o->use_graphs = 2;
     o->coarse_hess_rtol = 1e-4;
     o->dense_solve_max = 2048;
     o->mixed_mode = 0;
@@ -230,7 +230,7 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
     if (!(o.beta > 0.0) || o.nb_max < 1 || o.nb_max > 16 || o.max_levels < 1 || o.max_coarse < 1 ||
         o.dense_max < 1 || o.dense_max > 4096 || (o.inner_precision != 32 && o.inner_precision != 64) ||
         o.nu != 1 || o.inner_maxit < 1 || o.mass_maxit < 1 || o.outer_maxit < 1 || o.hess_levels < 0 ||
-        !(o.theta0 >= 0.0) || o.refine_maxit < 1 || o.use_graphs < 0 || o.use_graphs > 1 ||
+        !(o.theta0 >= 0.0) || o.refine_maxit < 1 || o.use_graphs < 0 || o.use_graphs > 2 ||
         !(o.coarse_hess_rtol > 0.0) || o.dense_solve_max < 0 || o.dense_solve_max > 4096 || o.mixed_mode < 0 ||
         o.mixed_mode > 1 || o.smoother < 0 || o.smoother > 1) {
         g_setup_err = "invalid options (beta > 0, 1 <= nb_max <= 16, dense_max <= 4096, nu = 1, precision 32/64)";
@@ -639,13 +639,21 @@ int amg_hierarchy_quality(amg_ctx *ctx, int level, const double *v0, int iters, 
 
 int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double *ms_avg, double *bytes) {
     if (int e = check_vec_call(ctx ? &ctx->c : nullptr, 0, nb)) return e;
-    if (which < 0 || which > 2 || (prec != 32 && prec != 64) || reps < 1 || !ms_avg) return AMG_ERR_ARG;
+    if (which < 0 || which > 3 || (prec != 32 && prec != 64) || reps < 1 || !ms_avg) return AMG_ERR_ARG;
     Ctx &c = ctx->c;
     if (prec == 32 && c.o.inner_precision != 32) {
         c.err = "float32 kernels need inner_precision = 32";
         return AMG_ERR_ARG;
     }
     if (c.L < 2 && which > 0) return AMG_ERR_ARG;
+    if (which == 3) {
+        const Level &L0 = c.lev[0];
+        const bool has = L0.T.rp && (prec == 64 ? (L0.T.v && L0.Ts) : (L0.T.v32 && L0.Ts32));
+        if (!has) {
+            c.err = "level 0 keeps no T = A S for the fused coarse correction";
+            return AMG_ERR_ARG;
+        }
+    }
     return guarded(&c, [&]() {
         return dispatch_nb(c.nbp, [&](auto tag) {
             constexpr int NB = decltype(tag)::value;
@@ -678,12 +686,20 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                     else if (which == 1)  // the pre-sweep residual r = b - A x, x = D^{-1} b given
                         S.template spmv<T, 0>(L0.A, avals<T>(L0.A), GPlain<T, NB>{v.x}, EResB<T, NB>{v.b, v.r},
                                               NoFin{}, nullptr);
+                    else if (which == 3)  // coarse correction t += S e fused with the first post step
+                        S.template tpro<T, 0>(L0, vcws<T>(c.ws[1]).x,
+                                              EProCheb<T, NB>{v.t, v.r, dl1inv<T>(L0), v.x, T(1)}, nullptr);
                     else
                         S.template vcycle<T>(0, v.b, v.x2, false, nullptr);
                 };
                 // defined inputs
                 AMG_HIP(hipMemsetAsync(v.x, 0, sizeof(T) * n * NB, c.stream));
                 AMG_HIP(hipMemsetAsync(v.b, 0, sizeof(T) * n * NB, c.stream));
+                if (which == 3) {
+                    AMG_HIP(hipMemsetAsync(v.t, 0, sizeof(T) * n * NB, c.stream));
+                    AMG_HIP(hipMemsetAsync(v.r, 0, sizeof(T) * n * NB, c.stream));
+                    AMG_HIP(hipMemsetAsync(vcws<T>(c.ws[1]).x, 0, sizeof(T) * c.lev[1].n * NB, c.stream));
+                }
                 once();
                 AMG_HIP(hipStreamSynchronize(c.stream));
                 AMG_HIP(hipEventRecord(e0, c.stream));
@@ -706,6 +722,10 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                 if (which == 0) *bytes = spmv_b;
                 else if (which == 1)  // gathers x once, reads b, writes r
                     *bytes = 4.0 * (n + 1) + (ib(0) + sz) * L0.A.nnz + 3.0 * sz * n * nbd;
+                else if (which == 3)  // T's pattern with both value arrays, e gathered once,
+                                      // t, r and dinv read, t and y written
+                    *bytes = 4.0 * (n + 1) + (4.0 + 2.0 * sz) * L0.T.nnz + sz * c.lev[1].n * nbd +
+                             (4.0 * sz * nbd + sz) * n;
                 else {
                     // the cycle ends at the first level with a dense inverse
                     int Lc = c.L - 1;

@@ -398,7 +398,9 @@ template <int NB> struct Solver {
         if (phase != 2)
             elem<JAC ? 2 : 1>(n, OpInit<T, NB, JAC>{b, w.r, x, w.p0, z0, d0, r32, x32, d32, first_scale()},
                               FinInit<NB, JAC>{w.sc, rtol, nlive, (void *)x, fused}, nullptr, fused ? 1 : 0);
-        const bool graphs = c.o.use_graphs != 0;
+        // captured graphs for every CG (1) or only for the mass-matrix CGs (2),
+        // whose two-kernel iterations outrun eager launches from the host
+        const bool graphs = c.o.use_graphs == 1 || (c.o.use_graphs == 2 && JAC);
         auto first_precond = [&] {
             if constexpr (MIX) vcycle<float>(j, c.ws[j].b32, c.ws[j].d32, true, stop);
             else vcycle<T>(j, w.r, w.z, true, stop);

@@ -262,7 +262,8 @@ class HessianSolver:
         return a.value
 
     def time_kernel(self, which: int, prec: int = 64, nb: int = 1, reps: int = 50):
-        """(ms per launch, algorithmic bytes per launch) of 0: SpMV, 1: smoother sweep, 2: V-cycle."""
+        """(ms per launch, algorithmic bytes per launch) of 0: level-0 SpMV, 1: pre-sweep
+        residual, 2: V-cycle, 3: fused coarse correction and first post step at level 0."""
         ms, by = C.c_double(), C.c_double()
         check(lib().amg_time_kernel(self._h, which, prec, nb, reps, C.byref(ms), C.byref(by)), self._h)
         return ms.value, by.value
