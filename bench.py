@@ -40,12 +40,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def counter_traffic():
-    """HBM bytes per launch of the roofline kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE runs, scaled by the same counters' reading of a
-    plain 256 MiB copy; None once the kernel source has changed since."""
+def counter_traffic(name="sell_presweep_c3"):
+    """HBM bytes per launch of a timed kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (means over its timing loop's launches), scaled
+    by the same counters' reading of a plain 256 MiB copy; None once the kernel
+    source has changed since."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "sell_presweep_c3_hbm_counters.json")
+    path = os.path.join(ROOT, "profiles", f"{name}_hbm_counters.json")
     if not os.path.exists(path):
         return None
     m = json.load(open(path))
@@ -264,18 +265,20 @@ def main():
                     "outer_iters": max(i["outer_iters"] for i in infob)},
         "vcycle": {"f32_ms": vc_ms, "f32_GBps_alg": vc_bytes / (vc_ms * 1e-3) / 1e9,
                    "f64_ms": vc64_ms, "f64_GBps_alg": vc64_bytes / (vc64_ms * 1e-3) / 1e9},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(),
-                     "kernel": "level-0 float32 pre-sweep residual r = b - A x of the V-cycle (sell_kernel<float,0,GPlain,EResB>)",
-                     "ms": kern_ms, "bytes": kern_bytes,
-                     "timing": ("HIP events on the library stream over 200 back-to-back launches that "
-                                "rotate the slice-to-XCD assignment, so no launch reuses its L2")},
-        "roofline_tpro": {"bound": "hbm", "achieved": tpro_bytes / (tpro_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                          "unit": "GB/s", "frac": tpro_bytes / (tpro_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                          "kernel": ("level-0 float32 coarse correction fused with the first post step "
-                                     "(tpro_kernel<float,1,0,EProCheb>)"),
-                          "ms": tpro_ms, "bytes": tpro_bytes,
-                          "timing": "HIP events on the library stream over 200 back-to-back launches"},
+        "roofline": {"bound": "hbm", "achieved": tpro_bytes / (tpro_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": tpro_bytes / (tpro_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": counter_traffic("tpro_cheb_c3"),
+                     "kernel": ("level-0 float32 coarse correction fused with the first post-smoothing step, "
+                                "one pass over T = A S (tpro_kernel<float,1,0,EProCheb>)"),
+                     "ms": tpro_ms, "bytes": tpro_bytes,
+                     "timing": "HIP events on the library stream over 200 back-to-back launches"},
+        "roofline_presweep": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic("sell_presweep_c3"),
+                              "kernel": ("level-0 float32 pre-sweep residual r = b - A x of the V-cycle "
+                                         "(sell_kernel<float,0,GPlain,EResB>)"),
+                              "ms": kern_ms, "bytes": kern_bytes,
+                              "timing": ("HIP events on the library stream over 200 back-to-back launches that "
+                                         "rotate the slice-to-XCD assignment, so no launch reuses its L2")},
         "roofline_128cube": dict(big, note="same kernels on the 128^3 level-0 matrix, timed as in "
                                            "roofline; algorithmic bytes as in roofline"),
         "cpu_baseline": cpu,
