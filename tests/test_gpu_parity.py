@@ -296,3 +296,23 @@ def test_hierarchy_quality_against_oracle():
         assert abs(at_gpu - at_orc) <= 1e-8 * at_orc
         a, at = odense.quality(o.h, j)
         assert at_orc <= at * (1 + 1e-9) and at_orc >= 0.99 * at
+
+
+def test_time_kernel_entries():
+    # every entry of amg_time_kernel times its launches and reports algorithmic
+    # bytes; the level-0 entries run with and without the XCD rotation of the
+    # sliced-ELL kernel, which must leave the solver's own launches untouched
+    import paper_2001_11533_amd as amg
+    from paper_2001_11533_amd import AmgError
+    p, g, o = make("c3", 12, max_coarse=40, inner_precision=32, smoother=1)
+    yd = cuda(p.yd[:, 0])
+    u0, _ = g.reduced_solve(yd)
+    for which in range(4):
+        ms, by = g.time_kernel(which, prec=32, nb=1, reps=3)
+        assert ms > 0 and by > 0, which
+    ms, by = g.time_kernel(3, prec=64, nb=1, reps=3)
+    assert ms > 0 and by > 0
+    with pytest.raises(AmgError):
+        g.time_kernel(4, prec=32, nb=1, reps=3)
+    u1, _ = g.reduced_solve(yd)
+    assert torch.equal(u0, u1)

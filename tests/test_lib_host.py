@@ -84,7 +84,14 @@ def test_setup_argument_validation_without_gpu():
     o.beta = 1.0
     o.nb_max = 17
     assert L.lib().amg_setup(C.byref(a), C.byref(a), None, C.byref(o), None, C.byref(h)) == -1
+    L.lib().amg_opts_default(C.byref(o))
+    assert o.use_graphs == 2          # graphs for the mass-matrix CGs only
+    o.use_graphs = 3
+    assert L.lib().amg_setup(C.byref(a), C.byref(a), None, C.byref(o), None, C.byref(h)) == -1
     assert not h.value
+    # kernel timing: which outside 0..3 and a null context are rejected
+    ms, by = C.c_double(), C.c_double()
+    assert L.lib().amg_time_kernel(None, 3, 32, 1, 1, C.byref(ms), C.byref(by)) == -1
     # calls on a null context
     assert L.lib().state_solve(None, 0, None, None, 1, None) == -1
     assert L.lib().amg_destroy(None) == 0
