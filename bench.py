@@ -95,7 +95,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the reduced-Hessian solve of this library is a single-GPU "
-              "path (see the sharding notes in the design document); use --gpus 1", file=sys.stderr)
+              "path (independent desired states would shard by columns, one hierarchy replica per GPU; "
+              "that mode is not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
