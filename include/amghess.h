@@ -139,6 +139,28 @@ int amg_p1_assemble(int dim, int32_t nv, const double *coords, int32_t ne, const
                     const double *kappa, int32_t nnz, int32_t *rowptr, int32_t *col,
                     double *valA, double *valM);
 
+/* ---- The same assembly on the GPU (Section 2), bit-identical to amg_p1_assemble:
+ *      one thread per row adds the row vertex's element contributions in ascending
+ *      element index with the host's element arithmetic (no fused multiply-add). ----
+ * amg_p1_pattern_device: *nnz (host) = stored entries of the mesh graph.
+ *   elems: device int32 [ne x (dim+1)].
+ * amg_p1_assemble_device: device outputs rowptr[nv+1], col[nnz], valA[nnz], valM[nnz]
+ *   (caller-allocated, nnz from amg_p1_pattern_device); coords: device FP64 [nv x dim];
+ *   kappa: device FP64 [ne].  Columns sorted, explicit zeros kept.
+ * stream: a hipStream_t passed as void* (NULL: the default stream); the work runs on
+ *   it and both calls synchronise it before returning.  Temporary device memory
+ *   (vertex-to-element lists, counters: about 4 (2 nv + ne (dim+1)) bytes) is
+ *   allocated and freed inside the call.
+ * Errors: AMG_ERR_ARG for dim not 2/3, sizes <= 0, null pointers, out-of-range vertex
+ *   ids (checked on the device before any use), a total beyond int32 or an nnz that
+ *   differs from the mesh graph's; AMG_ERR_HIP when a HIP call fails. */
+int amg_p1_pattern_device(int dim, int32_t nv, int32_t ne, const int32_t *elems, int32_t *nnz,
+                          void *stream);
+int amg_p1_assemble_device(int dim, int32_t nv, const double *coords, int32_t ne,
+                           const int32_t *elems, const double *kappa, int32_t nnz,
+                           int32_t *rowptr, int32_t *col, double *valA, double *valM,
+                           void *stream);
+
 /* Build the context: the Dirichlet-reduced stiffness A_0, the smoothed-aggregation
  * hierarchy (strength graph, distance-2 aggregation, smoothed prolongators S_j and
  * their transposes, Galerkin products A_{j+1} = S_j^T A_j S_j and M_{j+1} = S_j^T M_j

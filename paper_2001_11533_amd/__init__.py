@@ -12,7 +12,7 @@ from ._lib import AmgError, LIB_PATH  # noqa: F401
 
 
 def __getattr__(name):
-    if name in ("HessianSolver", "assemble_p1", "default_opts", "release_memory"):
+    if name in ("HessianSolver", "assemble_p1", "assemble_p1_device", "default_opts", "release_memory"):
         from . import solver
         return getattr(solver, name)
     if name in ("StateSolve", "MassQuad", "reduced_functional"):

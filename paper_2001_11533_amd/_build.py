@@ -19,7 +19,7 @@ ARCH = "gfx950"
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", f"-I{INC}", "-Wno-unused-command-line-argument"]
 
-SOURCES = [("setup.hip", "hip"), ("api.hip", "hip"), ("assemble.cpp", "c++")]
+SOURCES = [("setup.hip", "hip"), ("api.hip", "hip"), ("assemble_gpu.hip", "hip"), ("assemble.cpp", "hip")]
 
 
 def _compile(src: str, lang: str) -> str:

@@ -1,76 +1,21 @@
 // Host P1 finite-element assembly (paper, Section 2: [A]_ij = a(phi_j, phi_i)
 // with a(y, v) = int kappa grad y . grad v, and [M]_ij = (phi_j, phi_i)).
 //
-// Element formulas (textbook P1 on a d-simplex with vertices x_0..x_d): J has
-// rows x_a - x_0; J^{-1} = adj(J)/det J; grad lambda_a (a >= 1) is column a of
-// J^{-1} and grad lambda_0 = -(sum of the others); K_T = kappa |T| G G^T,
-// M_T = |T| (1 + delta_ab) / ((d+1)(d+2)).  Each global entry adds its
-// element contributions in ascending element index; the pattern is the mesh
-// graph with sorted columns and explicit zeros kept.
+// The element matrices come from p1_element.hpp (shared with the device
+// assembler).  Each global entry adds its element contributions in ascending
+// element index; the pattern is the mesh graph with sorted columns and
+// explicit zeros kept.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <vector>
 
 #include "amghess.h"
+#include "p1_element.hpp"
 
 #pragma clang fp contract(off)
 
 namespace {
-
-struct Elem {
-    double K[4][4];
-    double M[4][4];
-};
-
-void element(int dim, const double *X, double kappa, Elem &e) {
-    // X: (dim+1) x dim vertex coordinates
-    double g[4][3];
-    double meas;
-    if (dim == 2) {
-        const double j00 = X[2] - X[0], j01 = X[3] - X[1];
-        const double j10 = X[4] - X[0], j11 = X[5] - X[1];
-        const double det = j00 * j11 - j01 * j10;
-        const double i00 = j11 / det, i01 = -j01 / det, i10 = -j10 / det, i11 = j00 / det;
-        g[1][0] = i00;
-        g[1][1] = i10;
-        g[2][0] = i01;
-        g[2][1] = i11;
-        meas = std::fabs(det) / 2.0;
-    } else {
-        const double a = X[3] - X[0], b = X[4] - X[1], c = X[5] - X[2];
-        const double ee = X[6] - X[0], f = X[7] - X[1], gg = X[8] - X[2];
-        const double h = X[9] - X[0], i = X[10] - X[1], k = X[11] - X[2];
-        const double c00 = f * k - gg * i;
-        const double c01 = gg * h - ee * k;
-        const double c02 = ee * i - f * h;
-        const double det = a * c00 + b * c01 + c * c02;
-        const double inv[3][3] = {
-            {c00 / det, (c * i - b * k) / det, (b * gg - c * f) / det},
-            {c01 / det, (a * k - c * h) / det, (c * ee - a * gg) / det},
-            {c02 / det, (b * h - a * i) / det, (a * f - b * ee) / det},
-        };
-        for (int q = 1; q <= 3; ++q)
-            for (int r = 0; r < 3; ++r) g[q][r] = inv[r][q - 1];
-        meas = std::fabs(det) / 6.0;
-    }
-    for (int r = 0; r < dim; ++r) {
-        double v = -g[1][r];
-        for (int q = 2; q <= dim; ++q) v = v - g[q][r];
-        g[0][r] = v;
-    }
-    const double w = kappa * meas;
-    const int nl = dim + 1;
-    for (int p = 0; p < nl; ++p)
-        for (int q = 0; q < nl; ++q) {
-            double dot = g[p][0] * g[q][0];
-            for (int r = 1; r < dim; ++r) dot = dot + g[p][r] * g[q][r];
-            e.K[p][q] = w * dot;
-        }
-    const double base = meas / (double)((dim + 1) * (dim + 2));
-    for (int p = 0; p < nl; ++p)
-        for (int q = 0; q < nl; ++q) e.M[p][q] = p == q ? 2.0 * base : base;
-}
 
 // vertex -> elements (ascending) adjacency
 void vertex_elems(int nl, int32_t nv, int32_t ne, const int32_t *elems, std::vector<int64_t> &vp,
@@ -133,7 +78,7 @@ extern "C" int amg_p1_assemble(int dim, int32_t nv, const double *coords, int32_
     int64_t pos = 0;
     rowptr[0] = 0;
     double X[12];
-    Elem el;
+    amg::P1Elem el;
     for (int32_t v = 0; v < nv; ++v) {
         row_pattern(nl, elems, vp, ve, v, cols);
         if (pos + (int64_t)cols.size() > nnz) return AMG_ERR_ARG;
@@ -148,7 +93,7 @@ extern "C" int amg_p1_assemble(int dim, int32_t nv, const double *coords, int32_
             const int32_t *ev = elems + (int64_t)e * nl;
             for (int a = 0; a < nl; ++a)
                 for (int r = 0; r < dim; ++r) X[a * dim + r] = coords[(int64_t)ev[a] * dim + r];
-            element(dim, X, kappa[e], el);
+            amg::p1_element(dim, X, kappa[e], el);
             int a = 0;
             while (ev[a] != v) ++a;
             for (int b = 0; b < nl; ++b) {

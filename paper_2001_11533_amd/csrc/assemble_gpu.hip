@@ -1,0 +1,259 @@
+// P1 finite-element assembly on the GPU (paper, Section 2: [A]_ij =
+// a(phi_j, phi_i), [M]_ij = (phi_j, phi_i)), bit-identical to the host
+// assembler: one thread forms one row, visiting the row vertex's elements in
+// ascending element index and adding each element's contributions with the
+// shared element arithmetic (p1_element.hpp, no fused multiply-add), exactly
+// the order in which the host adds them.
+//
+// Steps: vertex -> element lists (counts, exclusive scan, placement, then a
+// per-vertex sort so each list is ascending whatever order the placement
+// took); per row the sorted distinct neighbours by repeated minimum search
+// over the row vertex's elements (counts, scan, fill); then the values.
+#include <climits>
+#include <cstdint>
+
+#include "amghess.h"
+#include "p1_element.hpp"
+
+#pragma clang fp contract(off)
+
+namespace amg {
+namespace {
+
+constexpr int kAsmBlock = 256;
+
+int blocks_for(long n) {
+    long b = (n + kAsmBlock - 1) / kAsmBlock;
+    if (b < 1) b = 1;
+    if (b > 65536) b = 65536;
+    return (int)b;
+}
+
+__global__ void k_ids_in_range(long n, const int32_t *ids, int32_t nv, int *bad) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        if (ids[i] < 0 || ids[i] >= nv) *bad = 1;
+}
+
+__global__ void k_vertex_count(long n, const int32_t *ids, int32_t *cnt) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[ids[i]], 1);
+}
+
+// out[0..n]: exclusive sums of in[0..n-1] (out[n] the total) by one workgroup:
+// each thread sums a contiguous chunk, the chunk totals are scanned in LDS,
+// then each thread writes its chunk.  *over is set when the total passes int32.
+__global__ __launch_bounds__(1024) void k_scan_one(int32_t n, const int32_t *in, int32_t *out, int *over) {
+    __shared__ long long tot[1024];
+    const int t = threadIdx.x;
+    const long chunk = ((long)n + 1023) / 1024;
+    const long a = t * chunk, b = a + chunk < n ? a + chunk : n;
+    long long s = 0;
+    for (long i = a; i < b; ++i) s += in[i];
+    tot[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        long long run = 0;
+        for (int k = 0; k < 1024; ++k) {
+            const long long v = tot[k];
+            tot[k] = run;
+            run += v;
+        }
+        out[n] = run > INT_MAX ? INT_MAX : (int32_t)run;
+        if (run > INT_MAX) *over = 1;
+    }
+    __syncthreads();
+    long long run = tot[t];
+    for (long i = a; i < b; ++i) {
+        out[i] = run > INT_MAX ? INT_MAX : (int32_t)run;
+        run += in[i];
+    }
+}
+
+__global__ void k_vertex_place(int32_t ne, int nl, const int32_t *elems, const int32_t *vp, int32_t *fill,
+                               int32_t *ve) {
+    const long n = (long)ne * nl;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int32_t v = elems[i];
+        ve[vp[v] + atomicAdd(&fill[v], 1)] = (int32_t)(i / nl);
+    }
+}
+
+// each vertex's element list in ascending order (insertion sort: the lists
+// are as long as the number of elements around a vertex)
+__global__ void k_vertex_sort(int32_t nv, const int32_t *vp, int32_t *ve) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+        const int32_t p0 = vp[v], p1 = vp[v + 1];
+        for (int32_t p = p0 + 1; p < p1; ++p) {
+            const int32_t x = ve[p];
+            int32_t q = p - 1;
+            while (q >= p0 && ve[q] > x) {
+                ve[q + 1] = ve[q];
+                --q;
+            }
+            ve[q + 1] = x;
+        }
+    }
+}
+
+// the smallest vertex above `last` among the vertices of v's elements (INT_MAX: none)
+__device__ int32_t next_neighbour(int nl, const int32_t *elems, const int32_t *ve, int32_t p0, int32_t p1,
+                                  int32_t last) {
+    int32_t best = INT_MAX;
+    for (int32_t p = p0; p < p1; ++p) {
+        const int32_t *ev = elems + (long)ve[p] * nl;
+        for (int a = 0; a < nl; ++a) {
+            const int32_t k = ev[a];
+            if (k > last && k < best) best = k;
+        }
+    }
+    return best;
+}
+
+// row lengths (count) or columns (fill) of the mesh graph, sorted and distinct
+template <bool FILL>
+__global__ void k_row_pattern(int32_t nv, int nl, const int32_t *elems, const int32_t *vp, const int32_t *ve,
+                              int32_t *cnt, const int32_t *rowptr, int32_t *col) {
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+        const int32_t p0 = vp[v], p1 = vp[v + 1];
+        int32_t last = -1, m = 0;
+        for (;;) {
+            const int32_t k = next_neighbour(nl, elems, ve, p0, p1, last);
+            if (k == INT_MAX) break;
+            if constexpr (FILL) col[rowptr[v] + m] = k;
+            ++m;
+            last = k;
+        }
+        if constexpr (!FILL) cnt[v] = m;
+    }
+}
+
+__global__ void k_row_values(int dim, int32_t nv, const double *coords, const int32_t *elems,
+                             const double *kappa, const int32_t *vp, const int32_t *ve, const int32_t *rowptr,
+                             const int32_t *col, double *valA, double *valM) {
+    const int nl = dim + 1;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
+        const int32_t r0 = rowptr[v], r1 = rowptr[v + 1];
+        for (int32_t q = r0; q < r1; ++q) {
+            valA[q] = 0.0;
+            valM[q] = 0.0;
+        }
+        double X[12];
+        P1Elem el;
+        for (int32_t p = vp[v]; p < vp[v + 1]; ++p) {  // elements in ascending order
+            const int32_t e = ve[p];
+            const int32_t *ev = elems + (long)e * nl;
+            for (int a = 0; a < nl; ++a)
+                for (int r = 0; r < dim; ++r) X[a * dim + r] = coords[(long)ev[a] * dim + r];
+            p1_element(dim, X, kappa[e], el);
+            int a = 0;
+            while (ev[a] != v) ++a;
+            for (int b = 0; b < nl; ++b) {
+                const int32_t k = ev[b];
+                int32_t lo = r0, hi = r1;  // first position with col >= k
+                while (lo < hi) {
+                    const int32_t mid = lo + (hi - lo) / 2;
+                    if (col[mid] < k) lo = mid + 1;
+                    else hi = mid;
+                }
+                valA[lo] = valA[lo] + el.K[a][b];
+                valM[lo] = valM[lo] + el.M[a][b];
+            }
+        }
+    }
+}
+
+struct Dev {
+    void *p = nullptr;
+    ~Dev() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+#define ASM_HIP(x)                                   \
+    do {                                             \
+        if ((x) != hipSuccess) return AMG_ERR_HIP;   \
+    } while (0)
+
+// vertex -> element lists (vp[nv+1], ve ascending per vertex) and the row
+// lengths of the mesh graph (cnt[nv]) with their scan (rowptr[nv+1])
+int mesh_lists(int dim, int32_t nv, int32_t ne, const int32_t *elems, hipStream_t s, Dev &vp, Dev &ve,
+               Dev &rp, Dev &flags) {
+    const int nl = dim + 1;
+    const long nid = (long)ne * nl;
+    if (nid > INT_MAX) return AMG_ERR_ARG;
+    Dev cnt;
+    ASM_HIP(hipMalloc(&flags.p, 2 * sizeof(int)));
+    ASM_HIP(hipMalloc(&cnt.p, sizeof(int32_t) * ((size_t)nv + 1)));
+    ASM_HIP(hipMalloc(&vp.p, sizeof(int32_t) * ((size_t)nv + 1)));
+    ASM_HIP(hipMalloc(&ve.p, sizeof(int32_t) * (size_t)nid));
+    ASM_HIP(hipMalloc(&rp.p, sizeof(int32_t) * ((size_t)nv + 1)));
+    int *fl = (int *)flags.p;
+    int32_t *c = (int32_t *)cnt.p, *vpp = (int32_t *)vp.p, *vep = (int32_t *)ve.p, *rpp = (int32_t *)rp.p;
+    ASM_HIP(hipMemsetAsync(fl, 0, 2 * sizeof(int), s));
+    ASM_HIP(hipMemsetAsync(c, 0, sizeof(int32_t) * ((size_t)nv + 1), s));
+    hipLaunchKernelGGL(k_ids_in_range, dim3(blocks_for(nid)), dim3(kAsmBlock), 0, s, nid, elems, nv, fl);
+    int h[2];
+    ASM_HIP(hipMemcpyAsync(h, fl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    ASM_HIP(hipStreamSynchronize(s));
+    if (h[0]) return AMG_ERR_ARG;  // out-of-range vertex ids: nothing below indexes with them
+    hipLaunchKernelGGL(k_vertex_count, dim3(blocks_for(nid)), dim3(kAsmBlock), 0, s, nid, elems, c);
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, s, nv, c, vpp, fl + 1);
+    ASM_HIP(hipMemsetAsync(c, 0, sizeof(int32_t) * ((size_t)nv + 1), s));
+    hipLaunchKernelGGL(k_vertex_place, dim3(blocks_for(nid)), dim3(kAsmBlock), 0, s, ne, nl, elems, vpp, c, vep);
+    hipLaunchKernelGGL(k_vertex_sort, dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, vpp, vep);
+    hipLaunchKernelGGL((k_row_pattern<false>), dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, nl, elems, vpp,
+                       vep, c, (const int32_t *)nullptr, (int32_t *)nullptr);
+    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, s, nv, c, rpp, fl + 1);
+    ASM_HIP(hipGetLastError());
+    return AMG_OK;
+}
+
+bool valid_args(int dim, int32_t nv, int32_t ne, const int32_t *elems) {
+    return (dim == 2 || dim == 3) && nv > 0 && ne > 0 && elems;
+}
+
+}  // namespace
+}  // namespace amg
+
+extern "C" int amg_p1_pattern_device(int dim, int32_t nv, int32_t ne, const int32_t *elems, int32_t *nnz,
+                                     void *stream) {
+    using namespace amg;
+    if (!nnz || !valid_args(dim, nv, ne, elems)) return AMG_ERR_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    Dev vp, ve, rp, flags;
+    if (int e = mesh_lists(dim, nv, ne, elems, s, vp, ve, rp, flags)) return e;
+    int32_t tot = 0;
+    int over = 0;
+    ASM_HIP(hipMemcpyAsync(&tot, (int32_t *)rp.p + nv, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    ASM_HIP(hipMemcpyAsync(&over, (int *)flags.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    ASM_HIP(hipStreamSynchronize(s));
+    if (over) return AMG_ERR_ARG;
+    *nnz = tot;
+    return AMG_OK;
+}
+
+extern "C" int amg_p1_assemble_device(int dim, int32_t nv, const double *coords, int32_t ne, const int32_t *elems,
+                                      const double *kappa, int32_t nnz, int32_t *rowptr, int32_t *col,
+                                      double *valA, double *valM, void *stream) {
+    using namespace amg;
+    if (!coords || !kappa || !rowptr || !col || !valA || !valM || !valid_args(dim, nv, ne, elems))
+        return AMG_ERR_ARG;
+    const hipStream_t s = (hipStream_t)stream;
+    Dev vp, ve, rp, flags;
+    if (int e = mesh_lists(dim, nv, ne, elems, s, vp, ve, rp, flags)) return e;
+    int32_t tot = 0;
+    int over = 0;
+    ASM_HIP(hipMemcpyAsync(&tot, (int32_t *)rp.p + nv, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    ASM_HIP(hipMemcpyAsync(&over, (int *)flags.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    ASM_HIP(hipStreamSynchronize(s));
+    if (over || tot != nnz) return AMG_ERR_ARG;  // the caller's arrays do not fit this pattern
+    const int nl = dim + 1;
+    ASM_HIP(hipMemcpyAsync(rowptr, rp.p, sizeof(int32_t) * ((size_t)nv + 1), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL((k_row_pattern<true>), dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, nl, elems,
+                       (const int32_t *)vp.p, (const int32_t *)ve.p, (int32_t *)nullptr, rowptr, col);
+    hipLaunchKernelGGL(k_row_values, dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, dim, nv, coords, elems, kappa,
+                       (const int32_t *)vp.p, (const int32_t *)ve.p, rowptr, col, valA, valM);
+    ASM_HIP(hipGetLastError());
+    ASM_HIP(hipStreamSynchronize(s));
+    return AMG_OK;
+}

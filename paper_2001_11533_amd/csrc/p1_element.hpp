@@ -1,0 +1,73 @@
+// P1 element matrices on a d-simplex (paper, Section 2: [A]_ij = a(phi_j,
+// phi_i) with a(y, v) = int kappa grad y . grad v, and [M]_ij = (phi_j, phi_i)),
+// shared by the host and the device assembler so that both form every value
+// with the same operations in the same order.
+//
+// Textbook formulas: J has rows x_a - x_0; J^{-1} = adj(J)/det J; grad lambda_a
+// (a >= 1) is column a of J^{-1} and grad lambda_0 = -(sum of the others);
+// K_T = kappa |T| G G^T, M_T = |T| (1 + delta_ab) / ((d+1)(d+2)), formed
+// without fused multiply-add.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+namespace amg {
+
+struct P1Elem {
+    double K[4][4];
+    double M[4][4];
+};
+
+// X: (dim+1) x dim vertex coordinates, row-major
+__host__ __device__ inline void p1_element(int dim, const double *X, double kappa, P1Elem &e) {
+#pragma clang fp contract(off)
+    double g[4][3];
+    double meas;
+    if (dim == 2) {
+        const double j00 = X[2] - X[0], j01 = X[3] - X[1];
+        const double j10 = X[4] - X[0], j11 = X[5] - X[1];
+        const double det = j00 * j11 - j01 * j10;
+        const double i00 = j11 / det, i01 = -j01 / det, i10 = -j10 / det, i11 = j00 / det;
+        g[1][0] = i00;
+        g[1][1] = i10;
+        g[2][0] = i01;
+        g[2][1] = i11;
+        meas = fabs(det) / 2.0;
+    } else {
+        const double a = X[3] - X[0], b = X[4] - X[1], c = X[5] - X[2];
+        const double ee = X[6] - X[0], f = X[7] - X[1], gg = X[8] - X[2];
+        const double h = X[9] - X[0], i = X[10] - X[1], k = X[11] - X[2];
+        const double c00 = f * k - gg * i;
+        const double c01 = gg * h - ee * k;
+        const double c02 = ee * i - f * h;
+        const double det = a * c00 + b * c01 + c * c02;
+        const double inv[3][3] = {
+            {c00 / det, (c * i - b * k) / det, (b * gg - c * f) / det},
+            {c01 / det, (a * k - c * h) / det, (c * ee - a * gg) / det},
+            {c02 / det, (b * h - a * i) / det, (a * f - b * ee) / det},
+        };
+        for (int q = 1; q <= 3; ++q)
+            for (int r = 0; r < 3; ++r) g[q][r] = inv[r][q - 1];
+        meas = fabs(det) / 6.0;
+    }
+    for (int r = 0; r < dim; ++r) {
+        double v = -g[1][r];
+        for (int q = 2; q <= dim; ++q) v = v - g[q][r];
+        g[0][r] = v;
+    }
+    const double w = kappa * meas;
+    const int nl = dim + 1;
+    for (int p = 0; p < nl; ++p)
+        for (int q = 0; q < nl; ++q) {
+            double dot = g[p][0] * g[q][0];
+            for (int r = 1; r < dim; ++r) dot = dot + g[p][r] * g[q][r];
+            e.K[p][q] = w * dot;
+        }
+    const double base = meas / (double)((dim + 1) * (dim + 2));
+    for (int p = 0; p < nl; ++p)
+        for (int q = 0; q < nl; ++q) e.M[p][q] = p == q ? 2.0 * base : base;
+}
+
+}  // namespace amg

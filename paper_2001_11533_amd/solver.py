@@ -39,6 +39,35 @@ def assemble_p1(coords: np.ndarray, elems: np.ndarray, kappa: np.ndarray):
     return rowptr, col, valA, valM
 
 
+def assemble_p1_device(coords, elems, kappa):
+    """The same assembly on the GPU (amg_p1_pattern_device / amg_p1_assemble_device),
+    bit-identical to assemble_p1.  coords (nv x dim, float64), elems (ne x (dim+1),
+    int32) and kappa (ne, float64) are CUDA tensors; returns CUDA tensors (rowptr,
+    col, valA, valM), computed on torch's current stream."""
+    import torch
+    if not (coords.is_cuda and elems.is_cuda and kappa.is_cuda):
+        raise ValueError("assemble_p1_device takes device tensors")
+    coords = coords.to(torch.float64).contiguous()
+    elems = elems.to(torch.int32).contiguous()
+    kappa = kappa.to(torch.float64).contiguous()
+    dim = coords.shape[1]
+    nv, ne = coords.shape[0], elems.shape[0]
+    if elems.shape[1] != dim + 1 or kappa.shape[0] != ne:
+        raise ValueError("mesh arrays have inconsistent shapes")
+    L = lib()
+    stream = C.c_void_p(torch.cuda.current_stream(coords.device).cuda_stream)
+    nnz = C.c_int32(0)
+    check(L.amg_p1_pattern_device(dim, nv, ne, elems.data_ptr(), C.byref(nnz), stream))
+    dev = coords.device
+    rowptr = torch.empty(nv + 1, dtype=torch.int32, device=dev)
+    col = torch.empty(nnz.value, dtype=torch.int32, device=dev)
+    valA = torch.empty(nnz.value, dtype=torch.float64, device=dev)
+    valM = torch.empty(nnz.value, dtype=torch.float64, device=dev)
+    check(L.amg_p1_assemble_device(dim, nv, coords.data_ptr(), ne, elems.data_ptr(), kappa.data_ptr(), nnz.value,
+                                   rowptr.data_ptr(), col.data_ptr(), valA.data_ptr(), valM.data_ptr(), stream))
+    return rowptr, col, valA, valM
+
+
 def release_memory() -> None:
     """Return the device memory that ended contexts keep cached for later ones
     to the driver (amg_release_memory)."""
