@@ -7,8 +7,8 @@
 //
 // Steps: vertex -> element lists (counts, exclusive scan, placement, then a
 // per-vertex sort so each list is ascending whatever order the placement
-// took); per row the sorted distinct neighbours by repeated minimum search
-// over the row vertex's elements (counts, scan, fill); then the values.
+// took); per row the sorted distinct neighbours by repeated wavefront-minimum
+// search over the row vertex's elements (counts, scan, fill); then the values.
 #include <climits>
 #include <cstdint>
 
@@ -39,33 +39,75 @@ __global__ void k_vertex_count(long n, const int32_t *ids, int32_t *cnt) {
         atomicAdd(&cnt[ids[i]], 1);
 }
 
-// out[0..n]: exclusive sums of in[0..n-1] (out[n] the total) by one workgroup:
-// each thread sums a contiguous chunk, the chunk totals are scanned in LDS,
-// then each thread writes its chunk.  *over is set when the total passes int32.
-__global__ __launch_bounds__(1024) void k_scan_one(int32_t n, const int32_t *in, int32_t *out, int *over) {
-    __shared__ long long tot[1024];
+// out[0..n]: exclusive sums of in[0..n-1], out[n] the total, in three
+// launches over chunks of kScanChunk entries: chunk sums (coalesced loads),
+// their exclusive scan by one workgroup (which flags a total beyond int32),
+// then each chunk scanned in its workgroup from its offset.
+constexpr int kScanPer = 8, kScanChunk = kAsmBlock * kScanPer;
+
+__device__ long long block_sum(long long v, long long *red) {
     const int t = threadIdx.x;
-    const long chunk = ((long)n + 1023) / 1024;
-    const long a = t * chunk, b = a + chunk < n ? a + chunk : n;
-    long long s = 0;
-    for (long i = a; i < b; ++i) s += in[i];
-    tot[t] = s;
+    red[t] = v;
     __syncthreads();
-    if (t == 0) {
-        long long run = 0;
-        for (int k = 0; k < 1024; ++k) {
-            const long long v = tot[k];
-            tot[k] = run;
-            run += v;
+    for (int o = kAsmBlock / 2; o > 0; o >>= 1) {
+        if (t < o) red[t] += red[t + o];
+        __syncthreads();
+    }
+    const long long r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kAsmBlock) void k_scan_chunks(int32_t n, const int32_t *in, long long *csum) {
+    __shared__ long long red[kAsmBlock];
+    const long c0 = (long)blockIdx.x * kScanChunk;
+    long long s = 0;
+    for (int i = 0; i < kScanPer; ++i) {
+        const long j = c0 + (long)i * kAsmBlock + threadIdx.x;
+        if (j < n) s += in[j];
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) csum[blockIdx.x] = s;
+}
+
+__global__ void k_scan_offsets(int nchunks, long long *csum, int32_t n, int32_t *out, int *over) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    long long run = 0;
+    for (int c = 0; c < nchunks; ++c) {
+        const long long v = csum[c];
+        csum[c] = run;
+        run += v;
+    }
+    out[n] = run > INT_MAX ? INT_MAX : (int32_t)run;
+    if (run > INT_MAX) *over = 1;
+}
+
+__global__ __launch_bounds__(kAsmBlock) void k_scan_write(int32_t n, const int32_t *in, const long long *coff,
+                                                          int32_t *out) {
+    __shared__ long long part[kAsmBlock];
+    const int t = threadIdx.x;
+    const long base = (long)blockIdx.x * kScanChunk + (long)t * kScanPer;  // this thread's entries
+    int32_t v[kScanPer];
+    long long s = 0;
+    for (int i = 0; i < kScanPer; ++i) {
+        v[i] = base + i < n ? in[base + i] : 0;
+        s += v[i];
+    }
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {  // exclusive scan of the thread sums, in order
+        long long run = coff[blockIdx.x];
+        for (int k = 0; k < kAsmBlock; ++k) {
+            const long long x = part[k];
+            part[k] = run;
+            run += x;
         }
-        out[n] = run > INT_MAX ? INT_MAX : (int32_t)run;
-        if (run > INT_MAX) *over = 1;
     }
     __syncthreads();
-    long long run = tot[t];
-    for (long i = a; i < b; ++i) {
-        out[i] = run > INT_MAX ? INT_MAX : (int32_t)run;
-        run += in[i];
+    long long run = part[t];
+    for (int i = 0; i < kScanPer; ++i) {
+        if (base + i < n) out[base + i] = run > INT_MAX ? INT_MAX : (int32_t)run;
+        run += v[i];
     }
 }
 
@@ -95,35 +137,43 @@ __global__ void k_vertex_sort(int32_t nv, const int32_t *vp, int32_t *ve) {
     }
 }
 
-// the smallest vertex above `last` among the vertices of v's elements (INT_MAX: none)
-__device__ int32_t next_neighbour(int nl, const int32_t *elems, const int32_t *ve, int32_t p0, int32_t p1,
-                                  int32_t last) {
-    int32_t best = INT_MAX;
-    for (int32_t p = p0; p < p1; ++p) {
-        const int32_t *ev = elems + (long)ve[p] * nl;
-        for (int a = 0; a < nl; ++a) {
-            const int32_t k = ev[a];
-            if (k > last && k < best) best = k;
-        }
-    }
-    return best;
-}
-
-// row lengths (count) or columns (fill) of the mesh graph, sorted and distinct
+// Row lengths (count) or columns (fill) of the mesh graph, sorted and
+// distinct: one wavefront per row.  The candidates are the vertices of the row
+// vertex's elements (candidate c: vertex c % nl of its (c / nl)-th element);
+// lane l holds candidates l and l + 64 in registers and reads any further ones
+// from memory.  Each step takes the smallest candidate above the last one by a
+// wavefront minimum (INT_MAX, never a vertex id, marks none).
 template <bool FILL>
 __global__ void k_row_pattern(int32_t nv, int nl, const int32_t *elems, const int32_t *vp, const int32_t *ve,
                               int32_t *cnt, const int32_t *rowptr, int32_t *col) {
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
-        const int32_t p0 = vp[v], p1 = vp[v + 1];
+    const int lane = threadIdx.x & 63;
+    const long w0 = (blockIdx.x * (long)blockDim.x + threadIdx.x) >> 6;
+    const long nw = ((long)gridDim.x * blockDim.x) >> 6;
+    for (long v = w0; v < nv; v += nw) {
+        const int32_t p0 = vp[v];
+        const int32_t nc = (vp[v + 1] - p0) * nl;
+        auto cand = [&](int32_t c) { return elems[(long)ve[p0 + c / nl] * nl + c % nl]; };
+        const int32_t c0 = lane < nc ? cand(lane) : INT_MAX;
+        const int32_t c1 = lane + 64 < nc ? cand(lane + 64) : INT_MAX;
+        const int32_t base = FILL ? rowptr[v] : 0;
         int32_t last = -1, m = 0;
         for (;;) {
-            const int32_t k = next_neighbour(nl, elems, ve, p0, p1, last);
-            if (k == INT_MAX) break;
-            if constexpr (FILL) col[rowptr[v] + m] = k;
+            int32_t best = INT_MAX;
+            if (c0 > last) best = c0;
+            if (c1 > last && c1 < best) best = c1;
+            for (int32_t c = lane + 128; c < nc; c += 64) {
+                const int32_t k = cand(c);
+                if (k > last && k < best) best = k;
+            }
+            for (int off = 32; off > 0; off >>= 1) best = min(best, __shfl_xor(best, off));
+            if (best == INT_MAX) break;  // the same value in every lane: the loop ends for the wavefront
+            if constexpr (FILL)
+                if (lane == 0) col[base + m] = best;
             ++m;
-            last = k;
+            last = best;
         }
-        if constexpr (!FILL) cnt[v] = m;
+        if constexpr (!FILL)
+            if (lane == 0) cnt[v] = m;
     }
 }
 
@@ -138,13 +188,17 @@ __global__ void k_row_values(int dim, int32_t nv, const double *coords, const in
             valM[q] = 0.0;
         }
         double X[12];
-        P1Elem el;
+        double g[4][3];
+        double meas;
         for (int32_t p = vp[v]; p < vp[v + 1]; ++p) {  // elements in ascending order
             const int32_t e = ve[p];
             const int32_t *ev = elems + (long)e * nl;
             for (int a = 0; a < nl; ++a)
                 for (int r = 0; r < dim; ++r) X[a * dim + r] = coords[(long)ev[a] * dim + r];
-            p1_element(dim, X, kappa[e], el);
+            // the row of the element matrices that belongs to v, formed by the
+            // same helpers (hence the same operations) as the host's full matrices
+            p1_grads(dim, X, g, meas);
+            const double w = kappa[e] * meas;
             int a = 0;
             while (ev[a] != v) ++a;
             for (int b = 0; b < nl; ++b) {
@@ -155,8 +209,8 @@ __global__ void k_row_values(int dim, int32_t nv, const double *coords, const in
                     if (col[mid] < k) lo = mid + 1;
                     else hi = mid;
                 }
-                valA[lo] = valA[lo] + el.K[a][b];
-                valM[lo] = valM[lo] + el.M[a][b];
+                valA[lo] = valA[lo] + p1_stiff(dim, g, w, a, b);
+                valM[lo] = valM[lo] + p1_mass(dim, meas, a, b);
             }
         }
     }
@@ -174,6 +228,13 @@ struct Dev {
         if ((x) != hipSuccess) return AMG_ERR_HIP;   \
     } while (0)
 
+void scan(int32_t n, const int32_t *in, int32_t *out, long long *csum, int *over, hipStream_t s) {
+    const int nchunks = (int)(((long)n + kScanChunk - 1) / kScanChunk);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(nchunks), dim3(kAsmBlock), 0, s, n, in, csum);
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(64), 0, s, nchunks, csum, n, out, over);
+    hipLaunchKernelGGL(k_scan_write, dim3(nchunks), dim3(kAsmBlock), 0, s, n, in, (const long long *)csum, out);
+}
+
 // vertex -> element lists (vp[nv+1], ve ascending per vertex) and the row
 // lengths of the mesh graph (cnt[nv]) with their scan (rowptr[nv+1])
 int mesh_lists(int dim, int32_t nv, int32_t ne, const int32_t *elems, hipStream_t s, Dev &vp, Dev &ve,
@@ -181,8 +242,10 @@ int mesh_lists(int dim, int32_t nv, int32_t ne, const int32_t *elems, hipStream_
     const int nl = dim + 1;
     const long nid = (long)ne * nl;
     if (nid > INT_MAX) return AMG_ERR_ARG;
-    Dev cnt;
+    Dev cnt, cs;
     ASM_HIP(hipMalloc(&flags.p, 2 * sizeof(int)));
+    ASM_HIP(hipMalloc(&cs.p, sizeof(long long) * (((size_t)nv + kScanChunk - 1) / kScanChunk)));
+    long long *csum = (long long *)cs.p;
     ASM_HIP(hipMalloc(&cnt.p, sizeof(int32_t) * ((size_t)nv + 1)));
     ASM_HIP(hipMalloc(&vp.p, sizeof(int32_t) * ((size_t)nv + 1)));
     ASM_HIP(hipMalloc(&ve.p, sizeof(int32_t) * (size_t)nid));
@@ -197,13 +260,13 @@ int mesh_lists(int dim, int32_t nv, int32_t ne, const int32_t *elems, hipStream_
     ASM_HIP(hipStreamSynchronize(s));
     if (h[0]) return AMG_ERR_ARG;  // out-of-range vertex ids: nothing below indexes with them
     hipLaunchKernelGGL(k_vertex_count, dim3(blocks_for(nid)), dim3(kAsmBlock), 0, s, nid, elems, c);
-    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, s, nv, c, vpp, fl + 1);
+    scan(nv, c, vpp, csum, fl + 1, s);
     ASM_HIP(hipMemsetAsync(c, 0, sizeof(int32_t) * ((size_t)nv + 1), s));
     hipLaunchKernelGGL(k_vertex_place, dim3(blocks_for(nid)), dim3(kAsmBlock), 0, s, ne, nl, elems, vpp, c, vep);
     hipLaunchKernelGGL(k_vertex_sort, dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, vpp, vep);
-    hipLaunchKernelGGL((k_row_pattern<false>), dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, nl, elems, vpp,
-                       vep, c, (const int32_t *)nullptr, (int32_t *)nullptr);
-    hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(1024), 0, s, nv, c, rpp, fl + 1);
+    hipLaunchKernelGGL((k_row_pattern<false>), dim3(blocks_for(64L * nv)), dim3(kAsmBlock), 0, s, nv, nl, elems,
+                       vpp, vep, c, (const int32_t *)nullptr, (int32_t *)nullptr);
+    scan(nv, c, rpp, csum, fl + 1, s);
     ASM_HIP(hipGetLastError());
     return AMG_OK;
 }
@@ -249,7 +312,7 @@ extern "C" int amg_p1_assemble_device(int dim, int32_t nv, const double *coords,
     if (over || tot != nnz) return AMG_ERR_ARG;  // the caller's arrays do not fit this pattern
     const int nl = dim + 1;
     ASM_HIP(hipMemcpyAsync(rowptr, rp.p, sizeof(int32_t) * ((size_t)nv + 1), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL((k_row_pattern<true>), dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, nl, elems,
+    hipLaunchKernelGGL((k_row_pattern<true>), dim3(blocks_for(64L * nv)), dim3(kAsmBlock), 0, s, nv, nl, elems,
                        (const int32_t *)vp.p, (const int32_t *)ve.p, (int32_t *)nullptr, rowptr, col);
     hipLaunchKernelGGL(k_row_values, dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, dim, nv, coords, elems, kappa,
                        (const int32_t *)vp.p, (const int32_t *)ve.p, rowptr, col, valA, valM);

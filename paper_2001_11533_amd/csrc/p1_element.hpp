@@ -20,11 +20,10 @@ struct P1Elem {
     double M[4][4];
 };
 
-// X: (dim+1) x dim vertex coordinates, row-major
-__host__ __device__ inline void p1_element(int dim, const double *X, double kappa, P1Elem &e) {
+// Gradients of the barycentric functions (g[a][0..dim-1], a = 0..dim) and the
+// element measure.  X: (dim+1) x dim vertex coordinates, row-major.
+__host__ __device__ inline void p1_grads(int dim, const double *X, double (&g)[4][3], double &meas) {
 #pragma clang fp contract(off)
-    double g[4][3];
-    double meas;
     if (dim == 2) {
         const double j00 = X[2] - X[0], j01 = X[3] - X[1];
         const double j10 = X[4] - X[0], j11 = X[5] - X[1];
@@ -57,17 +56,36 @@ __host__ __device__ inline void p1_element(int dim, const double *X, double kapp
         for (int q = 2; q <= dim; ++q) v = v - g[q][r];
         g[0][r] = v;
     }
+}
+
+// K_T[p][q] = w grad lambda_p . grad lambda_q with w = kappa |T|
+__host__ __device__ inline double p1_stiff(int dim, const double (&g)[4][3], double w, int p, int q) {
+#pragma clang fp contract(off)
+    double dot = g[p][0] * g[q][0];
+    for (int r = 1; r < dim; ++r) dot = dot + g[p][r] * g[q][r];
+    return w * dot;
+}
+
+// M_T[p][q] = |T| (1 + delta_pq) / ((d+1)(d+2))
+__host__ __device__ inline double p1_mass(int dim, double meas, int p, int q) {
+#pragma clang fp contract(off)
+    const double base = meas / (double)((dim + 1) * (dim + 2));
+    return p == q ? 2.0 * base : base;
+}
+
+// both element matrices
+__host__ __device__ inline void p1_element(int dim, const double *X, double kappa, P1Elem &e) {
+#pragma clang fp contract(off)
+    double g[4][3];
+    double meas;
+    p1_grads(dim, X, g, meas);
     const double w = kappa * meas;
     const int nl = dim + 1;
     for (int p = 0; p < nl; ++p)
         for (int q = 0; q < nl; ++q) {
-            double dot = g[p][0] * g[q][0];
-            for (int r = 1; r < dim; ++r) dot = dot + g[p][r] * g[q][r];
-            e.K[p][q] = w * dot;
+            e.K[p][q] = p1_stiff(dim, g, w, p, q);
+            e.M[p][q] = p1_mass(dim, meas, p, q);
         }
-    const double base = meas / (double)((dim + 1) * (dim + 2));
-    for (int p = 0; p < nl; ++p)
-        for (int q = 0; q < nl; ++q) e.M[p][q] = p == q ? 2.0 * base : base;
 }
 
 }  // namespace amg
