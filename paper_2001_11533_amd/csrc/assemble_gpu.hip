@@ -177,40 +177,61 @@ __global__ void k_row_pattern(int32_t nv, int nl, const int32_t *elems, const in
     }
 }
 
-__global__ void k_row_values(int dim, int32_t nv, const double *coords, const int32_t *elems,
-                             const double *kappa, const int32_t *vp, const int32_t *ve, const int32_t *rowptr,
-                             const int32_t *col, double *valA, double *valM) {
-    const int nl = dim + 1;
+// DIM is a template parameter so that the small coordinate and gradient arrays
+// stay in registers (all their indices are compile-time after unrolling; the
+// row's own gradient is picked by predication).
+template <int DIM>
+__global__ void k_row_values(int32_t nv, const double *coords, const int32_t *elems, const double *kappa,
+                             const int32_t *vp, const int32_t *ve, const int32_t *rowptr, const int32_t *col,
+                             double *valA, double *valM) {
+    constexpr int NL = DIM + 1;
     for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += gridDim.x * blockDim.x) {
         const int32_t r0 = rowptr[v], r1 = rowptr[v + 1];
         for (int32_t q = r0; q < r1; ++q) {
             valA[q] = 0.0;
             valM[q] = 0.0;
         }
-        double X[12];
-        double g[4][3];
-        double meas;
         for (int32_t p = vp[v]; p < vp[v + 1]; ++p) {  // elements in ascending order
             const int32_t e = ve[p];
-            const int32_t *ev = elems + (long)e * nl;
-            for (int a = 0; a < nl; ++a)
-                for (int r = 0; r < dim; ++r) X[a * dim + r] = coords[(long)ev[a] * dim + r];
+            const int32_t *ev = elems + (long)e * NL;
+            int32_t vid[NL];
+            double X[NL * DIM];
+#pragma unroll
+            for (int a = 0; a < NL; ++a) {
+                vid[a] = ev[a];
+#pragma unroll
+                for (int r = 0; r < DIM; ++r) X[a * DIM + r] = coords[(long)vid[a] * DIM + r];
+            }
             // the row of the element matrices that belongs to v, formed by the
             // same helpers (hence the same operations) as the host's full matrices
-            p1_grads(dim, X, g, meas);
+            double g[4][3];
+            double meas;
+            p1_grads(DIM, X, g, meas);
             const double w = kappa[e] * meas;
-            int a = 0;
-            while (ev[a] != v) ++a;
-            for (int b = 0; b < nl; ++b) {
-                const int32_t k = ev[b];
+            int a = 0;  // v's place in the element (its first, as on the host)
+#pragma unroll
+            for (int b = NL - 1; b >= 0; --b)
+                if (vid[b] == v) a = b;
+            double ga[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) ga[r] = 0.0;
+#pragma unroll
+            for (int b = 0; b < NL; ++b)
+                if (b == a) {
+#pragma unroll
+                    for (int r = 0; r < DIM; ++r) ga[r] = g[b][r];
+                }
+#pragma unroll
+            for (int b = 0; b < NL; ++b) {
+                const int32_t k = vid[b];
                 int32_t lo = r0, hi = r1;  // first position with col >= k
                 while (lo < hi) {
                     const int32_t mid = lo + (hi - lo) / 2;
                     if (col[mid] < k) lo = mid + 1;
                     else hi = mid;
                 }
-                valA[lo] = valA[lo] + p1_stiff(dim, g, w, a, b);
-                valM[lo] = valM[lo] + p1_mass(dim, meas, a, b);
+                valA[lo] = valA[lo] + p1_stiff_vec(DIM, ga, g[b], w);
+                valM[lo] = valM[lo] + p1_mass(DIM, meas, a, b);
             }
         }
     }
@@ -314,8 +335,12 @@ extern "C" int amg_p1_assemble_device(int dim, int32_t nv, const double *coords,
     ASM_HIP(hipMemcpyAsync(rowptr, rp.p, sizeof(int32_t) * ((size_t)nv + 1), hipMemcpyDeviceToDevice, s));
     hipLaunchKernelGGL((k_row_pattern<true>), dim3(blocks_for(64L * nv)), dim3(kAsmBlock), 0, s, nv, nl, elems,
                        (const int32_t *)vp.p, (const int32_t *)ve.p, (int32_t *)nullptr, rowptr, col);
-    hipLaunchKernelGGL(k_row_values, dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, dim, nv, coords, elems, kappa,
-                       (const int32_t *)vp.p, (const int32_t *)ve.p, rowptr, col, valA, valM);
+    if (dim == 2)
+        hipLaunchKernelGGL((k_row_values<2>), dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, coords, elems, kappa,
+                           (const int32_t *)vp.p, (const int32_t *)ve.p, rowptr, col, valA, valM);
+    else
+        hipLaunchKernelGGL((k_row_values<3>), dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, coords, elems, kappa,
+                           (const int32_t *)vp.p, (const int32_t *)ve.p, rowptr, col, valA, valM);
     ASM_HIP(hipGetLastError());
     ASM_HIP(hipStreamSynchronize(s));
     return AMG_OK;

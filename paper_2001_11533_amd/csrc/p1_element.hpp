@@ -58,12 +58,17 @@ __host__ __device__ inline void p1_grads(int dim, const double *X, double (&g)[4
     }
 }
 
-// K_T[p][q] = w grad lambda_p . grad lambda_q with w = kappa |T|
-__host__ __device__ inline double p1_stiff(int dim, const double (&g)[4][3], double w, int p, int q) {
+// w gp . gq (w = kappa |T|, gp and gq two rows of the gradients)
+__host__ __device__ inline double p1_stiff_vec(int dim, const double *gp, const double *gq, double w) {
 #pragma clang fp contract(off)
-    double dot = g[p][0] * g[q][0];
-    for (int r = 1; r < dim; ++r) dot = dot + g[p][r] * g[q][r];
+    double dot = gp[0] * gq[0];
+    for (int r = 1; r < dim; ++r) dot = dot + gp[r] * gq[r];
     return w * dot;
+}
+
+// K_T[p][q] = w grad lambda_p . grad lambda_q
+__host__ __device__ inline double p1_stiff(int dim, const double (&g)[4][3], double w, int p, int q) {
+    return p1_stiff_vec(dim, g[p], g[q], w);
 }
 
 // M_T[p][q] = |T| (1 + delta_pq) / ((d+1)(d+2))
