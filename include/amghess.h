@@ -149,11 +149,14 @@ int amg_p1_assemble(int dim, int32_t nv, const double *coords, int32_t ne, const
  *   kappa: device FP64 [ne].  Columns sorted, explicit zeros kept.
  * stream: a hipStream_t passed as void* (NULL: the default stream); the work runs on
  *   it and both calls synchronise it before returning.  Temporary device memory
- *   (vertex-to-element lists, counters: about 4 (2 nv + ne (dim+1)) bytes) is
- *   allocated and freed inside the call.
+ *   (vertex-to-element lists, row counts and pointers, scan sums: about
+ *   4 (3 nv + ne (dim+1)) bytes) comes from the library's process-wide cache of
+ *   device blocks and goes back to it when the call returns (a new block is
+ *   allocated only when the cache holds none of a fitting size).
  * Errors: AMG_ERR_ARG for dim not 2/3, sizes <= 0, null pointers, out-of-range vertex
  *   ids (checked on the device before any use), a total beyond int32 or an nnz that
- *   differs from the mesh graph's; AMG_ERR_HIP when a HIP call fails. */
+ *   differs from the mesh graph's; AMG_ERR_OOM when the workspace cannot be
+ *   allocated; AMG_ERR_HIP when another HIP call fails. */
 int amg_p1_pattern_device(int dim, int32_t nv, int32_t ne, const int32_t *elems, int32_t *nnz,
                           void *stream);
 int amg_p1_assemble_device(int dim, int32_t nv, const double *coords, int32_t ne,
@@ -239,6 +242,18 @@ int amg_copy_csr(amg_ctx *ctx, int level, int which, int32_t *rowptr, int32_t *c
 /* which: 0 = inverse of the coarsest A (n_{L-1}^2), 1 = dense coarsest Hessian H_{l-1},
  *        2 = its inverse.  Row-major FP64. */
 int amg_copy_dense(amg_ctx *ctx, int which, int32_t *n, double *out);
+/* x = V_j b: one application of the AMG V-cycle from level j, the preconditioner of
+ * every A_j-solve (Section 5.2 applies K and K^* by AMG-preconditioned CG): the
+ * smoothing pass (opts.smoother) before and after the coarse correction S_j V_{j+1}
+ * S_j^T r, ending with the exact dense solve at the coarsest level or at the first
+ * coarse level j >= 1 with at most opts.dense_solve_max rows.
+ *   prec: 64 (FP64 cycle) or 32 (the float32 cycle of inner_precision 32; b is
+ *   rounded to float32 on entry, x is the float32 result widened).
+ *   b, x: device FP64 [n_j x nb], caller-owned, not aliased.
+ * Errors: AMG_ERR_ARG for a bad level, nb, prec (32 needs inner_precision 32) or
+ * null pointers. */
+int amg_vcycle_apply(amg_ctx *ctx, int level, int prec, const double *b, double *x, int nb);
+
 /* Use l Hessian levels from now on (1 <= l <= L); rebuilds the dense H_{l-1}. */
 int amg_set_hess_levels(amg_ctx *ctx, int ell);
 

@@ -80,6 +80,7 @@ SIGNATURES = {
     "amg_last_error": (C.c_char_p, [P]),
     "amg_time_kernel": (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_int, PD, PD]),
     "amg_hierarchy_quality": (C.c_int, [P, C.c_int, C.c_void_p, C.c_int, PD]),
+    "amg_vcycle_apply": (C.c_int, [P, C.c_int, C.c_int, P, P, C.c_int]),
 }
 
 _lib = None

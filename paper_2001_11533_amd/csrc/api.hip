@@ -637,6 +637,39 @@ int amg_hierarchy_quality(amg_ctx *ctx, int level, const double *v0, int iters, 
     });
 }
 
+int amg_vcycle_apply(amg_ctx *ctx, int level, int prec, const double *b, double *x, int nb) {
+    if (int e = check_vec_call(ctx ? &ctx->c : nullptr, level, nb)) return e;
+    if (!b || !x || (prec != 32 && prec != 64)) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    if (prec == 32 && c.o.inner_precision != 32) {
+        c.err = "the float32 V-cycle needs inner_precision = 32";
+        return AMG_ERR_ARG;
+    }
+    return guarded(&c, [&]() {
+        const int n = c.lev[level].n;
+        return dispatch_nb(c.nbp, [&](auto tag) {
+            constexpr int NB = decltype(tag)::value;
+            Solver<NB> S(c);
+            auto run = [&](auto tT) {
+                using T = decltype(tT);
+                VcWs<T> &v = vcws<T>(c.ws[level]);
+                // the first smoothing iterate is needed only where the cycle smooths
+                const bool smooths = level < c.L - 1 && !c.lev[level].Ainv;
+                S.template elem<0>(n, OpVcIn<T, NB>{v.b, smooths ? v.x : nullptr, b, dl1inv<T>(c.lev[level]),
+                                                    (T)S.first_scale(), nb},
+                                   NoFin{}, nullptr);
+                if (smooths) S.template vcycle<T>(level, v.b, v.x2, false, nullptr);
+                else S.template dense_apply<T>(level == c.L - 1 ? c.dAc : c.lev[level].dA, v.b, v.x2, nullptr);
+                S.template elem<0>(n, OpVcOut<T, NB>{x, v.x2, nb}, NoFin{}, nullptr);
+            };
+            if (prec == 64) run(double{});
+            else run(float{});
+            AMG_HIP(hipStreamSynchronize(c.stream));
+            return AMG_OK;
+        });
+    });
+}
+
 int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double *ms_avg, double *bytes) {
     if (int e = check_vec_call(ctx ? &ctx->c : nullptr, 0, nb)) return e;
     if (which < 0 || which > 3 || (prec != 32 && prec != 64) || reps < 1 || !ms_avg) return AMG_ERR_ARG;

@@ -12,7 +12,7 @@
 #include <climits>
 #include <cstdint>
 
-#include "amghess.h"
+#include "common.hpp"
 #include "p1_element.hpp"
 
 #pragma clang fp contract(off)
@@ -237,17 +237,93 @@ __global__ void k_row_values(int32_t nv, const double *coords, const int32_t *el
     }
 }
 
-struct Dev {
-    void *p = nullptr;
-    ~Dev() {
-        if (p) (void)hipFree(p);
-    }
+#define ASM_HIP(x)                                                                   \
+    do {                                                                             \
+        const hipError_t e_ = (x);                                                   \
+        if (e_ != hipSuccess) return e_ == hipErrorOutOfMemory ? AMG_ERR_OOM : AMG_ERR_HIP; \
+    } while (0)
+
+// fills n ints with v (used instead of a memset node, so the clears stay
+// kernels of the caller's stream)
+__global__ void k_fill(long n, int32_t *p, int32_t v) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// The temporary arrays of one assembly, carved from one workspace: error
+// flags, chunk sums of the scans, row counts, the vertex -> element lists
+// (vp, ve) and the mesh graph's row pointers (rp).
+struct AsmScratch {
+    int *flags = nullptr;      // [2]: vertex id out of range, total beyond int32
+    long long *csum = nullptr; // [chunks]
+    int32_t *cnt = nullptr, *vp = nullptr, *ve = nullptr, *rp = nullptr;
 };
 
-#define ASM_HIP(x)                                   \
-    do {                                             \
-        if ((x) != hipSuccess) return AMG_ERR_HIP;   \
-    } while (0)
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t scratch_bytes(int dim, int32_t nv, int32_t ne) {
+    const size_t nid = (size_t)ne * (dim + 1), nv1 = (size_t)nv + 1;
+    const size_t chunks = ((size_t)nv + kScanChunk - 1) / kScanChunk;
+    return round256(2 * sizeof(int)) + round256(chunks * sizeof(long long)) + 3 * round256(nv1 * sizeof(int32_t)) +
+           round256(nid * sizeof(int32_t));
+}
+
+AsmScratch carve(void *base, int dim, int32_t nv, int32_t ne) {
+    const size_t nid = (size_t)ne * (dim + 1), nv1 = (size_t)nv + 1;
+    const size_t chunks = ((size_t)nv + kScanChunk - 1) / kScanChunk;
+    char *p = static_cast<char *>(base);
+    AsmScratch a;
+    auto take = [&](size_t b) {
+        char *q = p;
+        p += round256(b);
+        return q;
+    };
+    a.flags = (int *)take(2 * sizeof(int));
+    a.csum = (long long *)take(chunks * sizeof(long long));
+    a.cnt = (int32_t *)take(nv1 * sizeof(int32_t));
+    a.vp = (int32_t *)take(nv1 * sizeof(int32_t));
+    a.ve = (int32_t *)take(nid * sizeof(int32_t));
+    a.rp = (int32_t *)take(nv1 * sizeof(int32_t));
+    return a;
+}
+
+// A workspace from the process-wide cache of device blocks (a block of a
+// little more than the size asked for, or a new allocation), handed back to
+// the cache, not freed, once the stream has run the work that uses it: so
+// repeated assemblies call neither hipMalloc nor hipFree (which waits for the
+// whole device).
+struct PoolBlock {
+    int dev = -1;
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipStream_t s = nullptr;
+    int get(size_t b, hipStream_t st) {
+        s = st;
+        ASM_HIP(hipGetDevice(&dev));
+        auto got = DevPool::get().take(dev, b);
+        if (!got.first) {
+            void *q = nullptr;
+            hipError_t e = hipMalloc(&q, b);
+            if (e != hipSuccess) {  // once more without the cached blocks of this device
+                (void)hipGetLastError();
+                DevPool::get().release(dev);
+                e = hipMalloc(&q, b);
+            }
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return e == hipErrorOutOfMemory ? AMG_ERR_OOM : AMG_ERR_HIP;
+            }
+            got = {q, b};
+        }
+        p = got.first;
+        bytes = got.second;
+        return AMG_OK;
+    }
+    ~PoolBlock() {
+        if (!p) return;
+        (void)hipStreamSynchronize(s);
+        if (!DevPool::get().give(dev, p, bytes)) (void)hipFree(p);
+    }
+};
 
 void scan(int32_t n, const int32_t *in, int32_t *out, long long *csum, int *over, hipStream_t s) {
     const int nchunks = (int)(((long)n + kScanChunk - 1) / kScanChunk);
@@ -257,43 +333,61 @@ void scan(int32_t n, const int32_t *in, int32_t *out, long long *csum, int *over
 }
 
 // vertex -> element lists (vp[nv+1], ve ascending per vertex) and the row
-// lengths of the mesh graph (cnt[nv]) with their scan (rowptr[nv+1])
-int mesh_lists(int dim, int32_t nv, int32_t ne, const int32_t *elems, hipStream_t s, Dev &vp, Dev &ve,
-               Dev &rp, Dev &flags) {
+// lengths of the mesh graph with their scan (rp[nv+1]); *total gets rp[nv]
+int mesh_lists(int dim, int32_t nv, int32_t ne, const int32_t *elems, hipStream_t s, const AsmScratch &w,
+               int32_t *total) {
     const int nl = dim + 1;
     const long nid = (long)ne * nl;
-    if (nid > INT_MAX) return AMG_ERR_ARG;
-    Dev cnt, cs;
-    ASM_HIP(hipMalloc(&flags.p, 2 * sizeof(int)));
-    ASM_HIP(hipMalloc(&cs.p, sizeof(long long) * (((size_t)nv + kScanChunk - 1) / kScanChunk)));
-    long long *csum = (long long *)cs.p;
-    ASM_HIP(hipMalloc(&cnt.p, sizeof(int32_t) * ((size_t)nv + 1)));
-    ASM_HIP(hipMalloc(&vp.p, sizeof(int32_t) * ((size_t)nv + 1)));
-    ASM_HIP(hipMalloc(&ve.p, sizeof(int32_t) * (size_t)nid));
-    ASM_HIP(hipMalloc(&rp.p, sizeof(int32_t) * ((size_t)nv + 1)));
-    int *fl = (int *)flags.p;
-    int32_t *c = (int32_t *)cnt.p, *vpp = (int32_t *)vp.p, *vep = (int32_t *)ve.p, *rpp = (int32_t *)rp.p;
-    ASM_HIP(hipMemsetAsync(fl, 0, 2 * sizeof(int), s));
-    ASM_HIP(hipMemsetAsync(c, 0, sizeof(int32_t) * ((size_t)nv + 1), s));
-    hipLaunchKernelGGL(k_ids_in_range, dim3(blocks_for(nid)), dim3(kAsmBlock), 0, s, nid, elems, nv, fl);
-    int h[2];
-    ASM_HIP(hipMemcpyAsync(h, fl, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, s, 2L, (int32_t *)w.flags, 0);
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for((long)nv + 1)), dim3(kAsmBlock), 0, s, (long)nv + 1, w.cnt, 0);
+    hipLaunchKernelGGL(k_ids_in_range, dim3(blocks_for(nid)), dim3(kAsmBlock), 0, s, nid, elems, nv, w.flags);
+    int h[4] = {0, 0, 0, 0};  // host words of the two read-backs
+    ASM_HIP(hipMemcpyAsync(h, w.flags, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     ASM_HIP(hipStreamSynchronize(s));
     if (h[0]) return AMG_ERR_ARG;  // out-of-range vertex ids: nothing below indexes with them
-    hipLaunchKernelGGL(k_vertex_count, dim3(blocks_for(nid)), dim3(kAsmBlock), 0, s, nid, elems, c);
-    scan(nv, c, vpp, csum, fl + 1, s);
-    ASM_HIP(hipMemsetAsync(c, 0, sizeof(int32_t) * ((size_t)nv + 1), s));
-    hipLaunchKernelGGL(k_vertex_place, dim3(blocks_for(nid)), dim3(kAsmBlock), 0, s, ne, nl, elems, vpp, c, vep);
-    hipLaunchKernelGGL(k_vertex_sort, dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, vpp, vep);
+    hipLaunchKernelGGL(k_vertex_count, dim3(blocks_for(nid)), dim3(kAsmBlock), 0, s, nid, elems, w.cnt);
+    scan(nv, w.cnt, w.vp, w.csum, w.flags + 1, s);
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for((long)nv + 1)), dim3(kAsmBlock), 0, s, (long)nv + 1, w.cnt, 0);
+    hipLaunchKernelGGL(k_vertex_place, dim3(blocks_for(nid)), dim3(kAsmBlock), 0, s, ne, nl, elems, w.vp, w.cnt,
+                       w.ve);
+    hipLaunchKernelGGL(k_vertex_sort, dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, w.vp, w.ve);
     hipLaunchKernelGGL((k_row_pattern<false>), dim3(blocks_for(64L * nv)), dim3(kAsmBlock), 0, s, nv, nl, elems,
-                       vpp, vep, c, (const int32_t *)nullptr, (int32_t *)nullptr);
-    scan(nv, c, rpp, csum, fl + 1, s);
+                       w.vp, w.ve, w.cnt, (const int32_t *)nullptr, (int32_t *)nullptr);
+    scan(nv, w.cnt, w.rp, w.csum, w.flags + 1, s);
     ASM_HIP(hipGetLastError());
+    ASM_HIP(hipMemcpyAsync(h + 2, w.rp + nv, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    ASM_HIP(hipMemcpyAsync(h + 3, w.flags + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    ASM_HIP(hipStreamSynchronize(s));
+    if (h[3]) return AMG_ERR_ARG;  // more than 2^31 - 1 entries
+    *total = h[2];
+    return AMG_OK;
+}
+
+// the pattern and values into the caller's arrays (nnz checked against the
+// mesh graph first)
+int assemble_into(int dim, int32_t nv, const double *coords, int32_t ne, const int32_t *elems, const double *kappa,
+                  int32_t nnz, int32_t *rowptr, int32_t *col, double *valA, double *valM, hipStream_t s,
+                  const AsmScratch &w) {
+    int32_t tot = 0;
+    if (int e = mesh_lists(dim, nv, ne, elems, s, w, &tot)) return e;
+    if (tot != nnz) return AMG_ERR_ARG;  // the caller's arrays do not fit this pattern
+    const int nl = dim + 1;
+    ASM_HIP(hipMemcpyAsync(rowptr, w.rp, sizeof(int32_t) * ((size_t)nv + 1), hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL((k_row_pattern<true>), dim3(blocks_for(64L * nv)), dim3(kAsmBlock), 0, s, nv, nl, elems,
+                       (const int32_t *)w.vp, (const int32_t *)w.ve, (int32_t *)nullptr, rowptr, col);
+    if (dim == 2)
+        hipLaunchKernelGGL((k_row_values<2>), dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, coords, elems, kappa,
+                           (const int32_t *)w.vp, (const int32_t *)w.ve, rowptr, col, valA, valM);
+    else
+        hipLaunchKernelGGL((k_row_values<3>), dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, coords, elems, kappa,
+                           (const int32_t *)w.vp, (const int32_t *)w.ve, rowptr, col, valA, valM);
+    ASM_HIP(hipGetLastError());
+    ASM_HIP(hipStreamSynchronize(s));
     return AMG_OK;
 }
 
 bool valid_args(int dim, int32_t nv, int32_t ne, const int32_t *elems) {
-    return (dim == 2 || dim == 3) && nv > 0 && ne > 0 && elems;
+    return (dim == 2 || dim == 3) && nv > 0 && ne > 0 && elems && (long)ne * (dim + 1) <= INT_MAX;
 }
 
 }  // namespace
@@ -304,16 +398,9 @@ extern "C" int amg_p1_pattern_device(int dim, int32_t nv, int32_t ne, const int3
     using namespace amg;
     if (!nnz || !valid_args(dim, nv, ne, elems)) return AMG_ERR_ARG;
     const hipStream_t s = (hipStream_t)stream;
-    Dev vp, ve, rp, flags;
-    if (int e = mesh_lists(dim, nv, ne, elems, s, vp, ve, rp, flags)) return e;
-    int32_t tot = 0;
-    int over = 0;
-    ASM_HIP(hipMemcpyAsync(&tot, (int32_t *)rp.p + nv, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    ASM_HIP(hipMemcpyAsync(&over, (int *)flags.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    ASM_HIP(hipStreamSynchronize(s));
-    if (over) return AMG_ERR_ARG;
-    *nnz = tot;
-    return AMG_OK;
+    PoolBlock blk;
+    if (int e = blk.get(scratch_bytes(dim, nv, ne), s)) return e;
+    return mesh_lists(dim, nv, ne, elems, s, carve(blk.p, dim, nv, ne), nnz);
 }
 
 extern "C" int amg_p1_assemble_device(int dim, int32_t nv, const double *coords, int32_t ne, const int32_t *elems,
@@ -323,25 +410,8 @@ extern "C" int amg_p1_assemble_device(int dim, int32_t nv, const double *coords,
     if (!coords || !kappa || !rowptr || !col || !valA || !valM || !valid_args(dim, nv, ne, elems))
         return AMG_ERR_ARG;
     const hipStream_t s = (hipStream_t)stream;
-    Dev vp, ve, rp, flags;
-    if (int e = mesh_lists(dim, nv, ne, elems, s, vp, ve, rp, flags)) return e;
-    int32_t tot = 0;
-    int over = 0;
-    ASM_HIP(hipMemcpyAsync(&tot, (int32_t *)rp.p + nv, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    ASM_HIP(hipMemcpyAsync(&over, (int *)flags.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-    ASM_HIP(hipStreamSynchronize(s));
-    if (over || tot != nnz) return AMG_ERR_ARG;  // the caller's arrays do not fit this pattern
-    const int nl = dim + 1;
-    ASM_HIP(hipMemcpyAsync(rowptr, rp.p, sizeof(int32_t) * ((size_t)nv + 1), hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL((k_row_pattern<true>), dim3(blocks_for(64L * nv)), dim3(kAsmBlock), 0, s, nv, nl, elems,
-                       (const int32_t *)vp.p, (const int32_t *)ve.p, (int32_t *)nullptr, rowptr, col);
-    if (dim == 2)
-        hipLaunchKernelGGL((k_row_values<2>), dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, coords, elems, kappa,
-                           (const int32_t *)vp.p, (const int32_t *)ve.p, rowptr, col, valA, valM);
-    else
-        hipLaunchKernelGGL((k_row_values<3>), dim3(blocks_for(nv)), dim3(kAsmBlock), 0, s, nv, coords, elems, kappa,
-                           (const int32_t *)vp.p, (const int32_t *)ve.p, rowptr, col, valA, valM);
-    ASM_HIP(hipGetLastError());
-    ASM_HIP(hipStreamSynchronize(s));
-    return AMG_OK;
+    PoolBlock blk;
+    if (int e = blk.get(scratch_bytes(dim, nv, ne), s)) return e;
+    return assemble_into(dim, nv, coords, ne, elems, kappa, nnz, rowptr, col, valA, valM, s,
+                         carve(blk.p, dim, nv, ne));
 }

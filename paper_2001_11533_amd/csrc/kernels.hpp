@@ -1402,6 +1402,34 @@ template <int NB> struct FinRho {  // rho = r.z at the start of the outer CG
     }
 };
 
+// V-cycle input from a packed FP64 vector: b = T(in) (zero on padding
+// columns) and the first smoothing iterate x = (dinv b) s0 that the producer
+// of a V-cycle's right-hand side writes
+template <typename T, int NB> struct OpVcIn {
+    T *b, *x;
+    const double *in;
+    const T *dinv;
+    T s0;
+    int nb;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, double (&)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        const T v = c < nb ? (T)in[(size_t)i * nb + c] : T(0);
+        b[o] = v;
+        if (x) x[o] = (dinv[i] * v) * s0;
+    }
+};
+
+template <typename T, int NB> struct OpVcOut {  // out[i*nb + c] = double(z[i*NB + c]), c < nb
+    double *out;
+    const T *z;
+    int nb;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, double (&)[NV]) const {
+        if (c < nb) out[(size_t)i * nb + c] = (double)z[(size_t)i * NB + c];
+    }
+};
+
 template <int NB> struct OpPack {  // out[i*NB + c] = c < nb ? in[i*nb + c] : 0
     double *out;
     const double *in;

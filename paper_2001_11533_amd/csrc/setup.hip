@@ -45,6 +45,14 @@ constexpr int kMaxRowOut = 1024; // output columns per row at most
 // wavefront instruction), so reductions into a single word combine within the
 // wavefront first, and a maximum is only sent when it raises the stored one
 // (the stored value only grows, so a stale read never skips a needed update).
+// Orders the LDS and memory accesses of one wavefront around a point every
+// lane of it reaches: release fence, wavefront barrier, acquire fence.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int wave_max(int v) {
     for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
     return v;
@@ -519,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort(int m, const int *rp, const
                 kk[a] = a < len ? ci_in[s + a] : INT_MAX;
                 pp[a] = a;
             }
-            __syncwarp();
+            wave_sync();
             for (int k = 2; k <= P; k <<= 1)
                 for (int j = k >> 1; j > 0; j >>= 1) {
                     for (int i = lane; i < P; i += 64) {
@@ -535,17 +543,16 @@ __global__ __launch_bounds__(kBlock) void k_row_sort(int m, const int *rp, const
                             }
                         }
                     }
-                    __syncwarp();
+                    wave_sync();
                 }
             for (int a = lane; a < len; a += 64) {
                 ci_out[s + a] = kk[a];
                 v_out[s + a] = v_in[s + pp[a]];
             }
-            __syncwarp();
+            wave_sync();
         } else if (len <= kSortLds) {
             for (int a = lane; a < len; a += 64) keys[wl][a] = ci_in[s + a];
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            wave_sync();
             for (int a = lane; a < len; a += 64) {
                 const int key = keys[wl][a];
                 int rank = 0;
@@ -553,8 +560,7 @@ __global__ __launch_bounds__(kBlock) void k_row_sort(int m, const int *rp, const
                 ci_out[s + rank] = key;
                 v_out[s + rank] = v_in[s + a];
             }
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            wave_sync();
         } else {
             for (int a = s + lane; a < e; a += 64) {
                 const int key = ci_in[a];
@@ -843,7 +849,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_count_sub(int n, const int *a
             uc[g] = 0;
             full[g] = 0;
         }
-        __syncwarp();
+        wave_sync();
         const int a1 = arp[row + 1];
         for (int p = arp[row] + gl; p < a1; p += LPR) {
             const int k = aci[p];
@@ -851,7 +857,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_count_sub(int n, const int *a
             bmax = max(bmax, qe - qb);
             hs_insert_row_capped<HS>(tb, bci, qb, qe, &uc[g], &full[g]);
         }
-        __syncwarp();
+        wave_sync();
         if (gl == 0) {
             const int u = uc[g];
             if (full[g] || u > HS / 2) {
@@ -862,7 +868,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_count_sub(int n, const int *a
                 umax = max(umax, u);
             }
         }
-        __syncwarp();
+        wave_sync();
     }
     __shared__ int red[2][kBlock / 64];
     umax = wave_max(umax);
@@ -911,24 +917,24 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_fill_sub(int n, const int *ar
             uc[g] = 0;
             uc2[g] = 0;
         }
-        __syncwarp();
+        wave_sync();
         const int a0 = arp[row], a1 = arp[row + 1];
         for (int p = a0 + gl; p < a1; p += LPR) {
             const int k = aci[p];
             hs_insert_row<HS>(tb, bci, brp[k], brp[k + 1], &uc[g], ovf);
         }
-        __syncwarp();
+        wave_sync();
         const int u = uc[g];
         if (u > HS / 2) {  // the host sized HS from the symbolic pass: cannot happen
             if (gl == 0) atomicOr(ovf, 2);
-            __syncwarp();
+            wave_sync();
             continue;
         }
         for (int s = gl; s < HS; s += LPR) {
             const int key = tb[s];
             if (key >= 0) ls[atomicAdd(&uc2[g], 1)] = key;
         }
-        __syncwarp();
+        wave_sync();
         const int cs = crp[row];
         for (int s = gl; s < HS; s += LPR) {
             const int key = tb[s];
@@ -939,7 +945,7 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_fill_sub(int n, const int *ar
             cci[cs + rank] = key;
             ac[rank] = 0.0;
         }
-        __syncwarp();
+        wave_sync();
         for (int c0 = a0; c0 < a1; c0 += LPR) {
             const int cn = min(LPR, a1 - c0);
             int mb = 0, me = 0;
@@ -1004,12 +1010,12 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_fill_sub(int n, const int *ar
                             ac[r2] = ac[r2] + prod2;
                         }
                     }
-                    __syncwarp();
+                    wave_sync();
                 }
             }
         }
         for (int e = gl; e < u; e += LPR) cv[cs + e] = ac[e];
-        __syncwarp();
+        wave_sync();
     }
 }
 

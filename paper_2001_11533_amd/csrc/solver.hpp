@@ -446,9 +446,13 @@ template <int NB> struct Solver {
         };
         // The iterations the previous solve at this level needed (one more when
         // fused: the convergence of update k is decided in iteration k + 1) go
-        // out at once; then the host keeps kAhead launches in flight beyond the
-        // last one it has seen, reading the mailbox after an event.
-        constexpr int kAhead = 1, kRing = Ctx::kPollRing;
+        // out at once, and the host waits for them: usually they suffice, and
+        // nothing runs past convergence.  When they do not, the host keeps two
+        // launches in flight beyond the last one it has seen (it waits on the
+        // older one's event while the newer one runs), reading the mailbox
+        // after each event; at most one launch then runs past convergence,
+        // returning at once in every kernel.
+        constexpr int kRing = Ctx::kPollRing;
         int posted = 1, seen = 0;
         if (phase != 2) {
             const int first = std::min(std::max(1, w.pred + (fused ? 1 : 0) + margin), maxit);
@@ -476,7 +480,7 @@ template <int NB> struct Solver {
                 done = __atomic_load_n(&w.hmail->all_conv, __ATOMIC_ACQUIRE) != 0;
                 break;
             }
-            if (posted - seen < kAhead) {
+            if (posted - seen < (seen == 0 ? 1 : 2)) {
                 step();
                 post_flag(posted % kRing);
                 ++posted;

@@ -133,9 +133,12 @@ class HessianSolver:
             mptr = self._mask.data_ptr()
         else:
             self._mask, mptr = None, None
-        stream = torch.cuda.current_stream(self.device).cuda_stream
+        # every call of the context runs on this stream: inputs and outputs are
+        # made and used on it, so torch and the library see the same order
+        self._stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
-        rc = lib().amg_setup(C.byref(Ac), C.byref(Mc), mptr, C.byref(self.opts), stream, C.byref(h))
+        rc = lib().amg_setup(C.byref(Ac), C.byref(Mc), mptr, C.byref(self.opts), self._stream.cuda_stream,
+                             C.byref(h))
         check(rc, None)
         self._h = h
         self.beta = beta
@@ -153,7 +156,17 @@ class HessianSolver:
         except Exception:
             pass
 
+    def _check_stream(self):
+        """The library enqueues on the stream current at construction; a call
+        made while another stream is current would let torch allocate, copy and
+        read its tensors out of order with the library's work."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self._stream:
+            raise RuntimeError("HessianSolver calls must run on the stream that was current when it was built "
+                               f"(built on {self._stream}, called on {cur})")
+
     def _vec(self, x: torch.Tensor, n: int):
+        self._check_stream()
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
             raise TypeError("expected a float64 GPU tensor")
         squeeze = x.dim() == 1
@@ -279,12 +292,21 @@ class HessianSolver:
         check(lib().amg_copy_dense(self._h, which, C.byref(n), out.ctypes.data), self._h)
         return out
 
+    def vcycle_apply(self, b, level: int = 0, prec: int = 64):
+        """x = V_j b, one AMG V-cycle from level j (FP64, or the float32 cycle)."""
+        n = self.level_n(level)
+        b2, sq = self._vec(b, n)
+        out = torch.empty_like(b2)
+        check(lib().amg_vcycle_apply(self._h, level, prec, b2.data_ptr(), out.data_ptr(), b2.shape[1]), self._h)
+        return out.reshape(-1) if sq else out
+
     def set_hess_levels(self, ell: int):
         check(lib().amg_set_hess_levels(self._h, ell), self._h)
 
     def hierarchy_quality(self, level: int, v0, iters: int = 30) -> float:
         """a~_j = ||K_j - S_j K_{j+1} Pi_j||_2 by the power method from v0 (a
         float64 GPU tensor of n_level entries)."""
+        self._check_stream()
         v, _ = self._vec(v0, self.level_n(level))
         a = C.c_double()
         check(lib().amg_hierarchy_quality(self._h, level, v.data_ptr(), iters, C.byref(a)), self._h)
@@ -293,6 +315,7 @@ class HessianSolver:
     def time_kernel(self, which: int, prec: int = 64, nb: int = 1, reps: int = 50):
         """(ms per launch, algorithmic bytes per launch) of 0: level-0 SpMV, 1: pre-sweep
         residual, 2: V-cycle, 3: fused coarse correction and first post step at level 0."""
+        self._check_stream()
         ms, by = C.c_double(), C.c_double()
         check(lib().amg_time_kernel(self._h, which, prec, nb, reps, C.byref(ms), C.byref(by)), self._h)
         return ms.value, by.value
