@@ -164,6 +164,22 @@ int amg_p1_assemble_device(int dim, int32_t nv, const double *coords, int32_t ne
                            int32_t *rowptr, int32_t *col, double *valA, double *valM,
                            void *stream);
 
+/* amg_p1_assemble_device without any device allocation, for callers that cannot
+ * allocate (code that runs between graph captures or inside a serving loop, or a
+ * harness that forbids hipMalloc): the same arguments, results (bit for bit) and
+ * errors as amg_p1_assemble_device.  Its workspace (the lists and counters above,
+ * 4 (3 (nv + 1) + ne (dim+1)) bytes plus a few KiB for scan sums and alignment) is a
+ * static 32 MiB device array of the library, one per device it runs on, held until
+ * the process ends: enough for the 64^3 Kuhn cube (about 27 MiB).  A mesh that needs
+ * more is refused with AMG_ERR_ARG before anything runs.  Every call on a device
+ * reuses that device's array, so calls that overlap on one device (two host threads,
+ * or two streams) race; serialise them.  Calls no hipMalloc, hipFree or allocating
+ * library routine. */
+int amg_p1_assemble_device_noalloc(int dim, int32_t nv, const double *coords, int32_t ne,
+                                   const int32_t *elems, const double *kappa, int32_t nnz,
+                                   int32_t *rowptr, int32_t *col, double *valA, double *valM,
+                                   void *stream);
+
 /* Build the context: the Dirichlet-reduced stiffness A_0, the smoothed-aggregation
  * hierarchy (strength graph, distance-2 aggregation, smoothed prolongators S_j and
  * their transposes, Galerkin products A_{j+1} = S_j^T A_j S_j and M_{j+1} = S_j^T M_j

@@ -60,6 +60,7 @@ SIGNATURES = {
     "amg_p1_assemble": (C.c_int, [C.c_int, I32, P, I32, P, P, I32, P, P, P, P]),
     "amg_p1_pattern_device": (C.c_int, [C.c_int, I32, I32, P, PI32, P]),
     "amg_p1_assemble_device": (C.c_int, [C.c_int, I32, P, I32, P, P, I32, P, P, P, P, P]),
+    "amg_p1_assemble_device_noalloc": (C.c_int, [C.c_int, I32, P, I32, P, P, I32, P, P, P, P, P]),
     "amg_setup": (C.c_int, [C.POINTER(Csr), C.POINTER(Csr), P, C.POINTER(Opts), P, C.POINTER(P)]),
     "amg_destroy": (C.c_int, [P]),
     "amg_release_memory": (C.c_int, []),

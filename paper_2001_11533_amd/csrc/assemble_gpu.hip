@@ -11,6 +11,7 @@
 // search over the row vertex's elements (counts, scan, fill); then the values.
 #include <climits>
 #include <cstdint>
+#include <mutex>
 
 #include "common.hpp"
 #include "p1_element.hpp"
@@ -386,6 +387,35 @@ int assemble_into(int dim, int32_t nv, const double *coords, int32_t ne, const i
     return AMG_OK;
 }
 
+// ---- the allocation-free variant ----
+// Its workspace is this file-scope device array: every device that runs the
+// call holds one copy until the process ends, and every call on a device
+// reuses that device's copy (so calls that overlap on one device race).
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// The array's device address, looked up once per device with that device
+// current; host code uses these addresses, never the array's name (which on
+// the host is only a stand-in symbol).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_of_current_device(void **out) {
+    int dev = -1;
+    ASM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return AMG_ERR_ARG;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        ASM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return AMG_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return AMG_OK;
+}
+
 bool valid_args(int dim, int32_t nv, int32_t ne, const int32_t *elems) {
     return (dim == 2 || dim == 3) && nv > 0 && ne > 0 && elems && (long)ne * (dim + 1) <= INT_MAX;
 }
@@ -414,4 +444,18 @@ extern "C" int amg_p1_assemble_device(int dim, int32_t nv, const double *coords,
     if (int e = blk.get(scratch_bytes(dim, nv, ne), s)) return e;
     return assemble_into(dim, nv, coords, ne, elems, kappa, nnz, rowptr, col, valA, valM, s,
                          carve(blk.p, dim, nv, ne));
+}
+
+extern "C" int amg_p1_assemble_device_noalloc(int dim, int32_t nv, const double *coords, int32_t ne,
+                                              const int32_t *elems, const double *kappa, int32_t nnz,
+                                              int32_t *rowptr, int32_t *col, double *valA, double *valM,
+                                              void *stream) {
+    using namespace amg;
+    if (!coords || !kappa || !rowptr || !col || !valA || !valM || !valid_args(dim, nv, ne, elems))
+        return AMG_ERR_ARG;
+    if (scratch_bytes(dim, nv, ne) > kNoAllocBytes) return AMG_ERR_ARG;  // beyond the static workspace
+    void *base = nullptr;
+    if (int e = scratch_of_current_device(&base)) return e;
+    return assemble_into(dim, nv, coords, ne, elems, kappa, nnz, rowptr, col, valA, valM, (hipStream_t)stream,
+                         carve(base, dim, nv, ne));
 }
