@@ -104,6 +104,11 @@ typedef struct {
                                iteration of degree 2 preconditioned by the l1 diagonal on the interval
                                [0.3, 1] of the spectrum of D_l1^{-1} A (bounded by 1 on every level),
                                before and after the coarse correction */
+    int32_t true_resid;     /* 1: reduced_solve recomputes b - H_0 u at exit (one more Hessian
+                               action) and reports its norm in amg_info.true_rel_resid; 0 (default) */
+    int32_t autotune;       /* 1: apply the process-wide table of tuned sparse-product geometry
+                               (filled by amg_autotune) to this context's products; 0 (default):
+                               the fixed rule */
 } amg_opts;
 
 typedef struct {
@@ -115,10 +120,21 @@ typedef struct {
     int32_t refine_steps;     /* FP64 refinement steps (inner_precision 32) */
     int32_t levels;           /* AMG levels L */
     int32_t ell;              /* Hessian levels used (after any fallback) */
-    int32_t status_detail;
+    int32_t status_detail;    /* reduced_solve: this column's outer iterations */
     int32_t pad_;
-    double rel_resid;         /* outer ||r||/||b|| (max over columns) */
+    double rel_resid;         /* outer ||r||/||b|| of the recursive residual (this column) */
     double ms_total;          /* wall time of the call */
+    double true_rel_resid;    /* ||b - H_0 u||_2 / ||b||_2 recomputed at exit (reduced_solve with
+                                 opts.true_resid = 1), else -1 */
+    double ms_phase[8];       /* reduced_solve: device time (ms) between phase boundaries on the
+                                 context's stream: [0] right-hand side K^T M_y y_d, [1] Hessian
+                                 actions of the outer CG, [2] preconditioner actions, [3] the
+                                 outer CG's own vector work and read-backs, [4] the true-residual
+                                 check; [5..7] 0.  Other calls: all 0 */
+    double bytes_moved;       /* algorithmic bytes of the sparse and dense products the call
+                                 issued: per sparse product 4 (n+1) + (4 + s) nnz + 2 s n nb
+                                 (s = 8 or 4 value bytes), per dense apply s (n^2 + 2 n nb);
+                                 elementwise vector work is not counted */
 } amg_info;
 
 /* Fill *o with the defaults listed above.  Returns AMG_ERR_ARG if o is null. */
@@ -258,6 +274,22 @@ int amg_copy_csr(amg_ctx *ctx, int level, int which, int32_t *rowptr, int32_t *c
 /* which: 0 = inverse of the coarsest A (n_{L-1}^2), 1 = dense coarsest Hessian H_{l-1},
  *        2 = its inverse.  Row-major FP64. */
 int amg_copy_dense(amg_ctx *ctx, int which, int32_t *n, double *out);
+/* Autotuner of the sparse products (the tile choice of the row-blocked SpMV/SpMM
+ * kernels): for each CSR product of the context -- A_j, S_j, S_j^T, M_j and the fused
+ * coarse-correction pass over T_j = A_j S_j, in FP64 and (inner_precision 32) float32,
+ * at the context's padded batch width -- time every lanes-per-row choice
+ * G = 2^lg (G times the column groups of a row <= 64) over `reps` launches with HIP
+ * events, keep the fastest (the fixed rule's choice unless another is more than 2 %
+ * faster), record it in a process-wide table keyed by device, matrix kind, size, stored
+ * entries, batch width and value type, and apply it to the context.  Entries the table
+ * already holds are applied without timing.  cache_path: NULL, or a JSON file read
+ * first (if present) and rewritten with the whole table.  *n_timed (may be NULL): the
+ * products timed by this call.  Products of the level-0 sliced-ELL copy (one column)
+ * have no such choice.  Results change only at rounding level (the order in which a
+ * row's entries are summed).  Errors: ARG (reps < 1, an unreadable or malformed cache
+ * file, or one that cannot be written), HIP. */
+int amg_autotune(amg_ctx *ctx, int reps, const char *cache_path, int32_t *n_timed);
+
 /* x = V_j b: one application of the AMG V-cycle from level j, the preconditioner of
  * every A_j-solve (Section 5.2 applies K and K^* by AMG-preconditioned CG): the
  * smoothing pass (opts.smoother) before and after the coarse correction S_j V_{j+1}
@@ -293,18 +325,25 @@ const char *amg_last_error(amg_ctx *ctx);
  * level-0 first l1-Jacobi sweep fused with the residual (x = D^{-1} b, r = b - A_0 x,
  * the V-cycle's first kernel), 2: a whole V-cycle from level 0, 3: the level-0
  * coarse correction fused with the first post-smoothing step (one pass over
- * T_0 = A_0 S_0; Chebyshev form; needs a hierarchy that keeps T_0).  The kernels see
- * zero vectors.  For which 0 and 1, on the level-0 sliced-ELL copy, successive
+ * T_0 = A_0 S_0; Chebyshev form; needs a hierarchy that keeps T_0), 4: the level-0
+ * product of the FP64 inner CG preconditioned by float32 V-cycles (q = A_0 z +
+ * beta q_old with the previous iteration's finalize folded in, as in a solve;
+ * prec 64, inner_precision 32, mixed_mode 0), 5 and 6: the cost of a grid-wide
+ * synchronisation: `reps` rounds of an elementwise step over 2^16 floats separated
+ * by grid barriers inside one cooperative launch of one workgroup per CU (5), or
+ * by kernel boundaries (6, `reps` dependent launches); *ms_avg is then per round.
+ * The kernels see zero vectors.  For which 0, 1 and 4, on the level-0 sliced-ELL copy, successive
  * launches rotate which XCD serves which slices, so that no launch finds its
  * share of the matrix in the L2 where the launch before left it (back to back
  * it would; in a solve other work separates the launches).  prec: 64 or 32 (32 needs inner_precision 32); nb as above.
  * *ms_avg receives milliseconds per launch and *bytes the algorithmic bytes one
  * launch moves (row pointers, column indices and values once, every vector it
- * reads or gathers once, every vector it writes once).  Level-0 products with one
+ * reads or gathers once, every vector it writes once; for which 4 the bytes of
+ * the method's product q = A p: 4 (n+1) + (4 + 8) nnz(A_0) + 2 8 n nb).  Level-0 products with one
  * column run on a sliced-ELL copy whose columns are 16-bit offsets from a base
  * per slice of 64 rows (built when every slice spans fewer than 65536 columns);
  * their column indices count 2 bytes, all others 4.
- * Errors: ARG. */
+ * Errors: ARG; NOCONV if a grid barrier wait of entry 5 timed out. */
 int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double *ms_avg,
                     double *bytes);
 

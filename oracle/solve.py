@@ -23,7 +23,8 @@ practical form (K^T M_y K + beta M_u) u = K^T M_y y_d with K = A^{-1} M_yu
     residual 1e-8).
 
 All residuals are Euclidean 2-norms relative to the right-hand side; every CG
-starts from zero.  A mixed-precision twin (float32 V-cycle and CG inside FP64
+starts from zero, except the outer CG after a dropped Hessian level, which
+restarts from its last iterate.  A mixed-precision twin (float32 V-cycle and CG inside FP64
 iterative refinement, FP64 dense coarse solve) is provided beside the FP64
 path.
 """
@@ -39,7 +40,13 @@ from .csr import CSR
 
 
 class Indefinite(RuntimeError):
-    pass
+    """The preconditioner met a direction of non-positive curvature; x is the
+    last iterate (every step taken had p.q > 0) and iters the steps taken."""
+
+    def __init__(self, msg, x=None, iters=0):
+        super().__init__(msg)
+        self.x = x
+        self.iters = iters
 
 
 class NoConvergence(RuntimeError):
@@ -63,24 +70,27 @@ class Counters:
     history: list = field(default_factory=list)
 
 
-def pcg(apply_A, apply_B, b, rtol, maxit, indefinite_check=False):
-    """Preconditioned conjugate gradients (Hestenes-Stiefel), x_0 = 0, stop at
-    ||r||_2 <= rtol ||b||_2 on the recursive residual.  Returns (x, iters)."""
-    x = np.zeros_like(b)
+def pcg(apply_A, apply_B, b, rtol, maxit, indefinite_check=False, x0=None):
+    """Preconditioned conjugate gradients (Hestenes-Stiefel) from x_0 (zero
+    when not given), stop at ||r||_2 <= rtol ||b||_2 on the recursive residual
+    (r_0 = b - A x_0).  Returns (x, iters)."""
+    x = np.zeros_like(b) if x0 is None else x0.copy()
     bn = float(np.linalg.norm(b))
     if bn == 0.0:
+        return np.zeros_like(b), 0
+    r = b.copy() if x0 is None else b - apply_A(x)
+    if float(np.linalg.norm(r)) <= rtol * bn:
         return x, 0
-    r = b.copy()
     z = apply_B(r)
     rho = float(r @ z)
     if indefinite_check and not rho > 0.0:
-        raise Indefinite("r.z <= 0")
+        raise Indefinite("r.z <= 0", x, 0)
     p = z.copy()
     for it in range(1, maxit + 1):
         q = apply_A(p)
         pq = float(p @ q)
         if indefinite_check and not pq > 0.0:
-            raise Indefinite("p.q <= 0")
+            raise Indefinite("p.q <= 0", x, it - 1)
         alpha = rho / pq
         x = x + alpha * p
         r = r - alpha * q
@@ -89,11 +99,41 @@ def pcg(apply_A, apply_B, b, rtol, maxit, indefinite_check=False):
         z = apply_B(r)
         rho_new = float(r @ z)
         if indefinite_check and not rho_new > 0.0:
-            raise Indefinite("r.z <= 0")
+            raise Indefinite("r.z <= 0", x, it)
         beta = rho_new / rho
         rho = rho_new
         p = z + beta * p
     raise NoConvergence(f"CG did not reach {rtol} in {maxit} iterations")
+
+
+def cg_mass_inner(apply_H, mass_solve, b, rtol, maxit):
+    """CG for the practical-form system H x = b carried out in the inner
+    product of the mass matrix M: the paper states its operators on L^2, where
+    H = M G and the coarsest-level solve of Section 5.2 is CG on G with the L^2
+    inner product.  In coordinates that is CG on H preconditioned by M^{-1}
+    (each step's M^{-1} r is the vector of G x - g).  From x_0 = 0, it stops
+    when ||G x - g||_M <= rtol ||g||_M, g = M^{-1} b, i.e. when r.M^{-1}r <=
+    rtol^2 b.M^{-1}b.  Returns (x, iters)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = mass_solve(r)
+    rho = float(r @ z)
+    if rho == 0.0:
+        return x, 0
+    tol2 = rtol * rtol * rho
+    p = z.copy()
+    for it in range(1, maxit + 1):
+        q = apply_H(p)
+        alpha = rho / float(p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        z = mass_solve(r)
+        rho_new = float(r @ z)
+        if rho_new <= tol2:
+            return x, it
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    raise NoConvergence(f"CG in the M inner product did not reach {rtol} in {maxit} iterations")
 
 
 class Oracle:
@@ -291,10 +331,10 @@ class Oracle:
         if j == h.ell - 1:
             if h.chol_H is not None:
                 return sla.cho_solve(h.chol_H, r)
-            # Section 5.2: the coarsest Hessian solve by unpreconditioned CG
-            # to a loose relative residual (1e-4)
-            x, it = pcg(lambda v: self.hessian_apply(j, v, self.o.precond_inner_rtol), lambda v: v.copy(), r,
-                        self.o.coarse_hess_rtol, self.o.outer_maxit)
+            # Section 5.2: the coarsest Hessian level solved by CG (on G, in
+            # the L^2 inner product) to a loose relative residual (1e-4)
+            x, it = cg_mass_inner(lambda v: self.hessian_apply(j, v, self.o.precond_inner_rtol),
+                                  lambda v: self.mass_solve(j, v), r, self.o.coarse_hess_rtol, self.o.outer_maxit)
             self.cnt.coarse_cg_iters += it
             return x
         z = self.C(j, r)
@@ -331,17 +371,25 @@ class Oracle:
     # ---- outer solve (Section 5.3) ----
     def reduced_solve(self, yd: np.ndarray, rtol: float = 1e-8):
         """Solve H_0 u = b for one desired state; on an indefinite
-        preconditioner with auto_levels, drop one Hessian level and restart."""
+        preconditioner with auto_levels, drop one Hessian level and restart CG
+        from the last iterate (the paper drops levels when definiteness is
+        lost, Sections 5.5 and 5.6; every step taken before had p.q > 0, so
+        that iterate is no worse than zero).  Returns (u, outer iterations
+        over all attempts)."""
         b = self.rhs(yd)
+        x0, total = None, 0
         while True:
             try:
                 u, it = pcg(lambda v: self.hessian_apply(0, v), self.precond, b, rtol,
-                            self.o.outer_maxit, indefinite_check=True)
-                self.cnt.outer_iters += it
-                return u, it
-            except Indefinite:
+                            self.o.outer_maxit, indefinite_check=True, x0=x0)
+                total += it
+                self.cnt.outer_iters += total
+                return u, total
+            except Indefinite as e:
                 if not self.o.auto_levels or self.h.ell <= 1:
                     raise
+                total += e.iters
+                x0 = e.x
                 sa.set_hessian_levels(self.h, self.h.ell - 1)
 
     def objective(self, u: np.ndarray, yd: np.ndarray) -> float:

@@ -36,17 +36,20 @@ class Opts(C.Structure):
                 ("nb_max", C.c_int32), ("precond", C.c_int32), ("check_every", C.c_int32),
                 ("use_graphs", C.c_int32), ("coarse_hess_rtol", C.c_double),
                 ("dense_solve_max", C.c_int32), ("mixed_mode", C.c_int32),
-                ("smoother", C.c_int32)]
+                ("smoother", C.c_int32), ("true_resid", C.c_int32), ("autotune", C.c_int32)]
 
 
 class Info(C.Structure):
     _fields_ = [("outer_iters", C.c_int32), ("inner_solves", C.c_int32), ("inner_iters_total", C.c_int32),
                 ("inner_iters_max", C.c_int32), ("mass_iters_total", C.c_int32), ("refine_steps", C.c_int32),
                 ("levels", C.c_int32), ("ell", C.c_int32), ("status_detail", C.c_int32), ("pad_", C.c_int32),
-                ("rel_resid", C.c_double), ("ms_total", C.c_double)]
+                ("rel_resid", C.c_double), ("ms_total", C.c_double), ("true_rel_resid", C.c_double),
+                ("ms_phase", C.c_double * 8), ("bytes_moved", C.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("pad_", "ms_phase")}
+        d["ms_phase"] = dict(zip(("rhs", "hessian", "precond", "outer_vector", "true_resid"), list(self.ms_phase)[:5]))
+        return d
 
 
 P = C.c_void_p
@@ -82,6 +85,7 @@ SIGNATURES = {
     "amg_time_kernel": (C.c_int, [P, C.c_int, C.c_int, C.c_int, C.c_int, PD, PD]),
     "amg_hierarchy_quality": (C.c_int, [P, C.c_int, C.c_void_p, C.c_int, PD]),
     "amg_vcycle_apply": (C.c_int, [P, C.c_int, C.c_int, P, P, C.c_int]),
+    "amg_autotune": (C.c_int, [P, C.c_int, C.c_char_p, PI32]),
 }
 
 _lib = None

@@ -1,7 +1,12 @@
 // C ABI of the library (declared in include/amghess.h).  Every entry point
 // catches internal errors and returns a status code.
 #include <chrono>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
 
 #include "solver.hpp"
 
@@ -123,6 +128,8 @@ void alloc_workspaces(Ctx &c) {
     c.obq = a.alloc<double>(m0);
     c.pk_in = a.alloc<double>(m0);
     c.pk_out = a.alloc<double>(m0);
+    c.tsc = a.alloc<CgScal>(1);
+    (void)take_mail(c, &c.tsc_mail);
     c.rsd = a.alloc<RefScal>(1);
     RefScal rs{};
     c.rmail = take_mail(c, &rs.mail);
@@ -130,11 +137,15 @@ void alloc_workspaces(Ctx &c) {
     AMG_HIP(hipStreamSynchronize(c.stream));  // the host sources of the copies end with this call
 }
 
-void fill_info(Ctx &c, amg_info *info, int n, double ms, int outer_it) {
+void fill_info(Ctx &c, amg_info *info, int n, double ms, int outer_it, const double *phase_ms = nullptr) {
     if (!info) return;
     for (int k = 0; k < n; ++k) {
         amg_info &f = info[k];
         std::memset(&f, 0, sizeof(f));
+        f.true_rel_resid = -1.0;
+        f.bytes_moved = c.st.bytes;
+        if (phase_ms)
+            for (int q = 0; q < 8; ++q) f.ms_phase[q] = phase_ms[q];
         f.outer_iters = outer_it;
         f.inner_solves = (int)c.st.inner_solves;
         f.inner_iters_total = (int)c.st.inner_iters;
@@ -162,6 +173,305 @@ int check_vec_call(Ctx *c, int level, int nb) {
         c->err = "nb out of range (1..nb_max)";
         return AMG_ERR_ARG;
     }
+    return AMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Measurement only (amg_time_kernel): the cost of a grid-wide synchronisation
+// inside one persistent launch against a kernel boundary.  A cooperative
+// launch of one workgroup per CU runs `rounds` elementwise steps on v, each
+// followed by a grid barrier (release fence, arrival counter, generation
+// flag, acquire fence); every wait is bounded (a timed-out wait sets *timeout
+// and gives up), so the launch always ends.
+__global__ __launch_bounds__(kBlock) void coop_rounds_kernel(int rounds, int n, float *v, unsigned *cnt,
+                                                             unsigned *gen, int *timeout) {
+    unsigned mygen = 0;
+    if (threadIdx.x == 0) mygen = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    for (int r = 0; r < rounds; ++r) {
+        for (int i = t; i < n; i += gridDim.x * kBlock) v[i] = v[i] * 0.5f + 1.0f;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();
+            const unsigned g0 = mygen;
+            if (atomicAdd(cnt, 1u) == gridDim.x - 1) {
+                __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __threadfence();
+                atomicAdd(gen, 1u);
+            } else {
+                for (long k = 0; __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0; ++k) {
+                    if (k > (1L << 22)) {
+                        *timeout = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                }
+            }
+            __threadfence();
+            mygen = g0 + 1;
+        }
+        __syncthreads();
+    }
+}
+
+// the same elementwise step as one launch (its boundary is the synchronisation)
+__global__ __launch_bounds__(kBlock) void step_kernel(int n, float *v) {
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    for (int i = t; i < n; i += gridDim.x * kBlock) v[i] = v[i] * 0.5f + 1.0f;
+}
+
+
+// ---------------------------------------------------------------------------
+// Autotuner of the sparse-product geometry: for every CSR product of a
+// context (A_j, S_j, S_j^T, M_j and the fused pass over T_j, per value type and
+// at the context's batch width) the lanes per row G = 2^lg are timed over the
+// candidates lg = 0 .. the largest with G times the column groups <= 64, with HIP
+// events on the context's stream, and the fastest is kept (the default rule's
+// choice unless another is more than 2 % faster).  Choices live in a
+// process-wide table keyed by device, matrix kind, size, stored entries, batch
+// width and value type; amg_autotune fills it (and reads / writes it as JSON),
+// amg_setup with opts.autotune = 1 applies what it holds.  The level-0 products
+// that run on the sliced-ELL copy (one column) have no such parameter.
+struct TuneTable {
+    std::mutex m;
+    std::map<std::string, int> lg;
+    std::map<std::string, std::vector<float>> us;  // timings behind each choice (us per launch)
+    static TuneTable &get() {
+        static TuneTable *t = new TuneTable();
+        return *t;
+    }
+};
+
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return "unknown";
+    std::string a = p.gcnArchName;
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+std::string tune_key(const std::string &dev, const char *kind, const DCsr &A, int nb, int prec) {
+    std::ostringstream k;
+    k << "dev=" << dev << ";kind=" << kind << ";n=" << A.n << ";nnz=" << A.nnz << ";nb=" << nb << ";prec=" << prec;
+    return k.str();
+}
+
+// the table as JSON, one entry per line
+void tune_save(const char *path) {
+    TuneTable &t = TuneTable::get();
+    std::lock_guard<std::mutex> g(t.m);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) fail(AMG_ERR_ARG, std::string("cannot write ") + path);
+    std::fprintf(f, "{\"amghess_tune\": 1, \"entries\": [\n");
+    size_t k = 0;
+    for (const auto &e : t.lg) {
+        std::fprintf(f, "  {\"key\": \"%s\", \"lg\": %d, \"us\": [", e.first.c_str(), e.second);
+        const auto it = t.us.find(e.first);
+        if (it != t.us.end())
+            for (size_t q = 0; q < it->second.size(); ++q) std::fprintf(f, "%s%.3f", q ? ", " : "", it->second[q]);
+        std::fprintf(f, "]}%s\n", ++k < t.lg.size() ? "," : "");
+    }
+    std::fprintf(f, "]}\n");
+    std::fclose(f);
+    if (std::rename(tmp.c_str(), path) != 0) fail(AMG_ERR_ARG, std::string("cannot write ") + path);
+}
+
+// entries of a file written by tune_save (a missing file is an empty table)
+void tune_load(const char *path) {
+    std::ifstream in(path);
+    if (!in) return;
+    std::stringstream ss;
+    ss << in.rdbuf();
+    const std::string txt = ss.str();
+    TuneTable &t = TuneTable::get();
+    std::lock_guard<std::mutex> g(t.m);
+    size_t pos = 0;
+    for (;;) {
+        const size_t k0 = txt.find("\"key\": \"", pos);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = txt.find('"', k0 + 8);
+        const size_t l0 = txt.find("\"lg\": ", k1);
+        if (k1 == std::string::npos || l0 == std::string::npos) fail(AMG_ERR_ARG, std::string("malformed ") + path);
+        const int lg = std::atoi(txt.c_str() + l0 + 6);
+        if (lg < 0 || lg > 6) fail(AMG_ERR_ARG, std::string("malformed ") + path);
+        t.lg[txt.substr(k0 + 8, k1 - (k0 + 8))] = lg;
+        pos = l0;
+    }
+}
+
+// Enumerates the tunable products of a context at batch width NB: f(kind,
+// matrix, level, prec, is_tpro).
+template <int NB, class F> void for_tunables(Ctx &c, F &&f) {
+    const int precs[2] = {64, 32};
+    for (int pi = 0; pi < 2; ++pi) {
+        const int prec = precs[pi];
+        if (prec == 32 && c.o.inner_precision != 32) continue;
+        for (int l = 0; l < c.L; ++l) {
+            Level &Lv = c.lev[l];
+            const bool sell = NB == 1 && Lv.A.sl_off;  // level 0: A and M run on the sliced-ELL copy
+            const bool sell_vals = prec == 64 ? Lv.A.sl_v != nullptr : Lv.A.sl_v32 != nullptr;
+            if (!(sell && sell_vals)) f("A", Lv.A, l, prec, false);
+            if (l + 1 < c.L) {
+                if (Lv.S.rp) f("S", Lv.S, l, prec, false);
+                if (Lv.St.rp) f("St", Lv.St, l, prec, false);
+                if (Lv.T.rp && (prec == 64 ? (Lv.T.v && Lv.Ts) : (Lv.T.v32 && Lv.Ts32))) f("T", Lv.T, l, prec, true);
+            }
+            if (prec == 64 && !(sell && Lv.M.sl_v)) f("M", Lv.M, l, prec, false);
+        }
+    }
+}
+
+// applies the table's entries to the context (no timing)
+template <int NB> int tune_apply(Ctx &c) {
+    const std::string dev = device_arch();
+    TuneTable &t = TuneTable::get();
+    std::lock_guard<std::mutex> g(t.m);
+    int n = 0;
+    for_tunables<NB>(c, [&](const char *kind, DCsr &A, int, int prec, bool) {
+        const auto it = t.lg.find(tune_key(dev, kind, A, NB, prec));
+        if (it == t.lg.end()) return;
+        A.tuned_lg[ilog2(NB)][prec == 32 ? 1 : 0] = (int8_t)it->second;
+        ++n;
+    });
+    return n;
+}
+
+// times the candidates of every product the table does not hold yet
+template <int NB> int tune_time(Ctx &c, int reps) {
+    const std::string dev = device_arch();
+    Solver<NB> S(c);
+    hipEvent_t e0, e1;
+    AMG_HIP(hipEventCreate(&e0));
+    AMG_HIP(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{e0, e1};
+    // defined (zero) inputs in every buffer the timed products touch
+    for (int l = 0; l < c.L; ++l) {
+        const size_t m = (size_t)c.lev[l].n * NB;
+        LevelWs &w = c.ws[l];
+        for (double *p : {w.vc64.x, w.vc64.r, w.vc64.t, w.hf, w.hy}) AMG_HIP(hipMemsetAsync(p, 0, m * 8, c.stream));
+        if (c.o.inner_precision == 32)
+            for (float *p : {w.vc32.x, w.vc32.r, w.vc32.t}) AMG_HIP(hipMemsetAsync(p, 0, m * 4, c.stream));
+    }
+    int timed = 0;
+    for_tunables<NB>(c, [&](const char *kind, DCsr &A, int l, int prec, bool is_t) {
+        const std::string key = tune_key(dev, kind, A, NB, prec);
+        {
+            TuneTable &t = TuneTable::get();
+            std::lock_guard<std::mutex> g(t.m);
+            if (t.lg.count(key)) return;
+        }
+        const int pi = prec == 32 ? 1 : 0, nbi = ilog2(NB);
+        const int lgmax = is_t ? 6 - ilog2(NB) : max_lg<NB>();
+        // the default rule's choice
+        int lg_def;
+        if (is_t) {
+            const double mm = A.n > 0 ? (double)A.nnz / (double)A.n : 1.0;
+            int G = 1;
+            while (G * NB < 64 && G < mm / kSpmvUnroll) G <<= 1;
+            lg_def = ilog2(G);
+        } else {
+            lg_def = make_geo<NB>(A.nnz, A.n).lg;
+        }
+        auto launch = [&](auto tT) {
+            using T = decltype(tT);
+            Level &Lv = c.lev[l];
+            VcWs<T> &v = vcws<T>(c.ws[l]);
+            if (is_t) {
+                S.template tpro<T, 0>(Lv, vcws<T>(c.ws[l + 1]).x, EProCheb<T, NB>{v.t, v.r, dl1inv<T>(Lv), v.x, T(1)},
+                                      nullptr);
+            } else if (kind[0] == 'M') {
+                S.template spmv<double, 0>(A, A.v, GPlain<double, NB>{c.ws[l].hf}, EStore<double, NB>{c.ws[l].hy},
+                                           NoFin{}, nullptr);
+            } else {
+                const T *x = kind[0] == 'S' && kind[1] == 0 ? vcws<T>(c.ws[l + 1]).x : v.x;
+                T *y = kind[0] == 'S' && kind[1] == 't' ? vcws<T>(c.ws[l + 1]).r : v.r;
+                S.template spmv<T, 0>(A, avals<T>(A), GPlain<T, NB>{x}, EStore<T, NB>{y}, NoFin{}, nullptr);
+            }
+        };
+        auto once = [&]() {
+            if (prec == 64) launch(double{});
+            else launch(float{});
+        };
+        std::vector<float> us;
+        for (int lg = 0; lg <= lgmax; ++lg) {
+            A.tuned_lg[nbi][pi] = (int8_t)lg;
+            once();
+            once();
+            AMG_HIP(hipEventRecord(e0, c.stream));
+            for (int r = 0; r < reps; ++r) once();
+            AMG_HIP(hipEventRecord(e1, c.stream));
+            AMG_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            us.push_back(1e3f * ms / reps);
+        }
+        AMG_HIP(hipGetLastError());
+        int best = lg_def;
+        for (int lg = 0; lg <= lgmax; ++lg)
+            if (us[lg] < 0.98f * us[best] && us[lg] < us[lg_def] * 0.98f) best = lg;
+        A.tuned_lg[nbi][pi] = (int8_t)best;
+        TuneTable &t = TuneTable::get();
+        std::lock_guard<std::mutex> g(t.m);
+        t.lg[key] = best;
+        t.us[key] = us;
+        ++timed;
+    });
+    c.st.reset();
+    return timed;
+}
+
+// amg_time_kernel 5 and 6: `reps` rounds of an elementwise step over a float
+// vector of 2^16 entries, synchronised grid-wide between rounds, in one
+// cooperative launch of one workgroup per CU (5) or as `reps` dependent
+// launches of the same grid (6).  *ms_avg: ms per round.
+int time_sync(Ctx &c, int which, int reps, double *ms_avg, double *bytes) {
+    int dev = 0, ncu = 0;
+    AMG_HIP(hipGetDevice(&dev));
+    AMG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int n = 1 << 16;
+    float *v = c.arena.alloc<float>(n);
+    unsigned *w = c.arena.alloc<unsigned>(64);
+    int *to = reinterpret_cast<int *>(w + 32);
+    AMG_HIP(hipMemsetAsync(v, 0, sizeof(float) * n, c.stream));
+    AMG_HIP(hipMemsetAsync(w, 0, 64 * sizeof(unsigned), c.stream));
+    hipEvent_t e0, e1;
+    AMG_HIP(hipEventCreate(&e0));
+    AMG_HIP(hipEventCreate(&e1));
+    unsigned *cnt = w, *gen = w + 16;
+    void *args[] = {(void *)&reps, (void *)&n, (void *)&v, (void *)&cnt, (void *)&gen, (void *)&to};
+    auto run = [&]() {
+        if (which == 5)
+            AMG_HIP(hipLaunchCooperativeKernel((const void *)coop_rounds_kernel, dim3(ncu), dim3(kBlock), args, 0,
+                                               c.stream));
+        else
+            for (int r = 0; r < reps; ++r)
+                hipLaunchKernelGGL(step_kernel, dim3(ncu), dim3(kBlock), 0, c.stream, n, v);
+        AMG_HIP(hipGetLastError());
+    };
+    run();  // warm-up
+    AMG_HIP(hipEventRecord(e0, c.stream));
+    run();
+    AMG_HIP(hipEventRecord(e1, c.stream));
+    AMG_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    AMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int h_to = 0;
+    AMG_HIP(hipMemcpy(&h_to, to, sizeof(int), hipMemcpyDeviceToHost));
+    c.arena.release(v);
+    c.arena.release(w);
+    if (h_to) fail(AMG_ERR_NOCONV, "a grid barrier wait timed out");
+    *ms_avg = ms / reps;
+    if (bytes) *bytes = 2.0 * sizeof(float) * n;
     return AMG_OK;
 }
 
@@ -205,6 +515,8 @@ int amg_opts_default(amg_opts *o) {
     o->dense_solve_max = 2048;
     o->mixed_mode = 0;
     o->smoother = 0;
+    o->true_resid = 0;
+    o->autotune = 0;
     return AMG_OK;
 }
 
@@ -232,7 +544,8 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
         o.nu != 1 || o.inner_maxit < 1 || o.mass_maxit < 1 || o.outer_maxit < 1 || o.hess_levels < 0 ||
         !(o.theta0 >= 0.0) || o.refine_maxit < 1 || o.use_graphs < 0 || o.use_graphs > 2 ||
         !(o.coarse_hess_rtol > 0.0) || o.dense_solve_max < 0 || o.dense_solve_max > 4096 || o.mixed_mode < 0 ||
-        o.mixed_mode > 1 || o.smoother < 0 || o.smoother > 1) {
+        o.mixed_mode > 1 || o.smoother < 0 || o.smoother > 1 || o.true_resid < 0 || o.true_resid > 1 ||
+        o.autotune < 0 || o.autotune > 1) {
         g_setup_err = "invalid options (beta > 0, 1 <= nb_max <= 16, dense_max <= 4096, nu = 1, precision 32/64)";
         return AMG_ERR_ARG;
     }
@@ -242,6 +555,7 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
     c.o = o;
     c.stream = reinterpret_cast<hipStream_t>(stream);
     c.nbp = pad_nb(o.nb_max);
+    Range rg("amg_setup");
     int rc = guarded(nullptr, [&]() {
         c.lev.reserve(o.max_levels + 1);
         for (auto &p : c.part) p = c.arena.alloc<double>((size_t)2 * 16 * kMaxGrid);
@@ -265,6 +579,7 @@ int amg_setup(const amg_csr *A, const amg_csr *M, const uint8_t *dirichlet, cons
         build_hierarchy(c, *A, *M, dirichlet);
         form_dense_hessian(c, o.hess_levels > 0 ? o.hess_levels : c.L);
         alloc_workspaces(c);
+        if (o.autotune) dispatch_nb(c.nbp, [&](auto tag) { return tune_apply<decltype(tag)::value>(c); });
         AMG_HIP(hipStreamSynchronize(c.stream));
         return AMG_OK;
     });
@@ -297,6 +612,7 @@ int amg_destroy(amg_ctx *ctx) {
         if (e) (void)hipEventDestroy(e);
     for (auto e : c.mass_ev)
         if (e) (void)hipEventDestroy(e);
+    c.ph.destroy();
     if (c.cap_stream) (void)hipStreamDestroy(c.cap_stream);
     if (c.side) (void)hipStreamDestroy(c.side);
     if (c.gal) (void)hipStreamDestroy(c.gal);
@@ -400,24 +716,52 @@ int reduced_solve(amg_ctx *ctx, const double *yd, const double *u0, double *u, i
     if (int e = check_vec_call(ctx ? &ctx->c : nullptr, 0, nb)) return e;
     if (!yd || !u || !(rtol > 0.0)) return AMG_ERR_ARG;
     Ctx &c = ctx->c;
+    Range rg("reduced_solve");
     return guarded(&c, [&]() {
         auto t0 = clk::now();
         c.st.reset();
+        if (info) c.ph.start();
+        struct PhOff {  // no phase marks after an error either
+            PhaseTimer &p;
+            ~PhOff() { p.on = false; }
+        } ph_off{c.ph};
         const int n = c.N;
         return dispatch_nb(c.nbp, [&](auto tag) {
             constexpr int NB = decltype(tag)::value;
             Solver<NB> S(c);
             // b = K^T M_y y_d
-            S.template elem<0>(n, OpPack<NB>{c.pk_in, yd, nb}, NoFin{}, nullptr);
-            S.mass_apply(0, 1, c.pk_in, c.obq, nullptr, nullptr);
-            S.adjoint_solve(0, c.obq, c.ob, c.o.inner_rtol);
+            c.ph.mark(kPhRhs, c.stream);
+            {
+                Range rr("rhs");
+                S.template elem<0>(n, OpPack<NB>{c.pk_in, yd, nb}, NoFin{}, nullptr);
+                S.mass_apply(0, 1, c.pk_in, c.obq, nullptr, nullptr);
+                S.adjoint_solve(0, c.obq, c.ob, c.o.inner_rtol);
+            }
+            c.ph.mark(kPhOuter, c.stream);
             if (u0) S.template elem<0>(n, OpPack<NB>{c.ox, u0, nb}, NoFin{}, nullptr);
             int it = 0;
             const int rc = S.outer(c.ob, c.ox, u0 != nullptr, rtol, nb, &it);
+            // the true residual b - H u at exit (one more Hessian action)
+            const bool true_res = info && c.o.true_resid && (rc == AMG_OK || rc == AMG_ERR_NOCONV);
+            if (true_res) {
+                c.ph.mark(kPhTrue, c.stream);
+                Range rt("true_residual");
+                S.hessian_apply(0, c.ox, c.pk_out, c.o.inner_rtol, c.ob);
+                S.template elem<2>(n, OpDot<NB>{c.pk_out, c.pk_out, c.ob, c.ob}, FinStore<NB>{c.dscratch}, nullptr);
+                AMG_HIP(hipMemcpyAsync(c.hscr, c.dscratch, 2 * NB * sizeof(double), hipMemcpyDeviceToHost,
+                                       c.stream));
+            }
+            c.ph.mark(kPhEnd, c.stream);
             S.template elem<0>(n, OpUnpack<NB>{u, c.ox, nb}, NoFin{}, nullptr);
             AMG_HIP(hipStreamSynchronize(c.stream));
-            fill_info(c, info, nb, ms_since(t0), it);
+            double pms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (info) c.ph.sum(pms);
+            fill_info(c, info, nb, ms_since(t0), it, pms);
             if (info) {
+                if (true_res)
+                    for (int k = 0; k < nb; ++k)
+                        info[k].true_rel_resid =
+                            c.hscr[NB + k] > 0 ? std::sqrt(c.hscr[k] / c.hscr[NB + k]) : 0.0;
                 S.read_sc(c.outer.sc);
                 for (int k = 0; k < nb; ++k) {
                     const ColScal &cs = c.hsc->s[k];
@@ -637,6 +981,24 @@ int amg_hierarchy_quality(amg_ctx *ctx, int level, const double *v0, int iters, 
     });
 }
 
+int amg_autotune(amg_ctx *ctx, int reps, const char *cache_path, int32_t *n_timed) {
+    if (!ctx || reps < 1) return AMG_ERR_ARG;
+    Ctx &c = ctx->c;
+    return guarded(&c, [&]() {
+        if (cache_path) tune_load(cache_path);
+        int timed = 0;
+        dispatch_nb(c.nbp, [&](auto tag) {
+            constexpr int NB = decltype(tag)::value;
+            timed = tune_time<NB>(c, reps);
+            tune_apply<NB>(c);
+            return AMG_OK;
+        });
+        if (cache_path) tune_save(cache_path);
+        if (n_timed) *n_timed = timed;
+        return AMG_OK;
+    });
+}
+
 int amg_vcycle_apply(amg_ctx *ctx, int level, int prec, const double *b, double *x, int nb) {
     if (int e = check_vec_call(ctx ? &ctx->c : nullptr, level, nb)) return e;
     if (!b || !x || (prec != 32 && prec != 64)) return AMG_ERR_ARG;
@@ -672,13 +1034,18 @@ int amg_vcycle_apply(amg_ctx *ctx, int level, int prec, const double *b, double 
 
 int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double *ms_avg, double *bytes) {
     if (int e = check_vec_call(ctx ? &ctx->c : nullptr, 0, nb)) return e;
-    if (which < 0 || which > 3 || (prec != 32 && prec != 64) || reps < 1 || !ms_avg) return AMG_ERR_ARG;
+    if (which < 0 || which > 6 || (prec != 32 && prec != 64) || reps < 1 || !ms_avg) return AMG_ERR_ARG;
     Ctx &c = ctx->c;
     if (prec == 32 && c.o.inner_precision != 32) {
         c.err = "float32 kernels need inner_precision = 32";
         return AMG_ERR_ARG;
     }
-    if (c.L < 2 && which > 0) return AMG_ERR_ARG;
+    if (c.L < 2 && (which == 1 || which == 2 || which == 3)) return AMG_ERR_ARG;
+    if (which == 4 && (prec != 64 || c.o.inner_precision != 32 || c.o.mixed_mode != 0)) {
+        c.err = "the CG product of the float32-preconditioned FP64 CG needs prec 64, inner_precision 32, mixed_mode 0";
+        return AMG_ERR_ARG;
+    }
+    if (which >= 5) return guarded(&c, [&]() { return time_sync(c, which, reps, ms_avg, bytes); });
     if (which == 3) {
         const Level &L0 = c.lev[0];
         const bool has = L0.T.rp && (prec == 64 ? (L0.T.v && L0.Ts) : (L0.T.v32 && L0.Ts32));
@@ -708,7 +1075,7 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
             // the level-0 matrix in the L2 of the XCD the launch before left it
             // in (back to back it would, unlike the launches in a solve, which
             // other work separates)
-            const bool rotate = which < 2;
+            const bool rotate = which < 2 || which == 4;
             auto run = [&](auto tT) {
                 using T = decltype(tT);
                 VcWs<T> &v = vcws<T>(c.ws[0]);
@@ -722,12 +1089,51 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                     else if (which == 3)  // coarse correction t += S e fused with the first post step
                         S.template tpro<T, 0>(L0, vcws<T>(c.ws[1]).x,
                                               EProCheb<T, NB>{v.t, v.r, dl1inv<T>(L0), v.x, T(1)}, nullptr);
+                    else if (which == 4) {  // the inner CG's product q = A z + beta q_old with its
+                                            // folded finalize, as in every iteration of a solve
+                        if constexpr (std::is_same_v<T, double>) {
+                            CgWs<double> &w = c.ws[0].inmx;
+                            const FusedFin<NB, false> pro{c.tsc, c.part[1], c.pgrid[1], c.part[2], c.pgrid[2]};
+                            S.template spmv<double, 1>(L0.A, L0.A.v, GZ<double, NB, float>{c.ws[0].d32},
+                                                       ECgQR<double, NB, float>{c.ws[0].d32, w.p0, w.p1, w.q, c.tsc},
+                                                       NoFin{}, &c.tsc->all_conv, 0, pro);
+                        }
+                    }
                     else
                         S.template vcycle<T>(0, v.b, v.x2, false, nullptr);
                 };
                 // defined inputs
                 AMG_HIP(hipMemsetAsync(v.x, 0, sizeof(T) * n * NB, c.stream));
                 AMG_HIP(hipMemsetAsync(v.b, 0, sizeof(T) * n * NB, c.stream));
+                if (which == 4) {
+                    // a CG that never converges: the folded finalize sums partials of
+                    // ones (r.r > 0 = tolerance, r.z > 0) over as many workgroups as in
+                    // a solve, and beta = r.z / rho = 1; z, p and q start at zero
+                    CgWs<double> &w = c.ws[0].inmx;
+                    AMG_HIP(hipMemsetAsync(c.ws[0].d32, 0, sizeof(float) * n * NB, c.stream));
+                    AMG_HIP(hipMemsetAsync(w.p0, 0, sizeof(double) * n * NB, c.stream));
+                    AMG_HIP(hipMemsetAsync(w.q, 0, sizeof(double) * n * NB, c.stream));
+                    const int g = grid_rows((long)n * NB, kBlock, red_grid_max<NB>());
+                    S.pgrid[1] = g;
+                    S.pgrid[2] = S.template red_grid<float>(L0.A);
+                    std::vector<double> ones((size_t)2 * 16 * kMaxGrid, 1.0);
+                    AMG_HIP(hipMemcpyAsync(c.part[1], ones.data(), ones.size() * sizeof(double),
+                                           hipMemcpyHostToDevice, c.stream));
+                    AMG_HIP(hipMemcpyAsync(c.part[2], ones.data(), ones.size() * sizeof(double),
+                                           hipMemcpyHostToDevice, c.stream));
+                    CgScal h{};
+                    for (int col = 0; col < 16; ++col) {
+                        ColScal &cs = h.s[col];
+                        cs.conv = col < NB ? 0 : 1;
+                        cs.tol2 = 0.0;
+                        cs.rho = (double)S.pgrid[2];
+                        cs.rho_next = cs.rho;
+                    }
+                    h.nb = NB;
+                    h.mail = c.tsc_mail;
+                    AMG_HIP(hipMemcpyAsync(c.tsc, &h, sizeof(CgScal), hipMemcpyHostToDevice, c.stream));
+                    AMG_HIP(hipStreamSynchronize(c.stream));
+                }
                 if (which == 3) {
                     AMG_HIP(hipMemsetAsync(v.t, 0, sizeof(T) * n * NB, c.stream));
                     AMG_HIP(hipMemsetAsync(v.r, 0, sizeof(T) * n * NB, c.stream));
@@ -753,6 +1159,8 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
             *ms_avg = ms / reps;
             if (bytes) {
                 if (which == 0) *bytes = spmv_b;
+                else if (which == 4)  // the method's q = A p in FP64 (int32 columns counted)
+                    *bytes = spmv_bytes(n, L0.A.nnz, 8, NB);
                 else if (which == 1)  // gathers x once, reads b, writes r
                     *bytes = 4.0 * (n + 1) + (ib(0) + sz) * L0.A.nnz + 3.0 * sz * n * nbd;
                 else if (which == 3)  // T's pattern with both value arrays, e gathered once,

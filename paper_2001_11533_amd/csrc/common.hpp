@@ -193,6 +193,9 @@ struct DCsr {
     uint16_t *sl_cd = nullptr;
     double *sl_v = nullptr;
     float *sl_v32 = nullptr;
+    // lanes-per-row choice set by the autotuner: log2 G for batch width
+    // 2^k (k = 0..4) and values FP64 (0) / float32 (1); -1 = the default rule
+    int8_t tuned_lg[5][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
 };
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts of 64)

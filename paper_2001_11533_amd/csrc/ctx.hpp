@@ -73,7 +73,51 @@ struct LevelWs {
 
 struct Stats {
     long inner_solves = 0, inner_iters = 0, inner_max = 0, mass_iters = 0, refine = 0, coarse_cg = 0;
+    double bytes = 0.0;  // algorithmic bytes of the sparse and dense products issued
     void reset() { *this = Stats(); }
+};
+
+// Phases of a reduced solve whose device time amg_info reports.
+enum Phase { kPhRhs = 0, kPhHess = 1, kPhPrec = 2, kPhOuter = 3, kPhTrue = 4, kPhEnd = -1 };
+
+// Device time per phase of one call: an event is recorded on the main stream
+// where one phase ends and the next begins (work of the side streams joins the
+// main stream before it is used, so it falls inside the phase that waits for
+// it); the elapsed times are summed per phase once the call's work has run.
+struct PhaseTimer {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> lab;
+    int used = 0;
+    bool on = false;
+    void start() {
+        used = 0;
+        on = true;
+    }
+    void mark(int phase, hipStream_t s) {
+        if (!on) return;
+        if (used == (int)ev.size()) {
+            hipEvent_t e = nullptr;
+            AMG_HIP(hipEventCreate(&e));
+            ev.push_back(e);
+            lab.push_back(kPhEnd);
+        }
+        AMG_HIP(hipEventRecord(ev[used], s));
+        lab[used++] = phase;
+    }
+    // after the stream has run past the last mark
+    void sum(double (&ms)[8]) {
+        for (int k = 0; k + 1 < used; ++k) {
+            float t = 0.f;
+            AMG_HIP(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+            if (lab[k] >= 0 && lab[k] < 8) ms[lab[k]] += t;
+        }
+        on = false;
+    }
+    void destroy() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+        lab.clear();
+    }
 };
 
 struct Ctx {
@@ -119,6 +163,9 @@ struct Ctx {
     int *hiscr = nullptr;        // pinned [64]
     // outer CG workspace (level 0)
     CgWs<double> outer;
+    // CG scalars used only by kernel timing (amg_time_kernel), and their mailbox
+    CgScal *tsc = nullptr;
+    Mail *tsc_mail = nullptr;
     double *ox = nullptr, *ob = nullptr, *obq = nullptr;
     double *pk_in = nullptr, *pk_out = nullptr;  // packing buffers [N x nbp]
     // refinement per-column data (device) and its pinned host mirror
@@ -127,6 +174,7 @@ struct Ctx {
     Mail *mails = nullptr;              // pinned pool of mailboxes
     int nmail = 0;
     Stats st;
+    PhaseTimer ph;
     std::string err;
     bool has_mask = false;
     uint8_t *mask0 = nullptr;

@@ -19,6 +19,8 @@
 // every workgroup write back its XCD's L2 and costs far more than the launch.
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace amg {
@@ -112,6 +114,23 @@ template <int NB> inline Geo make_geo(long nnz, long rows) {
     geo.lg = ilog2(g);
     geo.llpr = ilog2(g * NG);
     return geo;
+}
+
+// the geometry with G = 2^lg lanes per (row, column group)
+template <int NB> inline Geo geo_from_lg(int lg) {
+    Geo geo;
+    geo.lg = lg;
+    geo.llpr = lg + ilog2(NB / spmv_cv<NB>());
+    return geo;
+}
+
+// largest log2 G a product on NB columns can take (LPR <= 64)
+template <int NB> constexpr int max_lg() { return NB >= 4 ? 6 - (NB == 4 ? 0 : NB == 8 ? 1 : 2) : 6; }
+
+// the autotuner's choice for this matrix, batch width and value type, else the default rule
+template <int NB, typename T> inline Geo geo_for(const DCsr &A) {
+    const int t = A.tuned_lg[ilog2(NB)][std::is_same_v<T, float> ? 1 : 0];
+    return t >= 0 ? geo_from_lg<NB>(t) : make_geo<NB>(A.nnz, A.n);
 }
 
 template <int NV, int NB> struct Reducer {
@@ -1109,6 +1128,40 @@ template <int NB> struct FinBeta {  // beta = r.z / rho after the preconditioner
         }
         int all = 1;
         for (int c = 0; c < NB; ++c) all &= sc->s[c].conv;
+        publish(sc, NB);
+    }
+};
+
+// CG in the mass-matrix inner product (the coarsest Hessian level): after the
+// preconditioner z = M^{-1} r, stop on r.z <= tol2 (tol2 = rtol^2 b.M^{-1}b, set
+// by FinOuterInit from b.z), else beta = r.z / rho
+template <int NB> struct FinRzConv {
+    CgScal *sc;
+    __device__ void operator()(double (&tot)[1][NB]) const {
+        for (int c = 0; c < NB; ++c) {
+            ColScal &s = sc->s[c];
+            if (s.conv) {
+                s.beta = 0.0;
+                continue;
+            }
+            const double rz = tot[0][c];
+            s.iters += 1;
+            s.rz = rz;
+            s.rr = rz;
+            if (s.bad || rz <= s.tol2) {
+                s.conv = 1;
+                s.beta = 0.0;
+                continue;
+            }
+            if (!(rz > 0.0)) {
+                s.bad = 1;
+                s.conv = 1;
+                s.beta = 0.0;
+                continue;
+            }
+            s.beta = rz / s.rho;
+            s.rho = rz;
+        }
         publish(sc, NB);
     }
 };

@@ -11,6 +11,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "ctx.hpp"
 
 namespace amg {
@@ -31,6 +33,21 @@ inline ChebConst cheb_const() {
 
 // partials a fused finalize may sum in every workgroup of the next kernel
 constexpr long kFusedPartials = 4096;
+
+// A named range on the host timeline of a profiler (roctx), for the span of a scope.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
+
+// Algorithmic bytes of one sparse product: row pointers, (column, value) per
+// stored entry, the gathered vector once and the written one once, per column
+// (int32 indices; the count of the method's work, whatever layout runs it).
+inline double spmv_bytes(long n, long nnz, int val_bytes, int nb) {
+    return 4.0 * (n + 1) + (4.0 + val_bytes) * (double)nnz + 2.0 * val_bytes * (double)n * nb;
+}
 
 template <int NB> struct Solver {
     Ctx &c;
@@ -56,14 +73,15 @@ template <int NB> struct Solver {
     }
 
     // workgroups of a reducing product with A (the partials it leaves)
-    int red_grid(const DCsr &A) const {
+    template <typename T> int red_grid(const DCsr &A) const {
         if (NB == 1 && A.sl_off) return grid_rows(A.nsl, kBlock / 64, red_grid_max<NB>());
-        return grid_rows(A.n, make_geo<NB>(A.nnz, A.n).rpb(), red_grid_max<NB>());
+        return grid_rows(A.n, geo_for<NB, T>(A).rpb(), red_grid_max<NB>());
     }
 
     template <typename T, int NV, class GX, class EP, class FIN, class PRO = NoPro>
     void spmv(const DCsr &A, const T *vals, GX gx, EP ep, FIN fin, const int *stop, int pbuf = 0,
               PRO pro = PRO{}) {
+        c.st.bytes += spmv_bytes(A.n, A.nnz, sizeof(T), NB);
         if constexpr (NB == 1) {
             const T *sv = nullptr;
             if constexpr (std::is_same_v<T, float>) sv = vals == A.v32 ? A.sl_v32 : nullptr;
@@ -78,7 +96,7 @@ template <int NB> struct Solver {
                 return;
             }
         }
-        const Geo geo = make_geo<NB>(A.nnz, A.n);
+        const Geo geo = geo_for<NB, T>(A);
         const int g = grid_rows(A.n, geo.rpb(), NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
         Reducer<(NV > 0 ? NV : 1), NB> red{part[pbuf]};
         if (NV > 0) pgrid[pbuf] = g;
@@ -95,9 +113,14 @@ template <int NB> struct Solver {
     template <typename T, int NV, class EP>
     void tpro(const Level &Lv, const T *e, EP ep, const int *stop, int pbuf = 0) {
         const DCsr &Tm = Lv.T;
+        // the method's work here: the prolongation S e and the product A (x + S e)
+        c.st.bytes += spmv_bytes(Lv.S.n, Lv.S.nnz, sizeof(T), NB) + spmv_bytes(Lv.A.n, Lv.A.nnz, sizeof(T), NB);
         const double m = Tm.n > 0 ? (double)Tm.nnz / (double)Tm.n : 1.0;
         int G = 1;
-        while (G * NB < 64 && G < m / kSpmvUnroll) G <<= 1;
+        const int tl = Tm.tuned_lg[ilog2(NB)][std::is_same_v<T, float> ? 1 : 0];
+        if (tl >= 0) G = 1 << tl;  // the autotuner's choice
+        else
+            while (G * NB < 64 && G < m / kSpmvUnroll) G <<= 1;
         const int llpr = ilog2(G * NB);
         const int g = grid_rows(Tm.n, kBlock >> llpr, NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
         Reducer<(NV > 0 ? NV : 1), NB> red{part[pbuf]};
@@ -143,6 +166,7 @@ template <int NB> struct Solver {
 
     template <typename T> void dense_apply(const DenseOp &d, const T *b, T *x, const int *stop) {
         const int g = ceil_div((long)d.n * 64, kBlock);
+        c.st.bytes += (double)sizeof(T) * ((double)d.n * d.n + 2.0 * d.n * NB);
         if (NB == 1 && reinterpret_cast<uintptr_t>(b) % 16 == 0) {
             const T *m;
             if constexpr (std::is_same_v<T, float>) m = d.m32;
@@ -391,7 +415,7 @@ template <int NB> struct Solver {
             // fold each finalize into the next iteration's first kernel when every
             // workgroup can afford to sum the partials it needs
             long q = (JAC ? 2L : 1L) * grid_rows((long)n * NB, kBlock, red_grid_max<NB>()) * NB;
-            if constexpr (!JAC) q += (long)red_grid(A) * NB;
+            if constexpr (!JAC) q += (long)red_grid<std::conditional_t<MIX, float, T>>(A) * NB;
             w.fused = q <= kFusedPartials ? 1 : 0;
         }
         const int fused = w.fused;
@@ -611,6 +635,7 @@ template <int NB> struct Solver {
     // Hu = K^T M_y K u + beta M_u u, formed as M (D t + beta u) with
     // t = A^{-1} M_y A^{-1} M_yu u; with rminus, Hu = rminus - H u.
     void hessian_apply(int j, const double *u, double *Hu, double rtol, const double *rminus) {
+        Range rg(j == 0 ? "hessian_apply" : "hessian_apply_coarse");
         Level &L = c.lev[j];
         LevelWs &w = c.ws[j];
         const uint8_t *mk = (j == 0 && c.has_mask) ? c.mask0 : nullptr;
@@ -691,34 +716,39 @@ template <int NB> struct Solver {
         Cop(l, w.ml_t, z, w.ml_z1);                                     // z = z1 + C_l t
     }
 
-    // Coarsest Hessian level too large to invert densely: unpreconditioned CG
-    // on H_l to coarse_hess_rtol from x = 0 (Section 5.2).
+    // Coarsest Hessian level too large to invert densely: CG on G_l in the
+    // L^2 inner product to coarse_hess_rtol from x = 0 (Section 5.2), i.e. CG on
+    // H_l = M_l G_l preconditioned by M_l^{-1}, stopped when
+    // r.M^{-1}r <= rtol^2 b.M^{-1}b (the relative M-norm of G_l x - g).
     void hess_cg(int l, const double *b, double *x) {
+        Range rg("coarse_hessian_cg");
         const int n = c.lev[l].n;
         CgWs<double> &w = c.ws[l].hcg;
         elem<0>(n, OpAxpby<NB>{w.r, b, nullptr, 1.0, 0.0}, NoFin{}, nullptr);
         elem<0>(n, OpAxpby<NB>{x, b, nullptr, 0.0, 0.0}, NoFin{}, nullptr);
-        elem<0>(n, OpAxpby<NB>{w.p0, b, nullptr, 1.0, 0.0}, NoFin{}, nullptr);
-        elem<2>(n, OpDot<NB>{b, b, w.r, w.r}, FinOuterInit<NB>{w.sc, c.o.coarse_hess_rtol, NB}, nullptr);
-        elem<1>(n, OpDot<NB>{w.r, w.r, nullptr, nullptr}, FinRho<NB>{w.sc}, nullptr);
+        mass_solve(l, w.r, w.z);
+        elem<0>(n, OpAxpby<NB>{w.p0, w.z, nullptr, 1.0, 0.0}, NoFin{}, nullptr);
+        elem<2>(n, OpDot<NB>{b, w.z, w.r, w.z}, FinOuterInit<NB>{w.sc, c.o.coarse_hess_rtol, NB}, nullptr);
+        elem<1>(n, OpDot<NB>{w.r, w.z, nullptr, nullptr}, FinRho<NB>{w.sc}, nullptr);
         read_sc(w.sc);
         for (int it = 0; !c.hsc->all_conv; ++it) {
             if (it >= c.o.outer_maxit) fail(AMG_ERR_NOCONV, "coarsest-level Hessian CG did not converge");
             hessian_apply(l, w.p0, w.q, c.o.precond_inner_rtol, nullptr);
             elem<1>(n, OpDot<NB>{w.p0, w.q, nullptr, nullptr}, NoFin{}, nullptr, 0);
             cg_update<double, false>(n, x, w.r, nullptr, w.p0, w.q, nullptr, w.sc, 0, nullptr);
-            finish<1>(1, FinUpd<NB, false>{w.sc}, nullptr);
+            mass_solve(l, w.r, w.z);
+            elem<1>(n, OpDot<NB>{w.r, w.z, nullptr, nullptr}, FinRzConv<NB>{w.sc}, nullptr);
             read_sc(w.sc);
             for (int col = 0; col < NB; ++col)
                 if (c.hsc->s[col].bad) fail(AMG_ERR_NOCONV, "coarsest-level Hessian CG breakdown");
             if (c.hsc->all_conv) break;
-            elem<1>(n, OpDot<NB>{w.r, w.r, nullptr, nullptr}, FinBeta<NB>{w.sc, 0}, nullptr);
-            elem<0>(n, OpPUpd<NB>{w.p0, w.r, w.sc}, NoFin{}, nullptr);
+            elem<0>(n, OpPUpd<NB>{w.p0, w.z, w.sc}, NoFin{}, nullptr);
         }
         c.st.coarse_cg += 1;
     }
 
     void precond(const double *r, double *z) {
+        Range rg("hessian_precond_apply");
         if (c.o.precond) Bop(0, r, z);
         else elem<0>(c.N, OpAxpby<NB>{z, r, nullptr, 1.0, 0.0}, NoFin{}, nullptr);
     }
@@ -727,15 +757,20 @@ template <int NB> struct Solver {
     int outer(const double *b, double *x, bool have_x0, double rtol, int nlive, int *iters_out) {
         const int n = c.N;
         CgWs<double> &w = c.outer;
+        int total = 0;  // iterations over all attempts
         for (;;) {
             if (have_x0) {
+                c.ph.mark(kPhHess, s);
                 hessian_apply(0, x, w.r, c.o.inner_rtol, b);  // r = b - H x0
+                c.ph.mark(kPhOuter, s);
             } else {
                 elem<0>(n, OpAxpby<NB>{w.r, b, nullptr, 1.0, 0.0}, NoFin{}, nullptr);
                 elem<0>(n, OpAxpby<NB>{x, b, nullptr, 0.0, 0.0}, NoFin{}, nullptr);
             }
             elem<2>(n, OpDot<NB>{b, b, w.r, w.r}, FinOuterInit<NB>{w.sc, rtol, nlive}, nullptr);
+            c.ph.mark(kPhPrec, s);
             precond(w.r, w.z);
+            c.ph.mark(kPhOuter, s);
             elem<1>(n, OpDot<NB>{w.r, w.z, nullptr, nullptr}, FinRho<NB>{w.sc}, nullptr);
             elem<0>(n, OpAxpby<NB>{w.p0, w.z, nullptr, 1.0, 0.0}, NoFin{}, nullptr);
             read_sc(w.sc);
@@ -744,10 +779,13 @@ template <int NB> struct Solver {
             bool done = c.hsc->all_conv;
             while (!done && !indefinite) {
                 if (it >= c.o.outer_maxit) {
-                    *iters_out = it;
+                    *iters_out = total + it;
                     return AMG_ERR_NOCONV;
                 }
+                Range rg("outer_iteration");
+                c.ph.mark(kPhHess, s);
                 hessian_apply(0, w.p0, w.q, c.o.inner_rtol, nullptr);
+                c.ph.mark(kPhOuter, s);
                 elem<1>(n, OpDot<NB>{w.p0, w.q, nullptr, nullptr}, NoFin{}, nullptr, 0);
                 cg_update<double, false>(n, x, w.r, nullptr, w.p0, w.q, nullptr, w.sc, 1, nullptr);
                 finish<1>(1, FinUpd<NB, false>{w.sc}, nullptr);
@@ -758,19 +796,26 @@ template <int NB> struct Solver {
                     break;
                 }
                 if (c.hsc->all_conv) break;
+                c.ph.mark(kPhPrec, s);
                 precond(w.r, w.z);
+                c.ph.mark(kPhOuter, s);
                 elem<1>(n, OpDot<NB>{w.r, w.z, nullptr, nullptr}, FinBeta<NB>{w.sc, 1}, nullptr);
                 elem<0>(n, OpPUpd<NB>{w.p0, w.z, w.sc}, NoFin{}, nullptr);
             }
+            total += it;
             if (!indefinite) {
-                *iters_out = it;
+                *iters_out = total;
                 return AMG_OK;
             }
             if (!(c.o.auto_levels && c.ell > 1)) {
-                *iters_out = it;
+                *iters_out = total;
                 return AMG_ERR_INDEFINITE;
             }
+            // one Hessian level fewer, and CG again from the last iterate: every
+            // step taken had p.q > 0, so it is no worse than zero (a column that
+            // met p.q <= 0 was not updated by that step)
             form_dense_hessian(c, c.ell - 1);
+            have_x0 = true;
         }
     }
 };

@@ -292,6 +292,16 @@ class HessianSolver:
         check(lib().amg_copy_dense(self._h, which, C.byref(n), out.ctypes.data), self._h)
         return out
 
+    def autotune(self, reps: int = 20, cache_path: str | None = None) -> int:
+        """Time the lanes-per-row choices of this context's sparse products (amg_autotune);
+        returns how many products were timed.  The choices go to the process-wide table
+        (and to cache_path as JSON when given); contexts made with autotune=1 apply them."""
+        self._check_stream()
+        n = C.c_int32(0)
+        path = cache_path.encode() if cache_path else None
+        check(lib().amg_autotune(self._h, reps, path, C.byref(n)), self._h)
+        return n.value
+
     def vcycle_apply(self, b, level: int = 0, prec: int = 64):
         """x = V_j b, one AMG V-cycle from level j (FP64, or the float32 cycle)."""
         n = self.level_n(level)
@@ -314,7 +324,9 @@ class HessianSolver:
 
     def time_kernel(self, which: int, prec: int = 64, nb: int = 1, reps: int = 50):
         """(ms per launch, algorithmic bytes per launch) of 0: level-0 SpMV, 1: pre-sweep
-        residual, 2: V-cycle, 3: fused coarse correction and first post step at level 0."""
+        residual, 2: V-cycle, 3: fused coarse correction and first post step at level 0,
+        4: level-0 product of the float32-preconditioned FP64 CG; 5 / 6: ms per round of a
+        grid-wide synchronisation by a barrier in a cooperative launch / by kernel boundaries."""
         self._check_stream()
         ms, by = C.c_double(), C.c_double()
         check(lib().amg_time_kernel(self._h, which, prec, nb, reps, C.byref(ms), C.byref(by)), self._h)

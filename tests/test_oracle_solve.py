@@ -267,10 +267,53 @@ def test_indefinite_fallback_drops_levels():
     assert np.linalg.norm(u - ref) <= 1e-6 * np.linalg.norm(ref)
 
 
+def test_cg_in_mass_inner_product_is_textbook_cg_on_G():
+    # The coarsest-level solve of Section 5.2 is CG on G = M^{-1} H in the L^2
+    # (M) inner product.  Written out plainly on the dense G with <u, v>_M, a
+    # textbook CG run for the same number of steps must give the practical-form
+    # routine's iterate (CG on H preconditioned by M^{-1}), and the routine's
+    # stopping rule is the relative M-norm of G x - g.
+    p, h = build("c2", 10, max_coarse=20, **tight())
+    j = 1
+    lev = h.levels[j]
+    H = dense.hessian_practical(h, j)
+    Mj = lev.M.dense()
+    G = np.linalg.solve(Mj, H)
+    rng = np.random.default_rng(2)
+    b = rng.standard_normal(lev.n)
+    g = np.linalg.solve(Mj, b)
+    ip = lambda u, v: float(u @ (Mj @ v))
+
+    def textbook(steps):
+        x = np.zeros_like(g)
+        r = g.copy()
+        d = r.copy()
+        for _ in range(steps):
+            Gd = G @ d
+            a = ip(r, r) / ip(d, Gd)
+            x = x + a * d
+            r_new = r - a * Gd
+            d = r_new + (ip(r_new, r_new) / ip(r, r)) * d
+            r = r_new
+        return x
+
+    for rtol in (1e-1, 1e-2, 1e-4, 1e-8):
+        x, it = solve.cg_mass_inner(lambda v: H @ v, lambda v: np.linalg.solve(Mj, v), b, rtol, 500)
+        assert it >= 1
+        xt = textbook(it)
+        assert np.linalg.norm(x - xt) <= 1e-9 * np.linalg.norm(xt), rtol
+        e = G @ x - g
+        assert math.sqrt(ip(e, e)) <= rtol * math.sqrt(ip(g, g)) * (1 + 1e-9), rtol
+        if it > 1:   # it is the first step count that meets the rule
+            e = G @ textbook(it - 1) - g
+            assert math.sqrt(ip(e, e)) > rtol * math.sqrt(ip(g, g)) * (1 - 1e-9), rtol
+
+
 def test_coarsest_hessian_by_loose_cg():
-    # Section 5.2 solves the coarsest Hessian level by unpreconditioned CG to
-    # 1e-4 instead of exactly; forcing that path (dense_max below the coarsest
-    # Hessian level) must leave the solution of H_0 u = b unchanged
+    # Section 5.2 solves the coarsest Hessian level by CG (on G in the L^2
+    # inner product) to 1e-4 instead of exactly; forcing that path (dense_max
+    # below the coarsest Hessian level) must leave the solution of H_0 u = b
+    # unchanged
     p, h = build("c2", 16, max_coarse=30, dense_max=30, hess_levels=2, beta=1e-3)
     assert h.levels[h.ell - 1].n > 30 and h.chol_H is None
     o = solve.Oracle(h)
