@@ -327,7 +327,7 @@ const char *amg_last_error(amg_ctx *ctx);
  * coarse correction fused with the first post-smoothing step (one pass over
  * T_0 = A_0 S_0; Chebyshev form; needs a hierarchy that keeps T_0), 4: the level-0
  * product of the FP64 inner CG preconditioned by float32 V-cycles (q = A_0 z +
- * beta q_old with the previous iteration's finalize folded in, as in a solve;
+ * beta q_old, with the previous iteration's finalize folded in where a solve folds it;
  * prec 64, inner_precision 32, mixed_mode 0), 5 and 6: the cost of a grid-wide
  * synchronisation: `reps` rounds of an elementwise step over 2^16 floats separated
  * by grid barriers inside one cooperative launch of one workgroup per CU (5), or

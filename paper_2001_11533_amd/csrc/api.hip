@@ -1076,6 +1076,14 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
             // in (back to back it would, unlike the launches in a solve, which
             // other work separates)
             const bool rotate = which < 2 || which == 4;
+            // entry 4 folds the finalize into the product exactly when a solve does
+            // (when every workgroup can afford to sum the partials it needs)
+            bool fused4 = false;
+            {
+                long q = (long)grid_rows((long)n * NB, kBlock, red_grid_max<NB>()) * NB;
+                q += (long)S.template red_grid<float>(L0.A) * NB;
+                fused4 = q <= kFusedPartials;
+            }
             auto run = [&](auto tT) {
                 using T = decltype(tT);
                 VcWs<T> &v = vcws<T>(c.ws[0]);
@@ -1093,10 +1101,14 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                                             // folded finalize, as in every iteration of a solve
                         if constexpr (std::is_same_v<T, double>) {
                             CgWs<double> &w = c.ws[0].inmx;
-                            const FusedFin<NB, false> pro{c.tsc, c.part[1], c.pgrid[1], c.part[2], c.pgrid[2]};
-                            S.template spmv<double, 1>(L0.A, L0.A.v, GZ<double, NB, float>{c.ws[0].d32},
-                                                       ECgQR<double, NB, float>{c.ws[0].d32, w.p0, w.p1, w.q, c.tsc},
-                                                       NoFin{}, &c.tsc->all_conv, 0, pro);
+                            const GZ<double, NB, float> gz{c.ws[0].d32};
+                            const ECgQR<double, NB, float> ep{c.ws[0].d32, w.p0, w.p1, w.q, c.tsc};
+                            if (fused4) {
+                                const FusedFin<NB, false> pro{c.tsc, c.part[1], c.pgrid[1], c.part[2], c.pgrid[2]};
+                                S.template spmv<double, 1>(L0.A, L0.A.v, gz, ep, NoFin{}, &c.tsc->all_conv, 0, pro);
+                            } else {
+                                S.template spmv<double, 1>(L0.A, L0.A.v, gz, ep, NoFin{}, &c.tsc->all_conv, 0);
+                            }
                         }
                     }
                     else
@@ -1128,6 +1140,7 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                         cs.tol2 = 0.0;
                         cs.rho = (double)S.pgrid[2];
                         cs.rho_next = cs.rho;
+                        cs.beta = 1.0;
                     }
                     h.nb = NB;
                     h.mail = c.tsc_mail;

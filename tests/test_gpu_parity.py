@@ -312,10 +312,39 @@ def test_time_kernel_entries():
         assert ms > 0 and by > 0, which
     ms, by = g.time_kernel(3, prec=64, nb=1, reps=3)
     assert ms > 0 and by > 0
+    # the FP64 CG product (FP64 only), and a grid barrier against a kernel boundary
+    ms, by = g.time_kernel(4, prec=64, nb=1, reps=3)
+    assert ms > 0 and by > 0
     with pytest.raises(AmgError):
         g.time_kernel(4, prec=32, nb=1, reps=3)
+    for which in (5, 6):
+        ms, by = g.time_kernel(which, prec=64, nb=1, reps=20)
+        assert ms > 0, which
+    with pytest.raises(AmgError):
+        g.time_kernel(7, prec=32, nb=1, reps=3)
     u1, _ = g.reduced_solve(yd)
     assert torch.equal(u0, u1)
+
+
+def test_solve_info_fields():
+    # amg_info of a reduced solve: the true residual recomputed at exit agrees
+    # with the recursive one, the phase times add up to about the call, and the
+    # algorithmic bytes grow with the work
+    p, g, o = make("c3", 12, max_coarse=40, inner_precision=32, smoother=1, true_resid=1)
+    yd = cuda(p.yd[:, 0])
+    u, info = g.reduced_solve(yd, rtol=1e-8)
+    f = info[0]
+    assert 0 < f["true_rel_resid"] <= 1e-7 and abs(f["true_rel_resid"] - f["rel_resid"]) <= 1e-8
+    ph = f["ms_phase"]
+    assert all(v >= 0 for v in ph.values()) and ph["hessian"] > 0 and ph["precond"] > 0 and ph["true_resid"] > 0
+    assert sum(ph.values()) <= f["ms_total"] * 1.05 + 0.5
+    assert f["bytes_moved"] > 0
+    _, info2 = g.reduced_solve(yd, rtol=1e-4)
+    assert 0 < info2[0]["bytes_moved"] < f["bytes_moved"]
+    # without the option nothing is recomputed
+    p, g2, _ = make("c3", 12, max_coarse=40)
+    _, info3 = g2.reduced_solve(yd, rtol=1e-8)
+    assert info3[0]["true_rel_resid"] == -1.0 and info3[0]["ms_phase"]["true_resid"] == 0.0
 
 
 def test_wide_slices_fall_back_to_csr():

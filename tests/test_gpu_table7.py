@@ -21,8 +21,9 @@ def run(p, ell):
     from paper_2001_11533_amd import AmgError
     rp, ci, va, vm = amg.assemble_p1(p.mesh.coords, p.mesh.elems, p.kappa)
     kw = dict(precond=0) if ell == 0 else dict(hess_levels=ell, auto_levels=0)
+    # max_coarse 20: a hierarchy deep enough for the table's five Hessian levels
     g = amg.HessianSolver((rp, ci, va), (rp, ci, vm), p.dirichlet, beta=p.beta, smoother=1, inner_precision=32,
-                          outer_maxit=200, **kw)
+                          outer_maxit=200, max_coarse=20, **kw)
     try:
         if ell > g.levels()[0]:
             return None
@@ -42,14 +43,18 @@ def test_ball_coefficient_table():
     table = {}
     for alpha in (1e-4, 1e-3, 1e-2, 1e-1, 1.0):
         p = inputs.ball_problem(n, alpha)
-        table[alpha] = [run(p, ell) for ell in (0, 2, 3)]
+        table[alpha] = [run(p, ell) for ell in (0, 2, 3, 4, 5)]
         print(f"{n}^3 alpha={alpha:g}: none {table[alpha][0]}, multilevel l=2 {table[alpha][1]}, "
-              f"l=3 {table[alpha][2]}", flush=True)
+              f"l=3 {table[alpha][2]}, l=4 {table[alpha][3]}, l=5 {table[alpha][4]}", flush=True)
     for alpha in (1e-2, 1e-1, 1.0):
-        plain, l2, l3 = table[alpha]
+        plain, l2, l3, l4, l5 = table[alpha]
         assert 0 < l2 <= 6 and 0 < l3 <= 6 and 5 * max(l2, l3) <= plain
-    plain, l2, l3 = table[1e-3]
+        # deeper: a few iterations, or the loss of definiteness reported
+        for lk in (l4, l5):
+            assert lk in (INDEFINITE, None) or 0 < lk <= 12
+    plain, l2, l3, l4, l5 = table[1e-3]
     assert 0 < l2 <= 15 and 4 * l2 <= plain
     assert l3 == INDEFINITE or 0 < l3 <= 20
     # high contrast: many levels lose definiteness, which is reported
     assert table[1e-4][2] in (INDEFINITE, NOCONV)
+    assert table[1e-4][4] in (INDEFINITE, NOCONV, None)
