@@ -151,6 +151,26 @@ constexpr int pow2floor(int x) {
 // holds column (t CV + v) mod NB, the column thread t serves as its v-th.
 template <int NV, int NB, int CV>
 __device__ void block_partials_cv(const double (&acc)[CV][NV], Reducer<NV, NB> r) {
+    if constexpr (NB == 1 && CV == 1) {
+        // one column: wavefront shuffles, then the four wavefronts' sums in order
+        __shared__ double wred[NV][kBlock / 64];
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double v = acc[0][q];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+            if ((t & 63) == 0) wred[q][t >> 6] = v;
+        }
+        __syncthreads();
+        if (t < NV) {
+            double v = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) v += wred[t][w];
+            r.partial[(size_t)t * gridDim.x + blockIdx.x] = v;
+        }
+        return;
+    }
     constexpr int W = kBlock * CV;
     __shared__ double red[NV][W];
     const int t = threadIdx.x;
@@ -175,19 +195,26 @@ __device__ void block_partials(const double (&acc)[NV], Reducer<NV, NB> r) {
     block_partials_cv<NV, NB, 1>(a1, r);
 }
 
-// Sums the nblk partials of each (quantity, column) in a fixed order with
-// all threads of the workgroup; every thread sees the totals in tot.
-template <int NV, int NB, int BS = kBlock>
-__device__ void sum_partials(const double *__restrict__ partial, int nblk, double (&tot)[NV][NB]) {
-    __shared__ double red[BS];
-    constexpr int Q = NV * NB;
+// Sums the partials of Q quantities in a fixed order with all BS threads of
+// the workgroup: quantity q's partials are src(q, &ptr, &count).  LPS threads
+// (a power of two) serve a quantity: each keeps four running sums over the
+// partials it strides through (four loads in flight), then the LPS sums are
+// folded by wavefront shuffles and, for LPS > 64, across the quantity's
+// wavefronts through LDS.  The order depends only on the counts, so every
+// workgroup that sums the same partials gets the same totals.  out (LDS,
+// [Q]) holds the totals for every thread on return.
+template <int Q, int BS, class SRC>
+__device__ void sum_quantities(SRC src, double *out) {
     constexpr int LPS = pow2floor(BS / Q);
+    constexpr int W = LPS < 64 ? LPS : 64;
+    __shared__ double wsum[BS / 64];
     const int t = threadIdx.x;
     const int q = t / LPS, sub = t % LPS;
     double s = 0.0;
     if (q < Q) {
-        // four running sums (fixed order for a given nblk) keep four loads in flight
-        const double *pp = partial + (size_t)q * nblk;
+        const double *pp;
+        int nblk;
+        src(q, pp, nblk);
         double s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int b = sub;
         for (; b + 3 * LPS < nblk; b += 4 * LPS) {
@@ -199,13 +226,54 @@ __device__ void sum_partials(const double *__restrict__ partial, int nblk, doubl
         for (; b < nblk; b += LPS) s += pp[b];
         s = (s + s1) + (s2 + s3);
     }
-    red[t] = s;
-    __syncthreads();
-    for (int w = LPS / 2; w >= 1; w >>= 1) {
-        if (q < Q && sub < w) red[t] += red[t + w];
+#pragma unroll
+    for (int off = W / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if constexpr (LPS > 64) {
+        if ((t & 63) == 0) wsum[t >> 6] = s;
         __syncthreads();
+        if (sub == 0 && q < Q) {
+            double v = 0.0;
+#pragma unroll
+            for (int w = 0; w < LPS / 64; ++w) v += wsum[(t >> 6) + w];
+            out[q] = v;
+        }
+    } else {
+        if (sub == 0 && q < Q) out[q] = s;
     }
-    if (q < Q && sub == 0) tot[q / NB][q % NB] = red[t];
+    __syncthreads();
+}
+
+// The partials of NV quantities x NB columns, quantity-major ([NV*NB][nblk]).
+template <int NV, int NB, int BS = kBlock>
+__device__ void sum_partials(const double *__restrict__ partial, int nblk, double (&tot)[NV][NB]) {
+    sum_quantities<NV * NB, BS>(
+        [&](int q, const double *&pp, int &n) {
+            pp = partial + (size_t)q * nblk;
+            n = nblk;
+        },
+        &tot[0][0]);
+}
+
+// Two buffers of one quantity x NB columns each, summed together.
+template <int NB, int BS = kBlock>
+__device__ void sum_partials2(const double *__restrict__ pa, int na, const double *__restrict__ pb, int nb,
+                              double (&ta)[1][NB], double (&tb)[1][NB]) {
+    __shared__ double both[2 * NB];
+    sum_quantities<2 * NB, BS>(
+        [&](int q, const double *&pp, int &n) {
+            if (q < NB) {
+                pp = pa + (size_t)q * na;
+                n = na;
+            } else {
+                pp = pb + (size_t)(q - NB) * nb;
+                n = nb;
+            }
+        },
+        both);
+    if (threadIdx.x < NB) {
+        ta[0][threadIdx.x] = both[threadIdx.x];
+        tb[0][threadIdx.x] = both[NB + threadIdx.x];
+    }
     __syncthreads();
 }
 
@@ -254,8 +322,8 @@ __device__ bool fused_fin(const FusedFin<NB, JAC> &f, const double *&beta) {
     __shared__ double t1[JAC ? 2 : 1][NB], t2[1][NB];
     __shared__ double sb[NB];
     __shared__ int sall;
-    sum_partials<JAC ? 2 : 1, NB>(f.p1, f.n1, t1);
-    if constexpr (!JAC) sum_partials<1, NB>(f.p2, f.n2, t2);
+    if constexpr (JAC) sum_partials<2, NB>(f.p1, f.n1, t1);
+    else sum_partials2<NB>(f.p1, f.n1, f.p2, f.n2, t1, t2);
     if (threadIdx.x == 0) {
         int all = 1;
         for (int c = 0; c < NB; ++c) {
@@ -324,8 +392,7 @@ __global__ __launch_bounds__(kFinBlock) void fin2_kernel(const double *__restric
                                                          const int *__restrict__ stop) {
     if (stop && *stop) return;
     __shared__ double ta[1][NB], tb[1][NB];
-    sum_partials<1, NB, kFinBlock>(pa, na, ta);
-    sum_partials<1, NB, kFinBlock>(pb, nb, tb);
+    sum_partials2<NB, kFinBlock>(pa, na, pb, nb, ta, tb);
     if (threadIdx.x == 0) fin(ta, tb);
 }
 
