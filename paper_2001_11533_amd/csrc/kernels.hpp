@@ -143,50 +143,35 @@ constexpr int pow2floor(int x) {
     return p;
 }
 
-// Block reduction of acc[NV] over threads of equal column (t % NB) in a
-// fixed LDS tree; thread t < NV*NB then writes partial (t / NB, t % NB) of
-// this workgroup.  The totals are formed by fin_kernel, launched next on the
-// same stream (a kernel boundary orders the partials; no device-scope fence
-// is issued by the workgroups).  With CV columns per thread, slot t CV + v
-// holds column (t CV + v) mod NB, the column thread t serves as its v-th.
+// Block reduction of acc over the threads that serve the same columns: thread
+// t serves column group t % NG (NG = NB / CV groups of CV consecutive columns;
+// slot v of acc is column (t % NG) CV + v).  Each wavefront folds its lanes of
+// one group by shuffles (xor offsets NG, 2 NG, .., 32), the wavefronts' sums are
+// added in order through LDS, and thread t < NV NB writes partial (t / NB,
+// t % NB) of this workgroup.  The totals are formed by fin_kernel, launched next
+// on the same stream (a kernel boundary orders the partials; no device-scope
+// fence is issued by the workgroups).
 template <int NV, int NB, int CV>
 __device__ void block_partials_cv(const double (&acc)[CV][NV], Reducer<NV, NB> r) {
-    if constexpr (NB == 1 && CV == 1) {
-        // one column: wavefront shuffles, then the four wavefronts' sums in order
-        __shared__ double wred[NV][kBlock / 64];
-        const int t = threadIdx.x;
-#pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            double v = acc[0][q];
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-            if ((t & 63) == 0) wred[q][t >> 6] = v;
-        }
-        __syncthreads();
-        if (t < NV) {
-            double v = 0.0;
-#pragma unroll
-            for (int w = 0; w < kBlock / 64; ++w) v += wred[t][w];
-            r.partial[(size_t)t * gridDim.x + blockIdx.x] = v;
-        }
-        return;
-    }
-    constexpr int W = kBlock * CV;
-    __shared__ double red[NV][W];
-    const int t = threadIdx.x;
+    constexpr int NG = NB / CV, WV = kBlock / 64;
+    __shared__ double wred[WV][NV][NB];
+    const int t = threadIdx.x, lane = t & 63;
 #pragma unroll
     for (int v = 0; v < CV; ++v)
 #pragma unroll
-        for (int q = 0; q < NV; ++q) red[q][t * CV + v] = acc[v][q];
-    __syncthreads();
-    for (int s = W / 2; s >= NB; s >>= 1) {
-        for (int i = t; i < s; i += kBlock) {
+        for (int q = 0; q < NV; ++q) {
+            double x = acc[v][q];
 #pragma unroll
-            for (int q = 0; q < NV; ++q) red[q][i] += red[q][i + s];
+            for (int off = NG; off < 64; off <<= 1) x += __shfl_xor(x, off);
+            if (lane < NG) wred[t >> 6][q][lane * CV + v] = x;
         }
-        __syncthreads();
+    __syncthreads();
+    if (t < NV * NB) {
+        double x = 0.0;
+#pragma unroll
+        for (int w = 0; w < WV; ++w) x += wred[w][t / NB][t % NB];
+        r.partial[(size_t)t * gridDim.x + blockIdx.x] = x;
     }
-    if (t < NV * NB) r.partial[(size_t)t * gridDim.x + blockIdx.x] = red[t / NB][t % NB];
 }
 
 template <int NV, int NB>
@@ -197,8 +182,8 @@ __device__ void block_partials(const double (&acc)[NV], Reducer<NV, NB> r) {
 
 // Sums the partials of Q quantities in a fixed order with all BS threads of
 // the workgroup: quantity q's partials are src(q, &ptr, &count).  LPS threads
-// (a power of two) serve a quantity: each keeps four running sums over the
-// partials it strides through (four loads in flight), then the LPS sums are
+// (a power of two) serve a quantity: each keeps eight running sums over the
+// partials it strides through (eight loads in flight), then the LPS sums are
 // folded by wavefront shuffles and, for LPS > 64, across the quantity's
 // wavefronts through LDS.  The order depends only on the counts, so every
 // workgroup that sums the same partials gets the same totals.  out (LDS,
@@ -215,16 +200,19 @@ __device__ void sum_quantities(SRC src, double *out) {
         const double *pp;
         int nblk;
         src(q, pp, nblk);
-        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int b = sub;
-        for (; b + 3 * LPS < nblk; b += 4 * LPS) {
-            s += pp[b];
-            s1 += pp[b + LPS];
-            s2 += pp[b + 2 * LPS];
-            s3 += pp[b + 3 * LPS];
+        for (; b + 7 * LPS < nblk; b += 8 * LPS) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = pp[b + k * LPS];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a[k] += v[k];
         }
-        for (; b < nblk; b += LPS) s += pp[b];
-        s = (s + s1) + (s2 + s3);
+#pragma unroll
+        for (int k = 0; k < 7; ++k)  // at most seven left
+            if (b + k * LPS < nblk) a[k] += pp[b + k * LPS];
+        s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
 #pragma unroll
     for (int off = W / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
