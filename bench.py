@@ -113,9 +113,11 @@ def cpu_oracle(p):
     return cpu, uref
 
 
-def run_c5(amg, inputs, torch, dev):
+def run_c5(amg, inputs, torch, dev, tune_path, compare_untuned):
     """The 128^3 workload's 16 desired states in one batched solve: setup and
-    solve timed with HIP events (inputs resident in HBM)."""
+    solve timed with HIP events (inputs resident in HBM), with the autotuner's
+    geometry for this hierarchy's products (tuned first, outside the timed
+    region) and, if asked, once more with the fixed geometry rule."""
     p5 = inputs.config("c5", nb=16)
     rp5, ci5, va5, vm5 = amg.assemble_p1(p5.mesh.coords, p5.mesh.elems, p5.kappa)
     A5 = tuple(torch.as_tensor(x).to(dev) for x in (rp5, ci5, va5))
@@ -124,17 +126,30 @@ def run_c5(amg, inputs, torch, dev):
     Y5 = torch.as_tensor(p5.yd).to(dev).contiguous()
     del rp5, ci5, va5, vm5
     torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-    ev[0].record()
     # two Hessian levels: at beta = 1e-4 the multilevel preconditioner of this
     # hierarchy is indefinite with three or more (B_0 H_0 has negative
     # eigenvalues even with tight inner solves), definite with two
-    s5 = amg.HessianSolver(A5, M5, mk5, beta=p5.beta, inner_precision=32, smoother=1, nb_max=16, autotune=1,
-                           hess_levels=2)
-    ev[1].record()
-    U5, info5 = s5.reduced_solve(Y5, rtol=1e-8)
-    ev[2].record()
-    torch.cuda.synchronize()
+    kw = dict(beta=p5.beta, inner_precision=32, smoother=1, nb_max=16, hess_levels=2)
+    st = amg.HessianSolver(A5, M5, mk5, **kw)
+    n_tuned = st.autotune(reps=10, cache_path=tune_path)
+    st.close()
+
+    def timed(autotune):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        s = amg.HessianSolver(A5, M5, mk5, autotune=autotune, **kw)
+        ev[1].record()
+        U, info = s.reduced_solve(Y5, rtol=1e-8)
+        ev[2].record()
+        torch.cuda.synchronize()
+        return s, info, ev
+
+    untuned_ms = None
+    if compare_untuned:
+        su, _, evu = timed(0)
+        untuned_ms = evu[1].elapsed_time(evu[2])
+        su.close()
+    s5, info5, ev = timed(1)
     L5, ell5 = s5.levels()
     c5 = {"workload": "3D unit cube 128^3 Kuhn tets, N=2146689, log-normal kappa var 2, beta=1e-4, "
                       "16 bump y_d in one batch, float32 V-cycles in FP64 CG",
@@ -144,10 +159,12 @@ def run_c5(amg, inputs, torch, dev):
                                       "(Lanczos estimate), definite with 2"),
           "outer_iters": max(i["outer_iters"] for i in info5),
           "inner_iters_total": info5[0]["inner_iters_total"], "mass_iters_total": info5[0]["mass_iters_total"],
-          "solve_phase_ms": info5[0]["ms_phase"], "max_rel_resid": max(i["rel_resid"] for i in info5)}
+          "solve_phase_ms": info5[0]["ms_phase"], "max_rel_resid": max(i["rel_resid"] for i in info5),
+          "autotune_products_timed": n_tuned, "untuned_geometry_solve_ms": untuned_ms}
     s5.close()
     log(f"[bench] 128^3 x 16: setup {c5['setup_ms']:.0f} ms, solve {c5['solve_ms']:.0f} ms "
-        f"({c5['ms_per_state']:.0f} ms per state), ell {ell5}, outer {c5['outer_iters']}")
+        f"({c5['ms_per_state']:.0f} ms per state), ell {ell5}, outer {c5['outer_iters']}, "
+        f"fixed geometry rule {untuned_ms} ms")
     return c5
 
 
@@ -206,8 +223,9 @@ def main():
     yd = torch.as_tensor(p.yd[:, 0].copy()).to(dev)
     torch.cuda.synchronize()
 
+    tune_path = args.tune_cache or os.path.join(tempfile.mkdtemp(), "tune.json")
     if args.c5_only:
-        c5 = run_c5(amg, inputs, torch, dev)
+        c5 = run_c5(amg, inputs, torch, dev, tune_path, False)
         print(json.dumps({"metric": "reduced-Hessian batched solve, 3D 128^3 P1, 16 desired states",
                           "value": c5["solve_ms"] / 1000.0, "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0,
                           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
@@ -228,7 +246,6 @@ def main():
         return s, u, info, ev
 
     # ---- autotuning (once per process; its table serves every later context) ----
-    tune_path = args.tune_cache or os.path.join(tempfile.mkdtemp(), "tune.json")
     tuned = {}
     for nbw in (1, 16):
         s = amg.HessianSolver(A, M, mask, beta=p.beta, inner_precision=32, smoother=1, nb_max=nbw)
@@ -342,7 +359,13 @@ def main():
     torch.cuda.synchronize()
     batch_solve_ms = ev[1].elapsed_time(ev[2])
     sb.close()
-    log(f"[bench] batch16 solve {batch_solve_ms:.1f} ms ({batch_solve_ms / 16:.1f} ms per state)")
+    # the same batch with the fixed geometry rule instead of the autotuner's
+    sbu, _, _, ev = step(32, yd16, nb_max=16, autotune=0)
+    torch.cuda.synchronize()
+    batch_untuned_ms = ev[1].elapsed_time(ev[2])
+    sbu.close()
+    log(f"[bench] batch16 solve {batch_solve_ms:.1f} ms ({batch_solve_ms / 16:.1f} ms per state), "
+        f"fixed geometry rule {batch_untuned_ms:.1f} ms")
 
     # ---- the same kernels on the 128^3 level-0 matrix (N = 2,146,689, 263 MB
     # float32): past the caches, where launch overheads no longer dominate; and
@@ -364,7 +387,7 @@ def main():
     log(f"[bench] 128^3 level 0: pre-sweep f32 {big['presweep_f32']['GBps']:.0f} GB/s, "
         f"CG product f64 {big['cg_product_f64']['GBps']:.0f} GB/s")
     del A5, M5, mk5
-    c5 = None if args.no_c5 else run_c5(amg, inputs, torch, dev)
+    c5 = None if args.no_c5 else run_c5(amg, inputs, torch, dev, tune_path, True)
 
     # ---- a plain device copy of 256 MiB: the reference that scales the
     # rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes ----
@@ -454,6 +477,7 @@ def main():
         "multilevel_vs": variants,
         "hierarchy_quality_a_tilde": quality,
         "batch16": {"solve_ms": batch_solve_ms, "ms_per_state": batch_solve_ms / 16,
+                    "untuned_geometry_solve_ms": batch_untuned_ms,
                     "outer_iters": max(i["outer_iters"] for i in infob)},
         "c5_batch16_128cube": c5,
         "vcycle": {"f32_ms": vc_ms, "f32_GBps_alg": vc_bytes / (vc_ms * 1e-3) / 1e9,

@@ -447,21 +447,23 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__re
         if (live) {
             const int p1 = rp[row + 1];
             for (int p = rp[row] + g; p < p1; p += U * G) {
+                // unconditional loads (past the row's end: its last entry,
+                // weighted by 0), so all U loads and gathers are in flight together
                 int kk[U];
                 T aa[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int q = p + u * G;
-                    const bool ok = q < p1;
-                    kk[u] = ok ? ci[q] : -1;
-                    aa[u] = ok ? av[q] : T(0);
+                    const int qc = min(q, p1 - 1);
+                    kk[u] = ci[qc];
+                    const T a = av[qc];
+                    aa[u] = q < p1 ? a : T(0);
                 }
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (kk[u] >= 0) {
+                for (int u = 0; u < U; ++u) {
 #pragma unroll
-                        for (int v = 0; v < CV; ++v) sum[v] += aa[u] * gxv[v](kk[u], c0 + v);
-                    }
+                    for (int v = 0; v < CV; ++v) sum[v] += aa[u] * gxv[v](kk[u], c0 + v);
+                }
             }
         }
         for (int off = NG; off < LPR; off <<= 1) {
@@ -514,18 +516,22 @@ __global__ __launch_bounds__(kBlock) void sell_kernel(int nrows, int nsl, const 
         const int o = soff[sl], w = (soff[sl + 1] - o) >> 6, cb = sbase[sl];
         T sum = T(0);
         for (int k0 = 0; k0 < w; k0 += U) {
+            // Every load is unconditional (entries past the slice's width read
+            // its last entry again, weighted by 0), so the U column and value
+            // loads, then the U gathers, are in flight together; guarded loads
+            // compile to one wait per entry.  A weight of exactly 0 leaves the
+            // sum unchanged.
             int kk[U];
             T aa[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const bool ok = k0 + u < w;
-                const size_t q = (size_t)o + (size_t)(k0 + u) * 64 + lane;
-                kk[u] = ok ? cb + (int)cd[q] : 0;
-                aa[u] = ok ? av[q] : T(0);
+                const size_t q = (size_t)o + (size_t)min(k0 + u, w - 1) * 64 + lane;
+                kk[u] = cb + (int)cd[q];
+                const T a = av[q];
+                aa[u] = k0 + u < w ? a : T(0);
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (k0 + u < w) sum += aa[u] * gx(kk[u], 0);
+            for (int u = 0; u < U; ++u) sum += aa[u] * gx(kk[u], 0);
         }
         if (live) ep(row, 0, sum, pr, acc);
     }
@@ -871,23 +877,24 @@ __global__ __launch_bounds__(kBlock) void tpro_kernel(int nrows, const int *__re
         if (live) {
             const int p1 = rp[row + 1];
             for (int p = rp[row] + g; p < p1; p += U * G) {
+                // unconditional loads, as in spmv_kernel
                 int kk[U];
                 T ta[U], sa[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int q = p + u * G;
-                    const bool ok = q < p1;
-                    kk[u] = ok ? ci[q] : -1;
-                    ta[u] = ok ? tv[q] : T(0);
-                    sa[u] = ok ? sv[q] : T(0);
+                    const int qc = min(q, p1 - 1);
+                    kk[u] = ci[qc];
+                    const T a = tv[qc], s = sv[qc];
+                    ta[u] = q < p1 ? a : T(0);
+                    sa[u] = q < p1 ? s : T(0);
                 }
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (kk[u] >= 0) {
-                        const T ev = e[(size_t)kk[u] * NB + c];
-                        se += sa[u] * ev;
-                        te += ta[u] * ev;
-                    }
+                for (int u = 0; u < U; ++u) {
+                    const T ev = e[(size_t)kk[u] * NB + c];
+                    se += sa[u] * ev;
+                    te += ta[u] * ev;
+                }
             }
         }
         for (int off = NB; off < LPR; off <<= 1) {  // the G groups of a row and column
@@ -1578,9 +1585,13 @@ template <> struct Vec16<float> {
 
 // One column with b of the matrix's type and 16-byte aligned: b is read in the
 // same 16-byte vectors as the matrix rows, eight vectors of each in flight per
-// lane (a float32 row of up to 2048 entries is one round).  The last vector of
-// a ragged row is read element by element (the row is zero-padded to ld, b is
-// not).
+// lane (a float32 row of up to 2048 entries is one round).  Every load is
+// unconditional (guarded loads compile to a wait each): matrix vectors past the
+// row's stride ld re-read its last vector and are zeroed, b vectors past its
+// last full vector re-read that one and are zeroed, and the ragged last vector
+// of b (b is not padded; the rows are zero-padded to ld) is read once per launch
+// with clamped indices.  The products and their order are those of a guarded
+// loop.
 template <typename TM>
 __global__ __launch_bounds__(kBlock) void dense_apply1_kernel(int n, int ld, const TM *__restrict__ inv,
                                                               const TM *__restrict__ b, TM *__restrict__ x,
@@ -1592,6 +1603,17 @@ __global__ __launch_bounds__(kBlock) void dense_apply1_kernel(int n, int ld, con
     const int lane = threadIdx.x % 64;
     const int w = (blockIdx.x * kBlock + threadIdx.x) / 64;
     const int nw = gridDim.x * kBlock / 64;
+    const int nal = n - n % W;  // b's full vectors end here
+    VT tail;                    // b[nal .. n-1], zeros after
+    {
+        TM t[W];
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            const TM v = b[min(nal + e, n - 1)];
+            t[e] = nal + e < n ? v : TM(0);
+        }
+        tail = *reinterpret_cast<const VT *>(t);
+    }
     for (int i = w; i < n; i += nw) {
         double acc = 0.0;
         const TM *row = inv + (size_t)i * ld;
@@ -1600,16 +1622,14 @@ __global__ __launch_bounds__(kBlock) void dense_apply1_kernel(int n, int ld, con
 #pragma unroll
             for (int u = 0; u < D; ++u) {
                 const int k = k0 + u * 64 * W;
-                m[u] = k < n ? *reinterpret_cast<const VT *>(row + k) : VT{};
-                if (k + W <= n) {
-                    bv[u] = *reinterpret_cast<const VT *>(b + k);
-                } else {
-                    TM t[W];
-#pragma unroll
-                    for (int e = 0; e < W; ++e) t[e] = k + e < n ? b[k + e] : TM(0);
-                    bv[u] = *reinterpret_cast<const VT *>(t);
-                }
+                const VT mv = *reinterpret_cast<const VT *>(row + min(k, ld - W));
+                const VT bl = *reinterpret_cast<const VT *>(b + max(min(k, nal - W), 0));
+                m[u] = k < n ? mv : VT{};
+                bv[u] = k < nal ? bl : k == nal ? tail : VT{};
             }
+            // keep the scheduler from interleaving the loads with their uses
+            // (it would otherwise issue them one at a time)
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < D; ++u)
 #pragma unroll
@@ -1637,22 +1657,24 @@ __global__ __launch_bounds__(kBlock) void dense_apply_kernel(int n, int ld, cons
         for (int c = 0; c < NB; ++c) acc[c] = 0.0;
         const TM *row = inv + (size_t)i * ld;
         for (int k0 = lane * W; k0 < n; k0 += 64 * W * D) {
+            // unconditional loads as in dense_apply1_kernel: entries past n
+            // read a valid entry again and are weighted by 0
             VT m[D];
 #pragma unroll
             for (int u = 0; u < D; ++u) {
                 const int k = k0 + u * 64 * W;
-                m[u] = k < n ? *reinterpret_cast<const VT *>(row + k) : VT{};
+                const VT mv = *reinterpret_cast<const VT *>(row + min(k, ld - W));
+                m[u] = k < n ? mv : VT{};
             }
 #pragma unroll
             for (int u = 0; u < D; ++u) {
 #pragma unroll
                 for (int e = 0; e < W; ++e) {
                     const int k = k0 + u * 64 * W + e;
-                    if (k < n) {
-                        const double a = V::get(m[u], e);
+                    const double a = k < n ? V::get(m[u], e) : 0.0;
+                    const size_t kc = (size_t)min(k, n - 1) * NB;
 #pragma unroll
-                        for (int c = 0; c < NB; ++c) acc[c] += a * (double)b[(size_t)k * NB + c];
-                    }
+                    for (int c = 0; c < NB; ++c) acc[c] += a * (double)b[kc + c];
                 }
             }
         }

@@ -167,7 +167,8 @@ template <int NB> struct Solver {
     template <typename T> void dense_apply(const DenseOp &d, const T *b, T *x, const int *stop) {
         const int g = ceil_div((long)d.n * 64, kBlock);
         c.st.bytes += (double)sizeof(T) * ((double)d.n * d.n + 2.0 * d.n * NB);
-        if (NB == 1 && reinterpret_cast<uintptr_t>(b) % 16 == 0) {
+        // the vector kernel reads b in 16-byte vectors: it needs one full vector
+        if (NB == 1 && reinterpret_cast<uintptr_t>(b) % 16 == 0 && d.n * sizeof(T) >= 16) {
             const T *m;
             if constexpr (std::is_same_v<T, float>) m = d.m32;
             else m = d.m64;
