@@ -576,6 +576,9 @@ __global__ __launch_bounds__(kBlock) void k_row_sort(int m, const int *rp, const
 // ---- sparse product C = A B, one wavefront per row of A, LDS hash of the
 // output columns; values summed over the stored A[i,k] in ascending k ----
 
+// steps of the numeric passes whose loads are issued together
+constexpr int kPre = 8;
+
 template <int HS> __device__ __forceinline__ void hs_insert(int *tab, int key, int *ucount, int *ovf) {
     unsigned h = ((unsigned)key * 2654435761u) & (HS - 1);
     for (int probe = 0; probe < HS; ++probe) {
@@ -602,17 +605,37 @@ template <int HS> __device__ __forceinline__ int hs_find(const int *tab, int key
 }
 
 // Insert the columns of B[qb:qe) into the hash, loading them 8 at a time
-// before the inserts so that their latencies overlap.
+// before the inserts so that their latencies overlap.  The loads are
+// unconditional (past qe: the row's last entry again, then discarded), since
+// guarded loads compile to one wait each.
 template <int HS>
 __device__ __forceinline__ void hs_insert_row(int *tab, const int *bci, int qb, int qe, int *ucount, int *ovf) {
     for (int q0 = qb; q0 < qe; q0 += 8) {
         int key[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) key[i] = q0 + i < qe ? bci[q0 + i] : -1;
+        for (int i = 0; i < 8; ++i) {
+            const int k = bci[min(q0 + i, qe - 1)];
+            key[i] = q0 + i < qe ? k : -1;
+        }
 #pragma unroll
         for (int i = 0; i < 8; ++i)
             if (key[i] >= 0) hs_insert<HS>(tab, key[i], ucount, ovf);
     }
+}
+
+// Rank of key among the u distinct keys of ls (the number smaller than it).
+// ls holds at least 8 INT_MAX sentinels after its u keys and is 16-byte
+// aligned, so it is read in whole 16-byte vectors, several in flight.
+__device__ __forceinline__ int rank_in(const int *ls, int u, int key) {
+    int rank = 0;
+#pragma unroll 2
+    for (int f = 0; f < u; f += 8) {
+        const int4 x0 = *reinterpret_cast<const int4 *>(ls + f);
+        const int4 x1 = *reinterpret_cast<const int4 *>(ls + f + 4);
+        rank += (x0.x < key) + (x0.y < key) + (x0.z < key) + (x0.w < key) + (x1.x < key) + (x1.y < key) +
+                (x1.z < key) + (x1.w < key);
+    }
+    return rank;
 }
 
 // Symbolic pass, W wavefronts per row of A sharing one LDS hash of HS slots:
@@ -626,7 +649,10 @@ __device__ __forceinline__ void hs_insert_row_capped(int *tab, const int *bci, i
     for (int q0 = qb; q0 < qe; q0 += 8) {
         int key[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) key[i] = q0 + i < qe ? bci[q0 + i] : -1;
+        for (int i = 0; i < 8; ++i) {  // unconditional loads, as in hs_insert_row
+            const int k = bci[min(q0 + i, qe - 1)];
+            key[i] = q0 + i < qe ? k : -1;
+        }
         // over the tier's capacity (checked per batch of 8): stop filling
         if (__hip_atomic_load(ucount, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= HS / 2 - 8) {
             *full = 1;
@@ -715,7 +741,7 @@ __global__ __launch_bounds__(64 * W) void k_spgemm_fill(int n, int G, const int 
     constexpr int NT = 64 * W;
     __shared__ int tab[HS];
     __shared__ int pos[HS];
-    __shared__ int lst[HS / 2];
+    __shared__ __align__(16) int lst[HS / 2 + 8];
     __shared__ double acc[HS / 2];
     __shared__ int sqb[NT], sqe[NT];
     __shared__ double sa[NT];
@@ -745,13 +771,13 @@ __global__ __launch_bounds__(64 * W) void k_spgemm_fill(int n, int G, const int 
             const int key = tab[s];
             if (key >= 0) lst[atomicAdd(&uc2, 1)] = key;
         }
+        if (t < 8) lst[u + t] = INT_MAX;  // sentinels for rank_in
         __syncthreads();
         const int cs = crp[row];
         for (int s = t; s < HS; s += NT) {
             const int key = tab[s];
             if (key < 0) continue;
-            int rank = 0;
-            for (int f = 0; f < u; ++f) rank += lst[f] < key;
+            const int rank = rank_in(lst, u, key);
             pos[s] = rank;
             cci[cs + rank] = key;
             acc[rank] = 0.0;
@@ -766,27 +792,27 @@ __global__ __launch_bounds__(64 * W) void k_spgemm_fill(int n, int G, const int 
                 sqe[t] = brp[k + 1];
             }
             __syncthreads();
-            int nkey = -1;
-            double nval = 0.0;
-            if (grp < cnt) {
-                const int q = sqb[grp] + gl;
-                if (q < sqe[grp]) {
-                    nkey = bci[q];
-                    nval = bv[q];
+            // kPre steps' loads at a time, unconditional (an empty slot reads a
+            // valid entry and discards it; the product has entries)
+            for (int eb = 0; eb < cnt; eb += kPre * G) {
+                int pkey[kPre];
+                double pval[kPre];
+#pragma unroll
+                for (int d = 0; d < kPre; ++d) {
+                    const int e = min(eb + d * G + grp, cnt - 1);
+                    const int qb = sqb[e], qe = eb + d * G + grp < cnt ? sqe[e] : qb;
+                    const int q = max(min(qb + gl, qe - 1), 0);
+                    const int kk = bci[q];
+                    pval[d] = bv[q];
+                    pkey[d] = qb + gl < qe ? kk : -1;
                 }
-            }
-            for (int e0 = 0; e0 < cnt; e0 += G) {
+#pragma unroll
+            for (int d = 0; d < kPre; ++d) {
+                const int e0 = eb + d * G;
+                if (e0 >= cnt) break;
                 const int e = e0 + grp;
-                const int key = nkey;
-                const double val = nval;
-                nkey = -1;
-                if (e + G < cnt) {
-                    const int q = sqb[e + G] + gl;
-                    if (q < sqe[e + G]) {
-                        nkey = bci[q];
-                        nval = bv[q];
-                    }
-                }
+                const int key = pkey[d];
+                const double val = pval[d];
                 int r = -1;
                 double prod = 0.0;
                 if (key >= 0) {
@@ -817,6 +843,7 @@ __global__ __launch_bounds__(64 * W) void k_spgemm_fill(int n, int G, const int 
                     }
                     __syncthreads();
                 }
+            }
             }
         }
         __syncthreads();
@@ -893,19 +920,23 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_count_sub(int n, const int *a
 // ascending k, LPR entries of the A row loaded at a time (one per lane) and
 // handed out by shuffles.  A step gives GS = LPR / BL consecutive k to GS
 // subgroups of BL lanes, one lane per entry of the row of B (a longer row
-// takes further rounds), with the loads of the next step issued first; the
-// subgroups then add their products one after another.  For one k the
-// products go to distinct outputs, so every output entry receives its
-// products strictly in ascending k: the rounded sums of a sequential loop.
+// takes further rounds); the loads of kPre steps are issued together, then
+// those steps run, the subgroups of a step adding their products one after
+// another.  For one k the products go to distinct outputs, so every output
+// entry receives its products strictly in ascending k: the rounded sums of a
+// sequential loop.  (B has at least one entry: the host launches no numeric
+// pass for an empty product, so clamped indices are valid.)
 template <int LPR, int HS, int BL>
 __global__ __launch_bounds__(kBlock) void k_spgemm_fill_sub(int n, const int *arp, const int *aci,
                                                             const double *av, const int *brp, const int *bci,
                                                             const double *bv, const int *crp, int *cci, double *cv,
                                                             int *ovf) {
     constexpr int NG = kBlock / LPR, GS = LPR / BL;
+    // fewer steps in flight for 16-lane groups (short rows of A, more groups per CU)
+    constexpr int KP = LPR >= 32 ? kPre : kPre / 2;
     __shared__ int tab[NG][HS];
     __shared__ int pos[NG][HS];
-    __shared__ int lst[NG][HS / 2];
+    __shared__ __align__(16) int lst[NG][HS / 2 + 8];
     __shared__ double acc[NG][HS / 2];
     __shared__ int uc[NG], uc2[NG];
     const int g = threadIdx.x / LPR, gl = threadIdx.x % LPR, sg = gl / BL, sl = gl % BL;
@@ -934,13 +965,13 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_fill_sub(int n, const int *ar
             const int key = tb[s];
             if (key >= 0) ls[atomicAdd(&uc2[g], 1)] = key;
         }
+        if (gl < 8) ls[u + gl] = INT_MAX;  // sentinels for rank_in
         wave_sync();
         const int cs = crp[row];
         for (int s = gl; s < HS; s += LPR) {
             const int key = tb[s];
             if (key < 0) continue;
-            int rank = 0;
-            for (int f = 0; f < u; ++f) rank += ls[f] < key;
+            const int rank = rank_in(ls, u, key);
             ps[s] = rank;
             cci[cs + rank] = key;
             ac[rank] = 0.0;
@@ -957,34 +988,31 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_fill_sub(int n, const int *ar
                 me = brp[k + 1];
             }
             const int nst = (cn + GS - 1) / GS;
-            // entry e * GS + sg of the chunk for step e (every lane of the group takes part)
-            int qb, qe;
-            double a;
-            auto take = [&](int e) {
-                const int src = e * GS + sg;
-                qb = __shfl(mb, src, LPR);
-                qe = __shfl(me, src, LPR);
-                a = __shfl(ma, src, LPR);
-                if (src >= cn) qe = qb;
-            };
-            take(0);
-            int nkey = -1;
-            double nval = 0.0;
-            if (qb + sl < qe) {
-                nkey = bci[qb + sl];
-                nval = bv[qb + sl];
-            }
-            for (int e = 0; e < nst; ++e) {
-                const int key = nkey, cb = qb, ce = qe;
-                const double val = nval, ca = a;
-                nkey = -1;
-                if (e + 1 < nst) {
-                    take(e + 1);
-                    if (qb + sl < qe) {
-                        nkey = bci[qb + sl];
-                        nval = bv[qb + sl];
-                    }
+            // step e takes entry e * GS + sg of the chunk (every lane of the
+            // group takes part in the shuffles); KP steps' loads at a time,
+            // unconditional (an empty slot reads a valid entry and discards it)
+            for (int e0 = 0; e0 < nst; e0 += KP) {
+                int pkey[KP], pqb[KP], pqe[KP];
+                double pval[KP], pa[KP];
+#pragma unroll
+                for (int d = 0; d < KP; ++d) {
+                    const int src = (e0 + d) * GS + sg;
+                    const int qb = __shfl(mb, src, LPR);
+                    int qe = __shfl(me, src, LPR);
+                    pa[d] = __shfl(ma, src, LPR);
+                    if (src >= cn) qe = qb;
+                    const int q = max(min(qb + sl, qe - 1), 0);
+                    const int kk = bci[q];
+                    pval[d] = bv[q];
+                    pkey[d] = qb + sl < qe ? kk : -1;
+                    pqb[d] = qb;
+                    pqe[d] = qe;
                 }
+#pragma unroll
+            for (int d = 0; d < KP; ++d) {
+                if (e0 + d >= nst) break;
+                const int key = pkey[d], cb = pqb[d], ce = pqe[d];
+                const double val = pval[d], ca = pa[d];
                 int r = -1;
                 double prod = 0.0;
                 if (key >= 0) {
@@ -1013,9 +1041,150 @@ __global__ __launch_bounds__(kBlock) void k_spgemm_fill_sub(int n, const int *ar
                     wave_sync();
                 }
             }
+            }
         }
         for (int e = gl; e < u; e += LPR) cv[cs + e] = ac[e];
         wave_sync();
+    }
+}
+
+// The two passes when B has at most DC columns (the products from level 1
+// down): one wavefront per row of A with a dense LDS accumulator and marker
+// over B's columns instead of a hash, so a step is a plain indexed update.
+// Symbolic: mark the columns reached (idempotent byte stores), count them.
+template <int DC>
+__global__ __launch_bounds__(64) void k_spgemm_count_dense(int n, const int *arp, const int *aci, const int *brp,
+                                                           const int *bci, int *cnt, int *maxes) {
+    __shared__ __align__(16) uint8_t mk[DC];
+    const int lane = threadIdx.x;
+    int umax = 0, bmax = 0;
+    for (int row = blockIdx.x; row < n; row += gridDim.x) {
+        for (int j = lane * 4; j < DC; j += 256) *reinterpret_cast<uint32_t *>(mk + j) = 0u;
+        wave_sync();
+        const int a1 = arp[row + 1];
+        for (int p = arp[row] + lane; p < a1; p += 64) {
+            const int k = aci[p];
+            const int qb = brp[k], qe = brp[k + 1];
+            bmax = max(bmax, qe - qb);
+            for (int q0 = qb; q0 < qe; q0 += 8) {
+                int key[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {  // unconditional loads, as in hs_insert_row
+                    const int kk = bci[min(q0 + i, qe - 1)];
+                    key[i] = q0 + i < qe ? kk : -1;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (key[i] >= 0) mk[key[i]] = 1;
+            }
+        }
+        wave_sync();
+        int c = 0;
+        for (int j = lane * 4; j < DC; j += 256) c += __popc(*reinterpret_cast<const uint32_t *>(mk + j));
+        c = wave_sum(c);
+        if (lane == 0) cnt[row] = c;
+        umax = max(umax, c);
+        wave_sync();
+    }
+    umax = wave_max(umax);
+    bmax = wave_max(bmax);
+    if (lane == 0) {
+        raise_max(&maxes[0], umax);
+        raise_max(&maxes[1], bmax);
+    }
+}
+
+// Numeric: the stored A[i,k] in ascending k, kPre steps' loads at a time; a
+// step adds a[i,k] b[k,j] into acc[j] for the entries of row k of B, one per
+// lane of the row's NW wavefronts (a row of B longer than 64 NW in further
+// rounds of the same step).  The columns of one step are distinct, and the
+// steps are ordered (a single wavefront's LDS accesses take effect in program
+// order; several wavefronts wait at a barrier after each step), so acc[j]
+// receives its products in ascending k from 0.0: the rounded sums of a
+// sequential loop.  The row is written in ascending column order, as the hash
+// passes write it.
+template <int DC, int NW>
+__global__ __launch_bounds__(64 * NW) void k_spgemm_fill_dense(int n, int m, const int *arp, const int *aci,
+                                                               const double *av, const int *brp, const int *bci,
+                                                               const double *bv, const int *crp, int *cci,
+                                                               double *cv) {
+    constexpr int NT = 64 * NW;
+    __shared__ double acc[DC];
+    __shared__ uint8_t mk[DC];
+    __shared__ int sq[2][NT];
+    __shared__ double sa[NT];
+    const int t = threadIdx.x, lane = t & 63;
+    auto sync = [&]() {
+        if constexpr (NW == 1) wave_sync();
+        else __syncthreads();
+    };
+    for (int row = blockIdx.x; row < n; row += gridDim.x) {
+        for (int j = t; j < m; j += NT) {
+            acc[j] = 0.0;
+            mk[j] = 0;
+        }
+        const int a0 = arp[row], a1 = arp[row + 1];
+        for (int c0 = a0; c0 < a1; c0 += NT) {
+            const int cn = min(NT, a1 - c0);
+            sync();  // zeroed sums / the previous chunk's staging no longer read
+            {
+                const int pc = c0 + min(t, cn - 1);  // threads past the chunk repeat its last entry (unused)
+                const int k = aci[pc];
+                sa[t] = av[pc];
+                sq[0][t] = brp[k];
+                sq[1][t] = brp[k + 1];
+            }
+            sync();
+            for (int e0 = 0; e0 < cn; e0 += kPre) {
+                int pkey[kPre];
+                double pval[kPre];
+#pragma unroll
+                for (int d = 0; d < kPre; ++d) {
+                    const int e = min(e0 + d, cn - 1);
+                    const int qb = sq[0][e], qe = e0 + d < cn ? sq[1][e] : qb;
+                    const int q = max(min(qb + t, qe - 1), 0);
+                    const int kk = bci[q];
+                    pval[d] = bv[q];
+                    pkey[d] = qb + t < qe ? kk : -1;
+                }
+#pragma unroll
+                for (int d = 0; d < kPre; ++d) {
+                    const int e = e0 + d;
+                    if (e >= cn) break;
+                    const double a = sa[e];
+                    const int key = pkey[d];
+                    if (key >= 0) {
+                        const double prod = a * pval[d];
+                        acc[key] = acc[key] + prod;
+                        mk[key] = 1;
+                    }
+                    for (int q = sq[0][e] + NT + t; q < sq[1][e]; q += NT) {  // rows of B longer than NT
+                        const int j = bci[q];
+                        const double prod = a * bv[q];
+                        acc[j] = acc[j] + prod;
+                        mk[j] = 1;
+                    }
+                    sync();
+                }
+            }
+        }
+        sync();
+        if (t < 64) {  // the first wavefront writes the row
+            const int cs = crp[row];
+            int base = 0;
+            for (int j0 = 0; j0 < m; j0 += 64) {
+                const int j = j0 + lane;
+                const bool on = j < m && mk[j];
+                const unsigned long long bal = __ballot(on);
+                if (on) {
+                    const int p = base + __popcll(bal & ((1ull << lane) - 1));
+                    cci[cs + p] = j;
+                    cv[cs + p] = acc[j];
+                }
+                base += __popcll(bal);
+            }
+        }
+        sync();
     }
 }
 
@@ -1106,6 +1275,9 @@ __global__ __launch_bounds__(kBlock) void k_densify(int n, const int *rp, const 
 // then update the trailing lower tiles.  Only the lower triangle is read later.
 // Every dense kernel below works on a batch of matrices of one order n stored
 // back to back (matrix blockIdx.z at D + blockIdx.z * n * n).
+// The dense factorisations and inverses below are compared with the oracle
+// within a tolerance, not bit for bit: fused multiply-add is allowed there.
+#pragma clang fp contract(fast)
 constexpr int kTB = 32;
 
 __device__ __forceinline__ double *bat(double *D, int n) { return D + (size_t)blockIdx.z * n * n; }
@@ -1116,10 +1288,15 @@ __device__ __forceinline__ const double *bat(const double *D, int n) { return D 
 // block of the product tile.
 typedef double Tile[kTB][kTB + 1];
 
+// (loads unconditional at clamped indices, then zeroed outside the matrix, so
+// that all of a thread's loads are in flight together; guarded loads compile
+// to one wait each)
 __device__ __forceinline__ void tile_load(Tile &T, const double *D, int n, int r0, int c0) {
+#pragma unroll
     for (int e = threadIdx.x; e < kTB * kTB; e += kBlock) {
         const int a = e / kTB, b = e % kTB;
-        T[a][b] = (r0 + a < n && c0 + b < n) ? D[(size_t)(r0 + a) * n + c0 + b] : 0.0;
+        const double v = D[(size_t)min(r0 + a, n - 1) * n + min(c0 + b, n - 1)];
+        T[a][b] = (r0 + a < n && c0 + b < n) ? v : 0.0;
     }
 }
 
@@ -1166,9 +1343,11 @@ __global__ __launch_bounds__(64) void k_potrf_panel(int n, double *Db, double *L
     double *D = bat(Db, n);
     const int tb = min(kTB, n - k0);
     const int t = threadIdx.x;
-    for (int e = t; e < kTB * kTB; e += 64) {
+#pragma unroll
+    for (int e = t; e < kTB * kTB; e += 64) {  // unconditional loads, as in tile_load
         const int i = e / kTB, j = e % kTB;
-        T[i][j] = (i < tb && j < tb) ? D[(size_t)(k0 + i) * n + k0 + j] : (i == j ? 1.0 : 0.0);
+        const double v = D[(size_t)(k0 + min(i, tb - 1)) * n + k0 + min(j, tb - 1)];
+        T[i][j] = (i < tb && j < tb) ? v : (i == j ? 1.0 : 0.0);
     }
     __syncthreads();
     double r[kTB];
@@ -1196,9 +1375,11 @@ __global__ __launch_bounds__(64) void k_potrf_panel(int n, double *Db, double *L
         }
         return;
     }
+    __shared__ double rdiag[kTB];
     if (t < kTB) {
 #pragma unroll
         for (int m = 0; m < kTB; ++m) T[t][m] = r[m];
+        rdiag[t] = 1.0 / r[t];
     }
     __syncthreads();
     const int row = k0 + tb + (blockIdx.x - 1) * 64 + t;
@@ -1214,7 +1395,7 @@ __global__ __launch_bounds__(64) void k_potrf_panel(int n, double *Db, double *L
 #pragma unroll
     for (int j = 0; j < kTB; ++j) {
         if (j < tb) {
-            x[j] = x[j] / T[j][j];
+            x[j] = x[j] * rdiag[j];
 #pragma unroll
             for (int m = j + 1; m < kTB; ++m) x[m] -= x[j] * T[m][j];
         }
@@ -1241,10 +1422,14 @@ __global__ __launch_bounds__(kBlock) void k_syrk_tile(int n, double *Db, int k0)
     const long tj = p - ti * (ti + 1) / 2;
     const int r0 = s0 + (int)ti * kTB, c0 = s0 + (int)tj * kTB;
     const int t = threadIdx.x, ra = (t / 16) * 2, cb = (t % 16) * 2;
-    for (int e = t; e < kTB * kTB; e += kBlock) {
+#pragma unroll
+    for (int e = t; e < kTB * kTB; e += kBlock) {  // unconditional loads, as in tile_load
         const int a = e / kTB, m = e % kTB;
-        P[a][m] = (r0 + a < n && m < tb) ? D[(size_t)(r0 + a) * n + k0 + m] : 0.0;
-        Q[m][a] = (c0 + a < n && m < tb) ? D[(size_t)(c0 + a) * n + k0 + m] : 0.0;
+        const int mc = k0 + min(m, tb - 1);
+        const double vp = D[(size_t)min(r0 + a, n - 1) * n + mc];
+        const double vq = D[(size_t)min(c0 + a, n - 1) * n + mc];
+        P[a][m] = (r0 + a < n && m < tb) ? vp : 0.0;
+        Q[m][a] = (c0 + a < n && m < tb) ? vq : 0.0;
     }
     __syncthreads();
     double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
@@ -1268,11 +1453,16 @@ __global__ __launch_bounds__(64) void k_trtri_tile(int n, const double *Ldb, dou
     const double *Ld = Ldb + ((size_t)blockIdx.z * T0 + blockIdx.x) * kTB * kTB;
     double *Lam = Lamb + ((size_t)blockIdx.z * T0 + blockIdx.x) * kTB * kTB;
     const int k0 = blockIdx.x * kTB;
-    for (int e = threadIdx.x; e < kTB * kTB; e += 64) {
+#pragma unroll
+    for (int e = threadIdx.x; e < kTB * kTB; e += 64) {  // the tile buffer is whole: unconditional loads
         const int a = e / kTB, b = e % kTB;
         const bool in = k0 + a < n && k0 + b < n;
-        T[a][b] = b > a ? 0.0 : in ? Ld[a * kTB + b] : (a == b ? 1.0 : 0.0);
+        const double v = Ld[a * kTB + b];
+        T[a][b] = b > a ? 0.0 : in ? v : (a == b ? 1.0 : 0.0);
     }
+    __shared__ double rdiag[kTB];
+    __syncthreads();
+    if (threadIdx.x < kTB) rdiag[threadIdx.x] = 1.0 / T[threadIdx.x][threadIdx.x];
     __syncthreads();
     const int j = threadIdx.x;
     if (j >= kTB) return;
@@ -1282,7 +1472,7 @@ __global__ __launch_bounds__(64) void k_trtri_tile(int n, const double *Ldb, dou
         double v = i == j ? 1.0 : 0.0;
 #pragma unroll
         for (int m = 0; m < i; ++m) v -= T[i][m] * x[m];
-        x[i] = v / T[i][i];
+        x[i] = v * rdiag[i];
     }
 #pragma unroll
     for (int i = 0; i < kTB; ++i) Lam[i * kTB + j] = x[i];
@@ -1351,10 +1541,31 @@ __global__ __launch_bounds__(kBlock) void k_wtw(int n, const double *Wb, double 
     const int i = (int)ti, j = (int)(p - ti * (ti + 1) / 2);
     const int t = threadIdx.x, ra = (t / 16) * 2, cb = (t % 16) * 2;
     double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    // the next tile pair is loaded into registers while the current one is
+    // multiplied (clamped indices, zero outside the matrix, as in tile_load)
+    constexpr int PER = kTB * kTB / kBlock;
+    double pr[PER], qr[PER];
+    auto fetch = [&](int m) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = t + u * kBlock, a = e / kTB, b = e % kTB;
+            const int r = m * kTB + a;
+            const size_t ro = (size_t)min(r, n - 1) * n;
+            const double vp = W[ro + min(i * kTB + b, n - 1)], vq = W[ro + min(j * kTB + b, n - 1)];
+            pr[u] = (r < n && i * kTB + b < n) ? vp : 0.0;
+            qr[u] = (r < n && j * kTB + b < n) ? vq : 0.0;
+        }
+    };
+    fetch(i);
     for (int m = i; m < T0; ++m) {
-        tile_load(P, W, n, m * kTB, i * kTB);
-        tile_load(Q, W, n, m * kTB, j * kTB);
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = t + u * kBlock;
+            P[e / kTB][e % kTB] = pr[u];
+            Q[e / kTB][e % kTB] = qr[u];
+        }
         __syncthreads();
+        if (m + 1 < T0) fetch(m + 1);
         tile_mac<true>(P, Q, acc);
         __syncthreads();
     }
@@ -1410,6 +1621,8 @@ __global__ void k_sell_fill(int n, int nsl, const int *rp, const int *ci, const 
         }
     }
 }
+
+#pragma clang fp contract(off)
 
 // padded FP64 and float32 copies of a dense n x n operator (row stride ld)
 __global__ void k_pad_dense(int n, int ld, const double *src, double *d64, float *d32) {
@@ -1672,6 +1885,7 @@ struct Setup {
         DCsr C;
         int *cnt = nullptr;
         bool wide = false;
+        int dc = 0;  // > 0: B has at most dc columns, dense-accumulator passes
         int gr = 0, umax = 0, bmax = 0;
     };
 
@@ -1701,9 +1915,20 @@ struct Setup {
         auto count_sub = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(grs), dim3(kBlock), 0, s, A.n, A.rp, A.ci, B.rp, B.ci, cnt, isc + 10);
         };
+        // dense accumulators for the products of few rows whose B has at most
+        // 2048 columns (for many rows the hash passes are faster)
+        pr.dc = !wide ? 0 : B.m <= 256 ? 256 : B.m <= 512 ? 512 : B.m <= 1024 ? 1024 : B.m <= 2048 ? 2048 : 0;
+        auto count_dense = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(std::max(1, std::min(A.n, 65535))), dim3(64), 0, s, A.n, A.rp, A.ci, B.rp,
+                               B.ci, cnt, isc + 10);
+        };
         // first tier: small tables; rows that overflow half of one are counted
         // again with kHS slots
-        if (wide) count(k_spgemm_count<4, 512>, 0);
+        if (pr.dc == 256) count_dense(k_spgemm_count_dense<256>);
+        else if (pr.dc == 512) count_dense(k_spgemm_count_dense<512>);
+        else if (pr.dc == 1024) count_dense(k_spgemm_count_dense<1024>);
+        else if (pr.dc == 2048) count_dense(k_spgemm_count_dense<2048>);
+        else if (wide) count(k_spgemm_count<4, 512>, 0);
         else if (lpr == 16) count_sub(k_spgemm_count_sub<16, 128>);
         else if (lpr == 32) count_sub(k_spgemm_count_sub<32, 256>);
         else count_sub(k_spgemm_count_sub<64, 512>);
@@ -1745,7 +1970,29 @@ struct Setup {
         const int gr = pr.gr, umax = pr.umax, bmax = pr.bmax;
         C.ci = c.arena.alloc<int>(C.nnz);
         C.v = c.arena.alloc<double>(C.nnz);
-        if (wide) {
+        if (C.nnz == 0) {  // no products: the numeric kernels assume B has entries
+            rel(pr.cnt);
+            return C;
+        }
+        if (pr.dc > 0) {
+            // four wavefronts per row when rows of B are longer than one wavefront
+            const int nw = bmax > 64 ? 4 : 1;
+            auto fill = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(std::max(1, std::min(A.n, 65535))), dim3(64 * nw), 0, s, A.n, B.m,
+                                   A.rp, A.ci, A.v, B.rp, B.ci, B.v, C.rp, C.ci, C.v);
+            };
+            if (nw == 1) {
+                if (pr.dc == 256) fill(k_spgemm_fill_dense<256, 1>);
+                else if (pr.dc == 512) fill(k_spgemm_fill_dense<512, 1>);
+                else if (pr.dc == 1024) fill(k_spgemm_fill_dense<1024, 1>);
+                else fill(k_spgemm_fill_dense<2048, 1>);
+            } else {
+                if (pr.dc == 256) fill(k_spgemm_fill_dense<256, 4>);
+                else if (pr.dc == 512) fill(k_spgemm_fill_dense<512, 4>);
+                else if (pr.dc == 1024) fill(k_spgemm_fill_dense<1024, 4>);
+                else fill(k_spgemm_fill_dense<2048, 4>);
+            }
+        } else if (wide) {
             // G rows of B per step when every row of B fits 256 / G threads (groups of 8 at least)
             int G = 1;
             while (2 * G <= 256 / 8 && 256 / (2 * G) >= bmax) G *= 2;
