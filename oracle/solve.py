@@ -311,20 +311,29 @@ class Oracle:
 
     def hessian_apply(self, j: int, u: np.ndarray, rtol=None) -> np.ndarray:
         """H_j u = K_j^T M_{y,j} K_j u + beta M_{u,j} u."""
+        return self.hessian_apply_t(j, u, rtol)[0]
+
+    def hessian_apply_t(self, j: int, u: np.ndarray, rtol=None):
+        """(H_j u, t) with t = A_j^{-1} M_{y,j} K_j u, so that
+        H_j u = M_{yu,j}^T t + beta M_{u,j} u."""
         y = self.state_solve(j, u, rtol)
-        z = self.adjoint_solve(j, sa.mass_y(self.h, j, y), rtol)
-        return z + self.beta * sa.mass_u(self.h, j, u)
+        t = self.solve_A(j, sa.mass_y(self.h, j, y), rtol or self.o.inner_rtol)
+        return sa.mass_yu_t(self.h, j, t) + self.beta * sa.mass_u(self.h, j, u), t
 
     def rhs(self, yd: np.ndarray) -> np.ndarray:
         """b = K_0^T M_{y,0} y_d."""
         return self.adjoint_solve(0, sa.mass_y(self.h, 0, yd))
 
     # ---- multilevel preconditioner ----
-    def C(self, j: int, r: np.ndarray) -> np.ndarray:
+    def C(self, j: int, r: np.ndarray, mr=None) -> np.ndarray:
+        """C_j r (practical form, Section 5.2); mr: M_{u,j}^{-1} r when the
+        caller has it."""
         lev = self.h.levels[j]
         q = lev.St.matvec(r)
         v = self.B(j + 1, q) - (1.0 / self.beta) * self.mass_solve(j + 1, q)
-        return lev.S.matvec(v) + (1.0 / self.beta) * self.mass_solve(j, r)
+        if mr is None:
+            mr = self.mass_solve(j, r)
+        return lev.S.matvec(v) + (1.0 / self.beta) * mr
 
     def B(self, j: int, r: np.ndarray) -> np.ndarray:
         h = self.h
@@ -337,10 +346,16 @@ class Oracle:
                                   lambda v: self.mass_solve(j, v), r, self.o.coarse_hess_rtol, self.o.outer_maxit)
             self.cnt.coarse_cg_iters += it
             return x
-        z = self.C(j, r)
-        if j > 0:
-            z = z + self.C(j, r - self.hessian_apply(j, z, self.o.precond_inner_rtol))
-        return z
+        if j == 0:
+            return self.C(0, r)
+        # Algorithm MLAS: B_j r = z + C_j (r - H_j z), z = C_j r.  At j >= 1 the
+        # mass matrices are all M_j, so H_j z = M_j (t + beta z) with t the
+        # Hessian's inner result, and the second C_j's mass solve is
+        # M_j^{-1} (r - H_j z) = M_j^{-1} r - (t + beta z), from the first's.
+        mr = self.mass_solve(j, r)
+        z = self.C(j, r, mr)
+        hz, t = self.hessian_apply_t(j, z, self.o.precond_inner_rtol)
+        return z + self.C(j, r - hz, mr - (t + self.beta * z))
 
     def precond(self, r: np.ndarray) -> np.ndarray:
         return self.B(0, r) if self.o.precond else r.copy()

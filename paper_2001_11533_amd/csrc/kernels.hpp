@@ -1358,6 +1358,18 @@ template <int NB> struct OpAxpby {  // out = a x + b y (a, b per column or scala
     }
 };
 
+// out = x - (y + b w)
+template <int NB> struct OpSubSum {
+    double *out;
+    const double *x, *y, *w;
+    double b;
+    __device__ void prep(int) {}
+    template <int NV> __device__ void operator()(int i, int c, double (&)[NV]) const {
+        const size_t o = (size_t)i * NB + c;
+        out[o] = x[o] - (y[o] + b * w[o]);
+    }
+};
+
 // outer CG direction update: p = z + beta_c p
 template <int NB> struct OpPUpd {
     double *p;

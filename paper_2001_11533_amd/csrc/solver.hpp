@@ -714,7 +714,11 @@ template <int NB> struct Solver {
         LevelWs &w = c.ws[l];
         Cop(l, r, w.ml_z1, nullptr, w.ml_mup);
         hessian_apply(l, w.ml_z1, w.ml_t, c.o.precond_inner_rtol, r);  // t = r - H_l z1
-        Cop(l, w.ml_t, z, w.ml_z1);                                     // z = z1 + C_l t
+        // the second C_l's mass solve from the first's: at l >= 1 every mass
+        // matrix is M_l, so H_l z1 = M_l (ht + beta z1) (ht the Hessian's inner
+        // result) and M_l^{-1} t = M_l^{-1} r - (ht + beta z1)
+        elem<0>(c.lev[l].n, OpSubSum<NB>{w.ml_mself, w.ml_mup, w.ht, w.ml_z1, c.o.beta}, NoFin{}, nullptr);
+        Cop(l, w.ml_t, z, w.ml_z1, w.ml_mself);                         // z = z1 + C_l t
     }
 
     // Coarsest Hessian level too large to invert densely: CG on G_l in the

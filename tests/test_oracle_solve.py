@@ -129,6 +129,46 @@ def test_practical_preconditioner_equals_paper_multilevel_operator(name, n, mc):
     assert np.max(np.abs(ref - ref.T)) <= 1e-8 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("name,n,mc", [("c2", 12, 12), ("c3", 5, 8)])
+def test_coarse_mass_solve_of_hessian_is_its_inner_result(name, n, mc):
+    """At levels j >= 1 the state, control and mixed mass matrices are all M_j,
+    so M_j^{-1} H_j z = t + beta z with t = A_j^{-1} M_j A_j^{-1} M_j z: checked
+    against a dense solve with M_j, at every intermediate level.  B_j uses it for
+    the mass solve of its second C_j."""
+    p, h = build(name, n, max_coarse=mc, beta=1e-2, **tight())
+    assert h.ell >= 3
+    o = solve.Oracle(h)
+    rng = np.random.default_rng(11)
+    for j in range(1, h.ell - 1):
+        z = rng.standard_normal(h.levels[j].n)
+        hz, t = o.hessian_apply_t(j, z, 1e-13)
+        Mj = h.levels[j].M.dense()
+        lhs = np.linalg.solve(Mj, hz)
+        rhs = t + h.opts.beta * z
+        assert np.linalg.norm(lhs - rhs) <= 1e-10 * np.linalg.norm(rhs)
+        # and t is not a neighbouring intermediate (K z, or M^{-1} H z without beta z)
+        y = o.state_solve(j, z, 1e-13)
+        assert np.linalg.norm(lhs - (y + h.opts.beta * z)) > 1e-3 * np.linalg.norm(rhs)
+        assert np.linalg.norm(lhs - t) > 1e-3 * np.linalg.norm(rhs)
+
+
+def test_multilevel_preconditioner_with_fresh_second_mass_solve():
+    """B_j with the second C_j's mass solve taken from the first (the identity
+    above) equals B_j with that mass solve done afresh, to the inner tolerances."""
+    p, h = build("c3", 5, max_coarse=8, beta=1e-2, **tight())
+    assert h.ell >= 3
+    o = solve.Oracle(h)
+    r = np.random.default_rng(12).standard_normal(h.levels[1].n)
+
+    def B_fresh(j, v):
+        z = o.C(j, v)
+        return z + o.C(j, v - o.hessian_apply(j, z, o.o.precond_inner_rtol))
+
+    ref = B_fresh(1, r)
+    got = o.B(1, r)
+    assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
 def test_two_grid_identities():
     p, h = build("c2", 12, max_coarse=12, beta=1e-3)
     P = h.levels[0].S.dense()
