@@ -25,6 +25,7 @@ struct Level {
     DCsr T;                     // A_j S_j (level < L-1; its pattern contains that of S_j)
     double *Ts = nullptr;       // S_j's values on T's pattern (zero where S_j has no entry)
     float *Ts32 = nullptr;
+    uint16_t *Tc16 = nullptr;   // T's columns as 16-bit values (when n_{j+1} <= 65536)
     double *dl1inv = nullptr;   // 1 / sum_k |a_ik|
     float *dl1inv32 = nullptr;
     double *mdinv = nullptr;    // 1 / diag(M_j)

@@ -848,10 +848,11 @@ template <typename T, int NB, bool DOT> struct EPost {
 // carries S's values aligned to it (zero where S has no entry): per row i and
 // column c, se = (S e)_i and te = (T e)_i, both gathered from the coarse
 // vector e.  LPR = G NB lanes per row: G groups over the entries, one lane per
-// column; the epilogue receives both sums.
-template <typename T, int NB, int NV, class EP>
+// column; the epilogue receives both sums.  Columns are int32 or, when the
+// coarse level has at most 65536 nodes, 16-bit (CI = uint16_t).
+template <typename T, int NB, int NV, class EP, typename CI = int>
 __global__ __launch_bounds__(kBlock) void tpro_kernel(int nrows, const int *__restrict__ rp,
-                                                      const int *__restrict__ ci, const T *__restrict__ tv,
+                                                      const CI *__restrict__ ci, const T *__restrict__ tv,
                                                       const T *__restrict__ sv, const T *__restrict__ e, EP ep,
                                                       int llpr, Reducer<(NV > 0 ? NV : 1), NB> red,
                                                       const int *__restrict__ stop) {
@@ -884,7 +885,7 @@ __global__ __launch_bounds__(kBlock) void tpro_kernel(int nrows, const int *__re
                 for (int u = 0; u < U; ++u) {
                     const int q = p + u * G;
                     const int qc = min(q, p1 - 1);
-                    kk[u] = ci[qc];
+                    kk[u] = (int)ci[qc];
                     const T a = tv[qc], s = sv[qc];
                     ta[u] = q < p1 ? a : T(0);
                     sa[u] = q < p1 ? s : T(0);

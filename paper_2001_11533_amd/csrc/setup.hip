@@ -1254,6 +1254,11 @@ __global__ void k_to_f32(long n, const double *a, float *b) {
         b[i] = (float)a[i];
 }
 
+__global__ void k_to_u16(long n, const int *a, uint16_t *b) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        b[i] = (uint16_t)a[i];
+}
+
 // ---- dense kernels (coarsest level) ----
 __global__ __launch_bounds__(kBlock) void k_densify(int n, const int *rp, const int *ci, const double *v,
                                                     const uint8_t *rmask, const uint8_t *cmask, double *D) {
@@ -2472,6 +2477,10 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
             f32(L.T);
             L.Ts32 = c.arena.alloc<float>(L.T.nnz);
             hipLaunchKernelGGL(k_to_f32, dim3(gsz(L.T.nnz)), dim3(kBlock), 0, s, (long)L.T.nnz, L.Ts, L.Ts32);
+            if (L.T.m <= 65536 && L.T.nnz > 0) {  // T's columns are coarse indices: 16 bits suffice
+                L.Tc16 = c.arena.alloc<uint16_t>(L.T.nnz);
+                hipLaunchKernelGGL(k_to_u16, dim3(gsz(L.T.nnz)), dim3(kBlock), 0, s, (long)L.T.nnz, L.T.ci, L.Tc16);
+            }
         }
         L.dl1inv32 = c.arena.alloc<float>(L.n);
         hipLaunchKernelGGL(k_to_f32, dim3(gsz(L.n)), dim3(kBlock), 0, s, (long)L.n, L.dl1inv, L.dl1inv32);

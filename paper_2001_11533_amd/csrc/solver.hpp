@@ -125,8 +125,12 @@ template <int NB> struct Solver {
         const int g = grid_rows(Tm.n, kBlock >> llpr, NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
         Reducer<(NV > 0 ? NV : 1), NB> red{part[pbuf]};
         if (NV > 0) pgrid[pbuf] = g;
-        hipLaunchKernelGGL((tpro_kernel<T, NB, NV, EP>), dim3(g), dim3(kBlock), 0, s, Tm.n, Tm.rp, Tm.ci,
-                           avals<T>(Tm), tsvals<T>(Lv), e, ep, llpr, red, stop);
+        if (Lv.Tc16)
+            hipLaunchKernelGGL((tpro_kernel<T, NB, NV, EP, uint16_t>), dim3(g), dim3(kBlock), 0, s, Tm.n, Tm.rp,
+                               Lv.Tc16, avals<T>(Tm), tsvals<T>(Lv), e, ep, llpr, red, stop);
+        else
+            hipLaunchKernelGGL((tpro_kernel<T, NB, NV, EP>), dim3(g), dim3(kBlock), 0, s, Tm.n, Tm.rp, Tm.ci,
+                               avals<T>(Tm), tsvals<T>(Lv), e, ep, llpr, red, stop);
     }
 
     template <int NV, class OP, class FIN> void elem(int n, OP op, FIN fin, const int *stop, int pbuf = 0) {
