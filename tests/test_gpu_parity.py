@@ -25,7 +25,7 @@ def _need_gpu():
 
 
 ORACLE_KEYS = ("hess_levels", "max_coarse", "inner_rtol", "mass_rtol", "precond_inner_rtol", "precond", "dense_max", "dense_solve_max",
-               "inner32_rtol", "mixed_mode", "smoother")
+               "inner32_rtol", "mixed_mode", "smoother", "theta0")
 
 
 def make(name, n, nb_max=1, **opts):
@@ -50,8 +50,12 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+# theta0 = 0.3 on the 64^2 mesh coarsens slowly (4225 -> 2253 -> 1218 -> 883 ->
+# 179 nodes): the level-0 products have fewer than 8192 rows and more than 2048
+# output columns, the case of the hash-table product kernels for few rows (the
+# other few-row products use dense accumulators)
 SETUP_CASES = [("c1", None, {}), ("c2", 64, {}), ("c3", 16, {}), ("c3", 20, {"max_coarse": 50}),
-               ("c2", 48, {"max_coarse": 10})]
+               ("c2", 48, {"max_coarse": 10}), ("c2", 64, {"theta0": 0.3})]
 
 
 @pytest.mark.parametrize("name,n,opts", SETUP_CASES)
