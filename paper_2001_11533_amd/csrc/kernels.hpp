@@ -209,9 +209,14 @@ __device__ void sum_quantities(SRC src, double *out) {
 #pragma unroll
             for (int k = 0; k < 8; ++k) a[k] += v[k];
         }
+        // at most seven left: loaded unconditionally (clamped index), added
+        // only where valid, so the seven loads are in flight together
+        const int last = nblk > 0 ? nblk - 1 : 0;
+        double v[7];
 #pragma unroll
-        for (int k = 0; k < 7; ++k)  // at most seven left
-            if (b + k * LPS < nblk) a[k] += pp[b + k * LPS];
+        for (int k = 0; k < 7; ++k) v[k] = pp[min(b + k * LPS, last)];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) a[k] = b + k * LPS < nblk ? a[k] + v[k] : a[k];
         s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
 #pragma unroll
