@@ -341,8 +341,9 @@ const char *amg_last_error(amg_ctx *ctx);
  * reads or gathers once, every vector it writes once; for which 4 the bytes of
  * the method's product q = A p: 4 (n+1) + (4 + 8) nnz(A_0) + 2 8 n nb).  Level-0 products with one
  * column run on a sliced-ELL copy whose columns are 16-bit offsets from a base
- * per slice of 64 rows (built when every slice spans fewer than 65536 columns);
- * their column indices count 2 bytes, all others 4.
+ * per slice of 64 rows (built when every slice spans fewer than 65536 columns),
+ * and T_0's columns are kept as 16-bit values when level 1 has at most 65536
+ * nodes; such column indices count 2 bytes, all others 4.
  * Errors: ARG; NOCONV if a grid barrier wait of entry 5 timed out. */
 int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double *ms_avg,
                     double *bytes);

@@ -1178,8 +1178,8 @@ int amg_time_kernel(amg_ctx *ctx, int which, int prec, int nb, int reps, double 
                     *bytes = 4.0 * (n + 1) + (ib(0) + sz) * L0.A.nnz + 3.0 * sz * n * nbd;
                 else if (which == 3)  // T's pattern with both value arrays, e gathered once,
                                       // t, r and dinv read, t and y written
-                    *bytes = 4.0 * (n + 1) + (4.0 + 2.0 * sz) * L0.T.nnz + sz * c.lev[1].n * nbd +
-                             (4.0 * sz * nbd + sz) * n;
+                    *bytes = 4.0 * (n + 1) + ((L0.Tc16 ? 2.0 : 4.0) + 2.0 * sz) * L0.T.nnz +
+                             sz * c.lev[1].n * nbd + (4.0 * sz * nbd + sz) * n;
                 else {
                     // the cycle ends at the first level with a dense inverse
                     int Lc = c.L - 1;
