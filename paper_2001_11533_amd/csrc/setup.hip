@@ -1384,8 +1384,10 @@ __global__ __launch_bounds__(64) void k_potrf_panel(int n, double *Db, double *L
     if (t < kTB) {
 #pragma unroll
         for (int m = 0; m < kTB; ++m) T[t][m] = r[m];
-        rdiag[t] = 1.0 / r[t];
     }
+    __syncthreads();
+    // (from LDS: indexing the register row r by the lane would move it to scratch)
+    if (t < kTB) rdiag[t] = 1.0 / T[t][t];
     __syncthreads();
     const int row = k0 + tb + (blockIdx.x - 1) * 64 + t;
     const bool live = row < n;
