@@ -52,7 +52,7 @@ extern "C" {
 #define AMG_OK 0
 #define AMG_ERR_ARG (-1)            /* invalid argument (null, size, range) */
 #define AMG_ERR_NOT_SYMMETRIC (-2)  /* input stiffness/mass matrix not exactly symmetric */
-#define AMG_ERR_NOT_SPD (-3)        /* non-positive diagonal / failed Cholesky */
+#define AMG_ERR_NOT_SPD (-3)        /* non-positive diagonal / non-positive pivot of a dense inverse */
 #define AMG_ERR_NOCONV (-4)         /* an iteration hit its limit; outputs hold the last iterate */
 #define AMG_ERR_INDEFINITE (-5)     /* outer CG met p.Hp <= 0 or r.Br <= 0 */
 #define AMG_ERR_HIP (-6)            /* a HIP runtime call failed */
@@ -199,9 +199,9 @@ int amg_p1_assemble_device_noalloc(int dim, int32_t nv, const double *coords, in
 /* Build the context: the Dirichlet-reduced stiffness A_0, the smoothed-aggregation
  * hierarchy (strength graph, distance-2 aggregation, smoothed prolongators S_j and
  * their transposes, Galerkin products A_{j+1} = S_j^T A_j S_j and M_{j+1} = S_j^T M_j
- * S_j: eqs. coarsestiffness and coarsemass with P_j = S_j), the dense Cholesky
- * factor of the coarsest A, and the dense coarsest Hessian H_{l-1} (Section 3.2:
- * the coarsest level is inverted exactly).
+ * S_j: eqs. coarsestiffness and coarsemass with P_j = S_j), the dense inverse of
+ * the coarsest A (and of A_j, M_j on small levels), and the dense coarsest Hessian
+ * H_{l-1} (Section 3.2: the coarsest level is inverted exactly).
  *   A, M: the assembled stiffness and mass matrices (device CSR, same pattern not
  *         required), N x N, exactly symmetric.
  *   dirichlet: device uint8 [N] (1 = Dirichlet node) or NULL (none).

@@ -1275,44 +1275,25 @@ __global__ __launch_bounds__(kBlock) void k_densify(int n, const int *rp, const 
     }
 }
 
-// Tiled right-looking Cholesky of the lower triangle (tiles of kTB): per tile
-// column, factor the diagonal tile and solve the panel below it (one launch),
-// then update the trailing lower tiles.  Only the lower triangle is read later.
-// Every dense kernel below works on a batch of matrices of one order n stored
-// back to back (matrix blockIdx.z at D + blockIdx.z * n * n).
-// The dense factorisations and inverses below are compared with the oracle
-// within a tolerance, not bit for bit: fused multiply-add is allowed there.
+// Dense inverses (tiles of kTB): every dense kernel below works on a batch of
+// matrices of one order n stored back to back (matrix blockIdx.z at
+// D + blockIdx.z * n * n).  They are compared with the oracle within a
+// tolerance, not bit for bit: fused multiply-add is allowed there.
 #pragma clang fp contract(fast)
 constexpr int kTB = 32;
 
 __device__ __forceinline__ double *bat(double *D, int n) { return D + (size_t)blockIdx.z * n * n; }
 __device__ __forceinline__ const double *bat(const double *D, int n) { return D + (size_t)blockIdx.z * n * n; }
 
-// ---- inverse from the Cholesky factor: A^{-1} = W^T W with W = L^{-1} ----
-// kTB x kTB tiles in LDS, zero outside the matrix; 256 threads each own a 2x2
-// block of the product tile.
+// kTB x kTB tiles in LDS; 256 threads each own a 2x2 block of a product tile.
 typedef double Tile[kTB][kTB + 1];
 
-// (loads unconditional at clamped indices, then zeroed outside the matrix, so
-// that all of a thread's loads are in flight together; guarded loads compile
-// to one wait each)
-__device__ __forceinline__ void tile_load(Tile &T, const double *D, int n, int r0, int c0) {
-#pragma unroll
-    for (int e = threadIdx.x; e < kTB * kTB; e += kBlock) {
-        const int a = e / kTB, b = e % kTB;
-        const double v = D[(size_t)min(r0 + a, n - 1) * n + min(c0 + b, n - 1)];
-        T[a][b] = (r0 + a < n && c0 + b < n) ? v : 0.0;
-    }
-}
-
-// acc += P Q (transP: P^T Q) for the thread's 2x2 block (rows ra, ra+1; columns cb, cb+1)
-template <bool TransP>
+// acc += P Q for the thread's 2x2 block (rows ra, ra+1; columns cb, cb+1)
 __device__ __forceinline__ void tile_mac(const Tile &P, const Tile &Q, double acc[2][2]) {
     const int ra = (threadIdx.x / 16) * 2, cb = (threadIdx.x % 16) * 2;
 #pragma unroll 8
     for (int m = 0; m < kTB; ++m) {
-        const double a0 = TransP ? P[m][ra] : P[ra][m];
-        const double a1 = TransP ? P[m][ra + 1] : P[ra + 1][m];
+        const double a0 = P[ra][m], a1 = P[ra + 1][m];
         const double b0 = Q[m][cb], b1 = Q[m][cb + 1];
         acc[0][0] += a0 * b0;
         acc[0][1] += a0 * b1;
@@ -1321,271 +1302,180 @@ __device__ __forceinline__ void tile_mac(const Tile &P, const Tile &Q, double ac
     }
 }
 
-// Value of v in lane l of the wavefront (an FP64 register read through two
-// 32-bit lane reads).
-__device__ __forceinline__ double lane_read(double v, int l) {
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
-    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
+// ---- inverse by block Gauss-Jordan sweeps ----
+// Sweeping a symmetric matrix on pivot block K (kTB rows) with Q = -(A_KK)^{-1}
+// gives A_KK <- Q, A_iK <- -A_iK Q, A_Kj <- -Q A_Kj and A_ij <- A_ij + A_iK Q A_Kj
+// for i, j outside K; swept on all of its pivots the matrix becomes -A^{-1}.
+// For an SPD matrix each pivot block met is a Schur complement of a leading
+// block, SPD as well, so no pivoting is needed, and the matrix stays symmetric:
+// only tiles (ti, tj) with ti >= tj are kept (diagonal tiles whole).  A sweep
+// reads the matrix from src and writes it to dst in two launches: the pivot
+// block column (k_gj_panel: Q and A_iK <- -A_iK Q), then every other tile
+// (k_gj_update: A_ij <- A_ij - A_iK' A_Kj with the new A_iK' from the first).
+// Tiles of a ragged last block hold the identity on their padded diagonal.
 
-// Diagonal tile factor and panel solve of tile column k0 in one launch, one
-// wavefront per workgroup.  Every workgroup factors the diagonal tile in
-// registers: lane i < kTB holds row i (padded with the identity past n), and
-// at step k the pivot and the entries of column k reach the other lanes by
-// lane reads, so the factorization needs neither LDS nor barriers; the upper
-// triangle of the registers holds garbage that no lower entry reads.
-// Workgroup 0 stores L_kk in the tile buffer Ldb (tile k0 / kTB of matrix z at
-// Ldb + (z T0 + k0 / kTB) kTB^2, row-major lower triangle), never in D: the
-// other workgroups of the launch read the unfactored tile from D and may
-// start after workgroup 0 has finished.  Workgroup b > 0 puts L_kk in LDS and
-// solves X L_kk^T = A_ik for the b-th block of 64 rows below the tile, one row
-// per lane.  Every entry takes its updates in ascending k as in an unblocked
-// column Cholesky.
-__global__ __launch_bounds__(64) void k_potrf_panel(int n, double *Db, double *Ldb, int k0, int *bad) {
-    __shared__ double T[kTB][kTB + 1];
-    double *D = bat(Db, n);
-    const int tb = min(kTB, n - k0);
-    const int t = threadIdx.x;
+// logical tile (r0 / kTB, c0 / kTB) of the symmetric matrix from stored tile
+// (r0, c0) (Tr = false) or, transposed, from stored tile (c0, r0) (Tr = true);
+// unconditional loads at clamped indices, zero outside the matrix
+template <bool Tr>
+__device__ __forceinline__ void tile_load_sym(Tile &T, const double *D, int n, int r0, int c0) {
+    const int sr = Tr ? c0 : r0, sc = Tr ? r0 : c0;
 #pragma unroll
-    for (int e = t; e < kTB * kTB; e += 64) {  // unconditional loads, as in tile_load
-        const int i = e / kTB, j = e % kTB;
-        const double v = D[(size_t)(k0 + min(i, tb - 1)) * n + k0 + min(j, tb - 1)];
-        T[i][j] = (i < tb && j < tb) ? v : (i == j ? 1.0 : 0.0);
-    }
-    __syncthreads();
-    double r[kTB];
-#pragma unroll
-    for (int m = 0; m < kTB; ++m) r[m] = t < kTB ? T[t][m] : 0.0;
-    // (the uniform branch per step also keeps the compiler from hoisting the
-    // reads of every step to the top, which spills registers)
-#pragma unroll
-    for (int k = 0; k < kTB; ++k) {
-        if (k < tb) {
-            const double a = lane_read(r[k], k);
-            if (!(a > 0.0) && blockIdx.x == 0 && t == 0) atomicOr(bad, 1);
-            const double piv = a > 0.0 ? sqrt(a) : 1.0;
-            r[k] = t == k ? piv : t > k ? r[k] / piv : r[k];
-#pragma unroll
-            for (int j = k + 1; j < kTB; ++j) r[j] -= r[k] * lane_read(r[k], j);
-        }
-    }
-    if (blockIdx.x == 0) {
-        double *Ld = Ldb + ((size_t)blockIdx.z * ceil_div(n, kTB) + k0 / kTB) * kTB * kTB;
-        if (t < tb) {
-#pragma unroll
-            for (int m = 0; m < kTB; ++m)
-                if (m <= t) Ld[t * kTB + m] = r[m];
-        }
-        return;
-    }
-    __shared__ double rdiag[kTB];
-    if (t < kTB) {
-#pragma unroll
-        for (int m = 0; m < kTB; ++m) T[t][m] = r[m];
-    }
-    __syncthreads();
-    // (from LDS: indexing the register row r by the lane would move it to scratch)
-    if (t < kTB) rdiag[t] = 1.0 / T[t][t];
-    __syncthreads();
-    const int row = k0 + tb + (blockIdx.x - 1) * 64 + t;
-    const bool live = row < n;
-    double x[kTB];
-    const double *src = D + (size_t)min(row, n - 1) * n + k0;  // a valid address for every lane
-#pragma unroll
-    for (int m = 0; m < kTB; ++m) {
-        const double v = src[min(m, tb - 1)];
-        x[m] = (live && m < tb) ? v : 0.0;
-    }
-    // by columns of L_kk: x[m] takes x[j] L_mj for j = 0, 1, ... before its division
-#pragma unroll
-    for (int j = 0; j < kTB; ++j) {
-        if (j < tb) {
-            x[j] = x[j] * rdiag[j];
-#pragma unroll
-            for (int m = j + 1; m < kTB; ++m) x[m] -= x[j] * T[m][j];
-        }
-    }
-    if (live) {
-#pragma unroll
-        for (int m = 0; m < kTB; ++m)
-            if (m < tb) D[(size_t)row * n + k0 + m] = x[m];
-    }
-}
-
-// Trailing update A_ij -= L_ik L_jk^T for tile pairs i >= j after tile column
-// k0: L_ik in P, L_jk transposed in Q, 2 x 2 entries per thread; every entry
-// subtracts its sum over the tile column in ascending order.
-__global__ __launch_bounds__(kBlock) void k_syrk_tile(int n, double *Db, int k0) {
-    __shared__ Tile P, Q;
-    double *D = bat(Db, n);
-    const int tb = min(kTB, n - k0);
-    const int s0 = k0 + tb;  // first trailing row
-    const long p = blockIdx.x;
-    long ti = (long)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-    while (ti * (ti + 1) / 2 > p) --ti;
-    while ((ti + 1) * (ti + 2) / 2 <= p) ++ti;
-    const long tj = p - ti * (ti + 1) / 2;
-    const int r0 = s0 + (int)ti * kTB, c0 = s0 + (int)tj * kTB;
-    const int t = threadIdx.x, ra = (t / 16) * 2, cb = (t % 16) * 2;
-#pragma unroll
-    for (int e = t; e < kTB * kTB; e += kBlock) {  // unconditional loads, as in tile_load
-        const int a = e / kTB, m = e % kTB;
-        const int mc = k0 + min(m, tb - 1);
-        const double vp = D[(size_t)min(r0 + a, n - 1) * n + mc];
-        const double vq = D[(size_t)min(c0 + a, n - 1) * n + mc];
-        P[a][m] = (r0 + a < n && m < tb) ? vp : 0.0;
-        Q[m][a] = (c0 + a < n && m < tb) ? vq : 0.0;
-    }
-    __syncthreads();
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    tile_mac<false>(P, Q, acc);
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            const int i = r0 + ra + u, j = c0 + cb + v;
-            if (i < n && j < n && j <= i) D[(size_t)i * n + j] -= acc[u][v];
-        }
-}
-
-// Lam[z][k] = inverse of the lower-triangular diagonal tile L_kk, read from
-// the tile buffer of k_potrf_panel (padded rows and columns of a ragged last
-// tile act as the identity); one wavefront per tile, lane j < kTB solves
-// L_kk x = e_j by forward substitution.
-__global__ __launch_bounds__(64) void k_trtri_tile(int n, const double *Ldb, double *Lamb) {
-    __shared__ double T[kTB][kTB + 1];
-    const int T0 = ceil_div(n, kTB);
-    const double *Ld = Ldb + ((size_t)blockIdx.z * T0 + blockIdx.x) * kTB * kTB;
-    double *Lam = Lamb + ((size_t)blockIdx.z * T0 + blockIdx.x) * kTB * kTB;
-    const int k0 = blockIdx.x * kTB;
-#pragma unroll
-    for (int e = threadIdx.x; e < kTB * kTB; e += 64) {  // the tile buffer is whole: unconditional loads
+    for (int e = threadIdx.x; e < kTB * kTB; e += kBlock) {
         const int a = e / kTB, b = e % kTB;
-        const bool in = k0 + a < n && k0 + b < n;
-        const double v = Ld[a * kTB + b];
-        T[a][b] = b > a ? 0.0 : in ? v : (a == b ? 1.0 : 0.0);
+        const double v = D[(size_t)min(sr + a, n - 1) * n + min(sc + b, n - 1)];
+        const double w = (sr + a < n && sc + b < n) ? v : 0.0;
+        if (Tr) T[b][a] = w;
+        else T[a][b] = w;
     }
-    __shared__ double rdiag[kTB];
-    __syncthreads();
-    if (threadIdx.x < kTB) rdiag[threadIdx.x] = 1.0 / T[threadIdx.x][threadIdx.x];
-    __syncthreads();
-    const int j = threadIdx.x;
-    if (j >= kTB) return;
-    double x[kTB];
-#pragma unroll
-    for (int i = 0; i < kTB; ++i) {
-        double v = i == j ? 1.0 : 0.0;
-#pragma unroll
-        for (int m = 0; m < i; ++m) v -= T[i][m] * x[m];
-        x[i] = v * rdiag[i];
-    }
-#pragma unroll
-    for (int i = 0; i < kTB; ++i) Lam[i * kTB + j] = x[i];
 }
 
-// Block forward substitution for W = L^{-1}, step k (tile row k): every block
-// (i, c), i > k, c <= k, forms W_kc = Lam_k Acc_kc (W_kk = Lam_k) and updates
-// Acc_ic -= L_ik W_kc; the blocks with i = k + 1 (or the only row of blocks at
-// the last step) store W_kc.  Acc starts at zero and holds, for row k, minus
-// the sum of L_km W_mc over m < k when step k runs.
-__global__ __launch_bounds__(kBlock) void k_trinv_step(int n, int k, const double *Db, const double *Lamb,
-                                                       double *Accb, double *Wb) {
-    __shared__ Tile P, Q, R;
-    const double *D = bat(Db, n);
-    double *Acc = bat(Accb, n), *W = bat(Wb, n);
-    const int T0 = ceil_div(n, kTB);
-    const double *Lam = Lamb + ((size_t)blockIdx.z * T0 + k) * kTB * kTB;
-    const int c = blockIdx.y, i = k + 1 + blockIdx.x;
+// logical tile (ti, tj) of the symmetric matrix kept as lower tiles
+__device__ __forceinline__ void tile_load_lower(Tile &T, const double *D, int n, int ti, int tj) {
+    if (ti >= tj) tile_load_sym<false>(T, D, n, ti * kTB, tj * kTB);
+    else tile_load_sym<true>(T, D, n, ti * kTB, tj * kTB);
+}
+
+__device__ __forceinline__ void tile_from_p(long p, int &ti, int &tj) {
+    long i = (long)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
+    while (i * (i + 1) / 2 > p) --i;
+    while ((i + 1) * (i + 2) / 2 <= p) ++i;
+    ti = (int)i;
+    tj = (int)(p - i * (i + 1) / 2);
+}
+
+// Pivot block column of sweep k: workgroup i (one per tile row) sweeps the
+// pivot block itself, pivot by pivot in registers, the pivot row broadcast
+// through LDS (symmetric products, so Q stays exactly symmetric), while A_iK
+// is loading; then tile row k gets Q and any other one -A_iK Q.
+__global__ __launch_bounds__(kBlock) void k_gj_panel(int n, const double *srcb, double *dstb, int k, int *bad) {
+    __shared__ Tile X, Qs;
+    __shared__ double vb[2][kTB];
+    const double *src = bat(srcb, n);
+    double *dst = bat(dstb, n);
+    const int ti = blockIdx.x;
     const int t = threadIdx.x, ra = (t / 16) * 2, cb = (t % 16) * 2;
-    for (int e = t; e < kTB * kTB; e += kBlock) P[e / kTB][e % kTB] = Lam[e];
-    if (c < k) tile_load(Q, Acc, n, k * kTB, c * kTB);
+    const int K0 = k * kTB;
+    // this thread's 2 x 2 of the pivot block, from its lower half
+    double q[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int r = ra + u, c = cb + v, i = K0 + max(r, c), j = K0 + min(r, c);
+            const double x = src[(size_t)min(i, n - 1) * n + min(j, n - 1)];
+            q[u][v] = i < n ? x : (r == c ? 1.0 : 0.0);
+        }
+    if (ti != k) tile_load_lower(X, src, n, ti, k);
+    if (ra == 0) {
+        vb[0][cb] = q[0][0];
+        vb[0][cb + 1] = q[0][1];
+    }
     __syncthreads();
-    if (c < k) {
-        double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-        tile_mac<false>(P, Q, acc);
-        R[ra][cb] = acc[0][0];
-        R[ra][cb + 1] = acc[0][1];
-        R[ra + 1][cb] = acc[1][0];
-        R[ra + 1][cb + 1] = acc[1][1];
+    // scalar sweeps: a_mm <- -1/a_mm, a_rm <- a_rm/a_mm, a_rc <- a_rc - a_rm a_mc/a_mm
+    for (int m = 0; m < kTB; ++m) {
+        const double *v = vb[m & 1];
+        const double piv = v[m];
+        if (!(piv > 0.0) && ti == 0 && t == 0) atomicOr(bad, 1);
+        const double rp = 1.0 / piv;
+        const double vr[2] = {v[ra], v[ra + 1]}, vc[2] = {v[cb], v[cb + 1]};
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int w = 0; w < 2; ++w) {
+                const int r = ra + u, c = cb + w;
+                const double upd = q[u][w] - (vr[u] * vc[w]) * rp;
+                q[u][w] = r == m ? (c == m ? -rp : vc[w] * rp) : (c == m ? vr[u] * rp : upd);
+            }
+        if (m + 1 < kTB && (ra == m + 1 || ra + 1 == m + 1)) {
+            const bool lo = ra == m + 1;
+            vb[(m + 1) & 1][cb] = lo ? q[0][0] : q[1][0];
+            vb[(m + 1) & 1][cb + 1] = lo ? q[0][1] : q[1][1];
+        }
+        __syncthreads();
+    }
+    double out[2][2];
+    if (ti == k) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) out[u][v] = q[u][v];
     } else {
-        for (int e = t; e < kTB * kTB; e += kBlock) R[e / kTB][e % kTB] = P[e / kTB][e % kTB];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) Qs[ra + u][cb + v] = q[u][v];
+        __syncthreads();
+        double z[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        tile_mac(X, Qs, z);
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) out[u][v] = -z[u][v];
     }
-    __syncthreads();
-    if (blockIdx.x == 0) {
-        for (int e = t; e < kTB * kTB; e += kBlock) {
-            const int a = e / kTB, b = e % kTB;
-            const int r = k * kTB + a, col = c * kTB + b;
-            if (r < n && col < n) W[(size_t)r * n + col] = R[a][b];
-        }
-    }
-    if (i >= T0) return;
-    tile_load(P, D, n, i * kTB, k * kTB);
-    __syncthreads();
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    tile_mac<false>(P, R, acc);
+    // logical tile (ti, k): stored as is below the pivot row, transposed above it
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
-            const int r = i * kTB + ra + u, col = c * kTB + cb + v;
-            if (r < n && col < n) Acc[(size_t)r * n + col] -= acc[u][v];
-        }
-}
-
-// X = W^T W for lower-triangular W: tile (i, j), i >= j, is the sum over tile
-// rows m >= i of W_mi^T W_mj; it is stored with its mirror X_ji.
-__global__ __launch_bounds__(kBlock) void k_wtw(int n, const double *Wb, double *Xb) {
-    __shared__ Tile P, Q;
-    const double *W = bat(Wb, n);
-    double *X = bat(Xb, n);
-    const int T0 = ceil_div(n, kTB);
-    const long p = blockIdx.x;
-    long ti = (long)((sqrt(8.0 * (double)p + 1.0) - 1.0) * 0.5);
-    while (ti * (ti + 1) / 2 > p) --ti;
-    while ((ti + 1) * (ti + 2) / 2 <= p) ++ti;
-    const int i = (int)ti, j = (int)(p - ti * (ti + 1) / 2);
-    const int t = threadIdx.x, ra = (t / 16) * 2, cb = (t % 16) * 2;
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    // the next tile pair is loaded into registers while the current one is
-    // multiplied (clamped indices, zero outside the matrix, as in tile_load)
-    constexpr int PER = kTB * kTB / kBlock;
-    double pr[PER], qr[PER];
-    auto fetch = [&](int m) {
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = t + u * kBlock, a = e / kTB, b = e % kTB;
-            const int r = m * kTB + a;
-            const size_t ro = (size_t)min(r, n - 1) * n;
-            const double vp = W[ro + min(i * kTB + b, n - 1)], vq = W[ro + min(j * kTB + b, n - 1)];
-            pr[u] = (r < n && i * kTB + b < n) ? vp : 0.0;
-            qr[u] = (r < n && j * kTB + b < n) ? vq : 0.0;
-        }
-    };
-    fetch(i);
-    for (int m = i; m < T0; ++m) {
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = t + u * kBlock;
-            P[e / kTB][e % kTB] = pr[u];
-            Q[e / kTB][e % kTB] = qr[u];
-        }
-        __syncthreads();
-        if (m + 1 < T0) fetch(m + 1);
-        tile_mac<true>(P, Q, acc);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            const int r = i * kTB + ra + u, col = j * kTB + cb + v;
-            if (r < n && col < n) {
-                X[(size_t)r * n + col] = acc[u][v];
-                X[(size_t)col * n + r] = acc[u][v];
+            const int i = ti * kTB + ra + u, j = K0 + cb + v;
+            if (i < n && j < n) {
+                if (ti >= k) dst[(size_t)i * n + j] = out[u][v];
+                else dst[(size_t)j * n + i] = out[u][v];
             }
         }
+}
+
+// Every tile outside the pivot row and column of sweep k:
+// A_ij <- A_ij - A_iK' A_Kj, A_iK' (new, from k_gj_panel) in dst, A_Kj and A_ij
+// (old) in src.  Workgroup p serves the p-th lower tile of the matrix with
+// tile row and column k taken out.
+__global__ __launch_bounds__(kBlock) void k_gj_update(int n, const double *srcb, double *dstb, int k) {
+    __shared__ Tile X, Y;
+    const double *src = bat(srcb, n);
+    double *dst = bat(dstb, n);
+    int ti, tj;
+    tile_from_p(blockIdx.x, ti, tj);
+    ti += ti >= k;
+    tj += tj >= k;
+    const int t = threadIdx.x, ra = (t / 16) * 2, cb = (t % 16) * 2;
+    tile_load_lower(X, dst, n, ti, k);
+    tile_load_lower(Y, src, n, k, tj);
+    double a[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int i = ti * kTB + ra + u, j = tj * kTB + cb + v;
+            const double x = src[(size_t)min(i, n - 1) * n + min(j, n - 1)];
+            a[u][v] = (i < n && j < n) ? x : 0.0;
+        }
+    __syncthreads();
+    double z[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    tile_mac(X, Y, z);
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int i = ti * kTB + ra + u, j = tj * kTB + cb + v;
+            if (i < n && j < n) dst[(size_t)i * n + j] = a[u][v] - z[u][v];
+        }
+}
+
+// inv = -S for the fully swept S in src (lower tiles): output tile (bx, by) of
+// the whole matrix from the lower half, so that inv is exactly symmetric
+__global__ __launch_bounds__(kBlock) void k_gj_out(int n, const double *srcb, double *invb) {
+    __shared__ Tile T;
+    const double *src = bat(srcb, n);
+    double *inv = bat(invb, n);
+    const int bi = blockIdx.y, bj = blockIdx.x;
+    tile_load_lower(T, src, n, bi, bj);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kTB * kTB; e += kBlock) {
+        const int a = e / kTB, b = e % kTB, i = bi * kTB + a, j = bj * kTB + b;
+        const double v = (bi == bj && b > a) ? T[b][a] : T[a][b];
+        if (i < n && j < n) inv[(size_t)i * n + j] = -v;
+    }
 }
 
 // sliced-ELL copy of a CSR matrix, one wavefront per slice of 64 rows:
@@ -1691,14 +1581,13 @@ int gwave(long rows) {
 struct DenseJob {
     int n = 0, nb = 0;
     const DCsr *mats[2] = {nullptr, nullptr};
-    double *D = nullptr, *ld = nullptr, *lam = nullptr, *acc = nullptr, *W = nullptr, *inv = nullptr;
+    double *D = nullptr, *acc = nullptr, *inv = nullptr;
     DenseOp op[2];
     int *bad = nullptr;
 };
 
-// The launches of a dense job on stream st: densify, tiled Cholesky (factor
-// and panel per tile column, trailing update), inverses of the diagonal tiles,
-// block forward substitution for W = L^{-1}, A^{-1} = W^T W, apply copies.
+// The launches of a dense job on stream st: densify, one block Gauss-Jordan
+// sweep per pivot block, the inverse out of the swept matrix, apply copies.
 // Touches no host state but the job, so it may run on another host thread.
 void launch_dense(const DenseJob &j, hipStream_t st) {
     const int n = j.n, nb = j.nb;
@@ -1709,23 +1598,17 @@ void launch_dense(const DenseJob &j, hipStream_t st) {
             hipLaunchKernelGGL(k_densify, dim3(gwave(n)), dim3(kBlock), 0, st, n, j.mats[b]->rp, j.mats[b]->ci,
                                j.mats[b]->v, (const uint8_t *)nullptr, (const uint8_t *)nullptr, j.D + b * nn);
     }
-    for (int k0 = 0; k0 < n; k0 += kTB) {
-        const int rest = std::max(0, n - (k0 + kTB));
-        hipLaunchKernelGGL(k_potrf_panel, dim3(1 + ceil_div(rest, 64), 1, nb), dim3(64), 0, st, n, j.D, j.ld, k0,
-                           j.bad);
-        if (rest <= 0) break;
-        const int tiles = ceil_div(rest, kTB);
-        hipLaunchKernelGGL(k_syrk_tile, dim3(tiles * (tiles + 1) / 2, 1, nb), dim3(kBlock), 0, st, n, j.D, k0);
-    }
-    AMG_HIP(hipGetLastError());
+    // block Gauss-Jordan sweeps, D and acc in turn as source and destination
     const int T0 = ceil_div(n, kTB);
-    AMG_HIP(hipMemsetAsync(j.acc, 0, sizeof(double) * nb * nn, st));
-    AMG_HIP(hipMemsetAsync(j.W, 0, sizeof(double) * nb * nn, st));
-    hipLaunchKernelGGL(k_trtri_tile, dim3(T0, 1, nb), dim3(64), 0, st, n, j.ld, j.lam);
-    for (int k = 0; k < T0; ++k)
-        hipLaunchKernelGGL(k_trinv_step, dim3(std::max(1, T0 - k - 1), k + 1, nb), dim3(kBlock), 0, st, n, k, j.D,
-                           j.lam, j.acc, j.W);
-    hipLaunchKernelGGL(k_wtw, dim3(T0 * (T0 + 1) / 2, 1, nb), dim3(kBlock), 0, st, n, j.W, j.inv);
+    double *buf[2] = {j.D, j.acc};
+    for (int k = 0; k < T0; ++k) {
+        hipLaunchKernelGGL(k_gj_panel, dim3(T0, 1, nb), dim3(kBlock), 0, st, n, buf[k & 1], buf[(k + 1) & 1], k,
+                           j.bad);
+        if (T0 > 1)
+            hipLaunchKernelGGL(k_gj_update, dim3((T0 - 1) * T0 / 2, 1, nb), dim3(kBlock), 0, st, n, buf[k & 1],
+                               buf[(k + 1) & 1], k);
+    }
+    hipLaunchKernelGGL(k_gj_out, dim3(T0, T0, nb), dim3(kBlock), 0, st, n, buf[T0 & 1], j.inv);
     for (int b = 0; b < nb; ++b)
         if (j.op[b].m64)
             hipLaunchKernelGGL(k_pad_dense, dim3(gsz((long)n * j.op[b].ld)), dim3(kBlock), 0, st, n, j.op[b].ld,
@@ -1826,7 +1709,7 @@ struct Setup {
     // downstream indexes memory by the flagged values): set by kernels,
     // cleared once per phase and read at its end in one transfer.
     static constexpr int kFlag0 = 16, kFlagN = 32;
-    static constexpr int kFlagFill = 16, kFlagMirror = 17, kFlagChol = 18, kFlagMassDiag = 19, kFlagDiag = 20;
+    static constexpr int kFlagFill = 16, kFlagMirror = 17, kFlagPivot = 18, kFlagMassDiag = 19, kFlagDiag = 20;
     static constexpr int kFlagAlign = kFlag0 + kFlagN - 1;  // the level flags end before it
     static constexpr int kFlagDiagN = kFlagAlign - kFlagDiag;
     void clear_flags() { zero(c.iscratch + kFlag0, kFlagN * sizeof(int)); }
@@ -1838,7 +1721,7 @@ struct Setup {
             if (f[kFlagDiag + j]) fail(AMG_ERR_NOT_SPD, "non-positive diagonal at level " + std::to_string(j));
         if (f[kFlagAlign]) fail(AMG_ERR_ARG, "prolongator entry missing from A S");
         if (f[kFlagMassDiag]) fail(AMG_ERR_NOT_SPD, "mass matrix has a non-positive diagonal");
-        if (f[kFlagChol]) fail(AMG_ERR_NOT_SPD, "dense Cholesky met a non-positive pivot");
+        if (f[kFlagPivot]) fail(AMG_ERR_NOT_SPD, "dense inverse met a non-positive pivot");
         if (f[kFlagMirror]) fail(AMG_ERR_ARG, "coarse matrix pattern is not symmetric");
         if (f[kFlagFill]) fail(AMG_ERR_CAPACITY, "sparse product: output column lost in the fill");
     }
@@ -2324,13 +2207,9 @@ struct Setup {
     }
     void plan_rest(DenseJob &j, bool ops) {
         const size_t nn = (size_t)j.n * j.n;
-        const int T0 = ceil_div(j.n, kTB);
-        j.ld = c.arena.alloc<double>((size_t)j.nb * T0 * kTB * kTB);
-        j.lam = c.arena.alloc<double>((size_t)j.nb * T0 * kTB * kTB);
         j.acc = c.arena.alloc<double>(j.nb * nn);
-        j.W = c.arena.alloc<double>(j.nb * nn);
         j.inv = c.arena.alloc<double>(j.nb * nn);
-        j.bad = c.iscratch + kFlagChol;
+        j.bad = c.iscratch + kFlagPivot;
         if (ops)
             for (int b = 0; b < j.nb; ++b) {
                 DenseOp &d = j.op[b];
@@ -2343,7 +2222,7 @@ struct Setup {
     // the temporaries (D included) back to the arena, or to *defer when the
     // work runs on a stream that the arena's reuse does not follow
     void release_job(DenseJob &j, std::vector<void *> *defer) {
-        for (void *p : {(void *)j.D, (void *)j.ld, (void *)j.lam, (void *)j.acc, (void *)j.W}) {
+        for (void *p : {(void *)j.D, (void *)j.acc}) {
             if (defer) defer->push_back(p);
             else c.arena.release(p);
         }
@@ -2527,7 +2406,7 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
 }
 
 // Dense practical-form Hessian at level ell-1: H = X^T M_y X + beta M_u,
-// X = A^{-1} M_yu, symmetrised and inverted through its Cholesky factor
+// X = A^{-1} M_yu, symmetrised and inverted by block Gauss-Jordan sweeps
 // (Section 3.2: the coarsest Hessian level is inverted exactly).
 void form_dense_hessian(Ctx &c, int ell) {
     Setup su(c);
