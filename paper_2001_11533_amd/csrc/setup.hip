@@ -174,59 +174,71 @@ __global__ void k_a0_fill(int n, const int *rp, const int *ci, const double *v, 
     }
 }
 
-// exclusive scan, three passes: per-block sums, one-block scan of the sums, add
+// exclusive scan in two passes over blocks of kScanPer counts: the block sums,
+// then per block its offset (the sum of the block sums before it) and its part
+// of the scan by wavefront shuffles; the last block writes out[n] and *total
 constexpr int kScanPer = 1024;
-__global__ void k_scan_blocks(int n, const int *in, int *bsum) {
-    __shared__ int s[kBlock];
-    const int base = blockIdx.x * kScanPer;
+constexpr int kScanPT = kScanPer / kBlock;  // counts per thread
+__global__ __launch_bounds__(kBlock) void k_scan_blocks(int n, const int *in, int *bsum) {
+    __shared__ int ws[kBlock / 64];
+    const int t = threadIdx.x, i0 = blockIdx.x * kScanPer + t * kScanPT;
     int acc = 0;
-    for (int k = threadIdx.x; k < kScanPer; k += kBlock) {
-        const int i = base + k;
-        if (i < n) acc += in[i];
+#pragma unroll
+    for (int q = 0; q < kScanPT; ++q) {
+        const int v = in[min(i0 + q, n - 1)];  // n >= 1 here
+        acc += i0 + q < n ? v : 0;
     }
-    s[threadIdx.x] = acc;
+    acc = wave_sum(acc);
+    if ((t & 63) == 0) ws[t >> 6] = acc;
     __syncthreads();
-    for (int w = kBlock / 2; w >= 1; w >>= 1) {
-        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) bsum[blockIdx.x] = s[0];
-}
-
-__global__ void k_scan_sums(int nb, int *bsum, int *total) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        int acc = 0;
-        for (int b = 0; b < nb; ++b) {
-            const int v = bsum[b];
-            bsum[b] = acc;
-            acc += v;
-        }
-        *total = acc;
+    if (t == 0) {
+        int b = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) b += ws[w];
+        bsum[blockIdx.x] = b;
     }
 }
 
-__global__ void k_scan_final(int n, const int *in, const int *bsum, int *out, const int *total) {
-    __shared__ int s[kScanPer];
-    const int base = blockIdx.x * kScanPer;
-    for (int k = threadIdx.x; k < kScanPer; k += kBlock) {
-        const int i = base + k;
-        s[k] = i < n ? in[i] : 0;
-    }
+__global__ __launch_bounds__(kBlock) void k_scan_final(int n, int nb, const int *in, const int *bsum, int *out,
+                                                       int *total) {
+    __shared__ int ws[kBlock / 64];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    int o = 0;
+    for (int b = t; b < (int)blockIdx.x; b += kBlock) o += bsum[b];
+    o = wave_sum(o);
+    if (lane == 0) ws[w] = o;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int acc = bsum[blockIdx.x];
-        for (int k = 0; k < kScanPer; ++k) {
-            const int v = s[k];
-            s[k] = acc;
-            acc += v;
-        }
-    }
+    int off = 0;
+#pragma unroll
+    for (int q = 0; q < kBlock / 64; ++q) off += ws[q];
     __syncthreads();
-    for (int k = threadIdx.x; k < kScanPer; k += kBlock) {
-        const int i = base + k;
-        if (i < n) out[i] = s[k];
+    const int i0 = blockIdx.x * kScanPer + t * kScanPT;
+    int v[kScanPT], tsum = 0;
+#pragma unroll
+    for (int q = 0; q < kScanPT; ++q) {
+        const int x = n > 0 ? in[min(i0 + q, n - 1)] : 0;
+        v[q] = i0 + q < n ? x : 0;
+        tsum += v[q];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = *total;
+    int inc = tsum;  // inclusive scan of the thread sums over the wavefront
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(inc, d);
+        if (lane >= d) inc += y;
+    }
+    if (lane == 63) ws[w] = inc;
+    __syncthreads();
+    int run = off + inc - tsum;
+    for (int q = 0; q < w; ++q) run += ws[q];
+#pragma unroll
+    for (int q = 0; q < kScanPT; ++q) {
+        if (i0 + q < n) out[i0 + q] = run;
+        run += v[q];
+    }
+    if (blockIdx.x == nb - 1 && t == kBlock - 1) {
+        out[n] = run;
+        *total = run;
+    }
 }
 
 __global__ void k_l1(int n, const int *rp, const double *v, double *dl1inv, double *dl1) {
@@ -1731,9 +1743,8 @@ struct Setup {
     int scan(const int *cnt, int *out, int n, bool read = true) {
         const int nb = std::max(1, ceil_div(n, kScanPer));
         int *bsum = c.arena.alloc<int>(nb);
-        hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum);
-        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(64), 0, s, nb, bsum, isc + 8);
-        hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum, out, isc + 8);
+        if (n > 0) hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(kBlock), 0, s, n, cnt, bsum);
+        hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kBlock), 0, s, n, nb, cnt, bsum, out, isc + 8);
         const int total = read ? read_int(isc + 8) : -1;
         rel(bsum);
         return total;

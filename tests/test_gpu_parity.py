@@ -252,6 +252,36 @@ def test_error_paths():
     assert e.value.code == -1
 
 
+def test_indefinite_coarse_level_is_not_spd():
+    # A - sigma M with sigma = 1.5 lambda_min(M^-1 A): every diagonal entry on
+    # every level stays positive, but the dense levels (18 and 2 rows) are
+    # indefinite, so the dense inverse meets a non-positive pivot; the oracle's
+    # Cholesky factorisation of the same level fails too
+    _need_gpu()
+    import scipy.linalg as sla
+    import paper_2001_11533_amd as amg
+    from paper_2001_11533_amd import AmgError
+    from oracle import fem
+    p = inputs.config("c1", n=12)
+    rp, ci, va, vm = amg.assemble_p1(p.mesh.coords, p.mesh.elems, p.kappa)
+    n = len(rp) - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    dA, dM = np.zeros((n, n)), np.zeros((n, n))
+    dA[rows, ci], dM[rows, ci] = va, vm
+    inner = np.nonzero(p.dirichlet == 0)[0]
+    lam = sla.eigh(dA[np.ix_(inner, inner)], dM[np.ix_(inner, inner)], eigvals_only=True)[0]
+    sigma = 1.5 * lam
+    shifted = va - sigma * vm
+    assert np.all(shifted[rows == ci] > 0)
+    A0 = fem.dirichlet_stiffness(fem.CSR(rp, ci, shifted, n), p.dirichlet)
+    with pytest.raises(np.linalg.LinAlgError):
+        osa.build(A0, fem.CSR(rp, ci, vm, n), p.dirichlet, osa.Opts(max_coarse=10))
+    print(f"[parity] indefinite shift sigma={sigma:.3f}", flush=True)
+    with pytest.raises(AmgError) as e:
+        amg.HessianSolver((rp, ci, shifted), (rp, ci, vm), p.dirichlet, beta=1e-2, max_coarse=10)
+    assert e.value.code == -3 and "pivot" in str(e.value)
+
+
 def test_graph_replay_matches_eager_launches():
     # the captured CG iterations are replayed many times, with eager work and
     # host synchronisations in between; every replay must reproduce the eager
