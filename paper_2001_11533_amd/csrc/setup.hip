@@ -394,8 +394,18 @@ __global__ void k_mis_r2(int n, const int *srp, const int *sci, const uint8_t *r
         if (any) st[i] = OUT;
         else ++left;
     }
+    // the rounds need only whether nodes are left: one add per workgroup, and
+    // none once the counter is nonzero (a relaxed load instead of a contended
+    // atomic)
+    __shared__ int wl[kBlock / 64];
     left = wave_sum(left);
-    if (threadIdx.x % 64 == 0 && left) atomicAdd(undec, left);
+    if (threadIdx.x % 64 == 0) wl[threadIdx.x / 64] = left;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int b = 0;
+        for (int w = 0; w < (int)blockDim.x / 64; ++w) b += wl[w];
+        if (b && __hip_atomic_load(undec, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) atomicAdd(undec, b);
+    }
 }
 
 __global__ void k_root_flags(int n, const int8_t *st, uint8_t *root, int *cnt) {
@@ -515,6 +525,80 @@ __global__ void k_t_place(int n, const int *rp, const int *ci, const double *v, 
             tci[o] = i;
             tv[o] = v[p];
         }
+}
+
+// Ordered transpose of a matrix with at most kTbCols columns, no atomics on
+// global memory and no sort: blocks of kTbRows source rows count their
+// entries per column in LDS (hist, column-major: column J, block b at
+// J nb + b); an exclusive scan of hist gives every (column, block) its first
+// position in the transpose; each block then places its entries in row order,
+// so every row of the transpose comes out sorted by source row.
+constexpr int kTbRows = 64, kTbCols = 8192, kTbChunk = 2048;
+__global__ __launch_bounds__(kBlock) void k_tb_hist(int n, int nc, int nb, const int *rp, const int *ci,
+                                                    int *hist) {
+    __shared__ int lc[kTbCols];
+    for (int J = threadIdx.x; J < nc; J += kBlock) lc[J] = 0;
+    __syncthreads();
+    static_assert(kTbRows * 4 == kBlock, "four lanes per row");
+    const int i = blockIdx.x * kTbRows + threadIdx.x / 4;
+    if (i < n)
+        for (int p = rp[i] + threadIdx.x % 4; p < rp[i + 1]; p += 4) atomicAdd(&lc[ci[p]], 1);
+    __syncthreads();
+    for (int J = threadIdx.x; J < nc; J += kBlock) hist[(size_t)J * nb + blockIdx.x] = lc[J];
+}
+
+// pos: the scan of hist (pos[nc nb] = the total); block 0 also writes the
+// transpose's row pointers trp[J] = pos[J nb].  Per chunk of the block's
+// entries: columns staged in LDS, one wavefront hands out the positions row
+// by row (the entries of a row have distinct columns, so its lanes never share
+// a counter), then all threads write the entries.
+__global__ __launch_bounds__(kBlock) void k_tb_place(int n, int nc, int nb, const int *rp, const int *ci,
+                                                     const double *v, const int *pos, int *trp, int *tci,
+                                                     double *tv) {
+    __shared__ int lc[kTbCols];
+    __shared__ int rps[kTbRows + 1];
+    __shared__ int cj[kTbChunk], op[kTbChunk];
+    const int t = threadIdx.x;
+    for (int J = t; J < nc; J += kBlock) lc[J] = pos[(size_t)J * nb + blockIdx.x];
+    if (blockIdx.x == 0)
+        for (int J = t; J <= nc; J += kBlock) trp[J] = pos[(size_t)J * nb];
+    const int r0 = blockIdx.x * kTbRows, nr = min(n, r0 + kTbRows) - r0;
+    for (int q = t; q <= nr; q += kBlock) rps[q] = rp[r0 + q];
+    __syncthreads();
+    const int e0 = rps[0], e1 = rps[nr];
+    for (int c0 = e0; c0 < e1; c0 += kTbChunk) {
+        const int c1 = min(e1, c0 + kTbChunk);
+        for (int p = c0 + t; p < c1; p += kBlock) cj[p - c0] = ci[p];
+        __syncthreads();
+        if (t < 64) {
+            for (int r = 0; r < nr; ++r) {
+                const int a = max(rps[r], c0), z = min(rps[r + 1], c1);
+                for (int p0 = a; p0 < z; p0 += 64) {
+                    const int p = p0 + t;
+                    if (p < z) {
+                        const int J = cj[p - c0];
+                        const int o = lc[J];
+                        lc[J] = o + 1;
+                        op[p - c0] = o;
+                    }
+                    wave_sync();
+                }
+            }
+        }
+        __syncthreads();
+        for (int p = c0 + t; p < c1; p += kBlock) {
+            int lo = 0, hi = nr;  // the row of entry p: rps[lo] <= p < rps[lo + 1]
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) / 2;
+                if (rps[mid] <= p) lo = mid;
+                else hi = mid;
+            }
+            const int o = op[p - c0];
+            tci[o] = r0 + lo;
+            tv[o] = v[p];
+        }
+        __syncthreads();
+    }
 }
 
 // rows of the transpose: rank sort by column index, one wavefront per row
@@ -1963,13 +2047,29 @@ struct Setup {
         T.n = A.m;
         T.m = A.n;
         T.nnz = A.nnz;
+        T.rp = c.arena.alloc<int>(T.n + 1);
+        T.ci = c.arena.alloc<int>(T.nnz);
+        T.v = c.arena.alloc<double>(T.nnz);
+        if (T.n <= kTbCols && A.n > 0) {
+            const int nb = ceil_div(A.n, kTbRows);
+            const long len = (long)T.n * nb;
+            if (len < (long)INT_MAX) {
+                int *hist = c.arena.alloc<int>(len);
+                int *pos = c.arena.alloc<int>(len + 1);
+                hipLaunchKernelGGL(k_tb_hist, dim3(nb), dim3(kBlock), 0, s, A.n, T.n, nb, A.rp, A.ci, hist);
+                scan(hist, pos, (int)len, false);  // the total is A.nnz
+                hipLaunchKernelGGL(k_tb_place, dim3(nb), dim3(kBlock), 0, s, A.n, T.n, nb, A.rp, A.ci, A.v, pos,
+                                   T.rp, T.ci, T.v);
+                check_kernels();
+                c.arena.release(hist);
+                c.arena.release(pos);
+                return T;
+            }
+        }
         int *cnt = c.arena.alloc<int>(T.n + 1);
         int *fill = c.arena.alloc<int>(T.n + 1);
         zero(cnt, sizeof(int) * (T.n + 1));
         zero(fill, sizeof(int) * (T.n + 1));
-        T.rp = c.arena.alloc<int>(T.n + 1);
-        T.ci = c.arena.alloc<int>(T.nnz);
-        T.v = c.arena.alloc<double>(T.nnz);
         int *tci = c.arena.alloc<int>(T.nnz);
         double *tv = c.arena.alloc<double>(T.nnz);
         hipLaunchKernelGGL(k_t_count, dim3(gsz(A.n)), dim3(kBlock), 0, s, A.n, A.rp, A.ci, cnt);
@@ -2060,8 +2160,9 @@ struct Setup {
         int *m1 = c.arena.alloc<int>(n);
         uint8_t *r1 = c.arena.alloc<uint8_t>(n);
         hipLaunchKernelGGL(k_mis_init, dim3(gsz(n)), dim3(kBlock), 0, s, n, mask, st);
-        // rounds in batches with one read of the undecided count per batch;
-        // round r counts into und[r % kMisRing] (the ring holds whole batches)
+        // rounds in batches with one read of the undecided flag per batch;
+        // round r leaves a nonzero und[r % kMisRing] while nodes are undecided
+        // (the ring holds whole batches)
         constexpr int kMisRing = 64, kMisBatch = 4;
         static_assert(kMisRing % kMisBatch == 0, "a batch must not wrap the ring");
         int *und = c.arena.alloc<int>(kMisRing);
