@@ -79,7 +79,7 @@ typedef struct {
     double theta0;          /* strength threshold at level 0, halved per level (0.08) */
     uint64_t agg_seed;      /* seed of the aggregation priority hash */
     int32_t nu;             /* l1-Jacobi sweeps before and after the coarse correction (1) */
-    double inner_rtol;      /* A-solves inside K and K^T (1e-10) */
+    double inner_rtol;      /* A-solves inside K and K^T (1e-8, Section 5.3) */
     double mass_rtol;       /* mass-matrix solves, all inside the preconditioner (1e-8, Section 5.3) */
     double precond_inner_rtol; /* A-solves inside the preconditioner's H_j (1e-8, Section 5.3) */
     int32_t inner_maxit, mass_maxit, outer_maxit; /* 500, 500, 200 */

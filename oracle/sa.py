@@ -243,7 +243,7 @@ class Opts:
     agg_seed: int = 0x200111533
     nu: int = 1
     smoother: int = 0               # 0 = l1-Jacobi, 1 = Chebyshev of degree 2 (pre and post)
-    inner_rtol: float = 1e-10
+    inner_rtol: float = 1e-8        # the A-solves that apply K and K* (Section 5.3)
     mass_rtol: float = 1e-8          # the paper's mass-solve tolerance (Section 5.3)
     precond_inner_rtol: float = 1e-8 # A-solves inside the preconditioner's H_j, as the paper's inner solves
     inner_maxit: int = 500

@@ -498,7 +498,7 @@ int amg_opts_default(amg_opts *o) {
     o->theta0 = 0.08;
     o->agg_seed = 0x200111533ull;
     o->nu = 1;
-    o->inner_rtol = 1e-10;
+    o->inner_rtol = 1e-8;
     o->mass_rtol = 1e-8;
     o->precond_inner_rtol = 1e-8;
     o->inner_maxit = 500;

@@ -140,7 +140,8 @@ def test_reduced_solve(name, n, mc):
 
 
 def test_reduced_solve_tiny_against_dense():
-    p, g, o = make("c1", 10, max_coarse=20)
+    # inner solves far below the comparison tolerance: the dense Hessian is exact
+    p, g, o = make("c1", 10, max_coarse=20, **TIGHT)
     yd = p.yd[:, 0]
     u, info = g.reduced_solve(cuda(yd), rtol=1e-11)
     H = odense.hessian_practical(o.h)
@@ -168,8 +169,9 @@ def test_mixed_precision_solve(mode):
 @pytest.mark.parametrize("prec", [64, 32])
 def test_chebyshev_smoother_solve(prec):
     # the V-cycle with the degree-2 Chebyshev smoother: same solution as the
-    # oracle with the same smoother, and the same inner iteration counts
-    p, g, o = make("c3", 16, smoother=1, inner_precision=prec)
+    # oracle with the same smoother, and the same inner iteration counts (the
+    # FP64 case compares at 1e-10: K and K* applied with inner solves to 1e-10)
+    p, g, o = make("c3", 16, smoother=1, inner_precision=prec, inner_rtol=1e-10 if prec == 64 else 1e-8)
     yd = p.yd[:, 0]
     u, info = g.reduced_solve(cuda(yd), rtol=1e-10 if prec == 64 else 1e-8)
     uo, _ = osolve.Oracle(o.h).reduced_solve(yd, rtol=1e-12)

@@ -42,7 +42,7 @@ def test_opts_defaults():
     L = _lib()
     o = L.Opts()
     assert L.lib().amg_opts_default(C.byref(o)) == 0
-    assert o.max_coarse == 200 and o.inner_rtol == 1e-10 and o.nu == 1 and o.precond == 1
+    assert o.max_coarse == 200 and o.inner_rtol == 1e-8 and o.nu == 1 and o.precond == 1
     assert L.lib().amg_opts_default(None) == -1
 
 
