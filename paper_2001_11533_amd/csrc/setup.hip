@@ -1440,39 +1440,23 @@ __device__ __forceinline__ void tile_from_p(long p, int &ti, int &tj) {
     tj = (int)(p - i * (i + 1) / 2);
 }
 
-// Pivot block column of sweep k: workgroup i (one per tile row) sweeps the
-// pivot block itself, pivot by pivot in registers, the pivot row broadcast
-// through LDS (symmetric products, so Q stays exactly symmetric), while A_iK
-// is loading; then tile row k gets Q and any other one -A_iK Q.
-__global__ __launch_bounds__(kBlock) void k_gj_panel(int n, const double *srcb, double *dstb, int k, int *bad) {
-    __shared__ Tile X, Qs;
-    __shared__ double vb[2][kTB];
-    const double *src = bat(srcb, n);
-    double *dst = bat(dstb, n);
-    const int ti = blockIdx.x;
+// Scalar sweeps of a kTB x kTB block held 2 x 2 per thread in q (rows ra, ra+1,
+// columns cb, cb+1; exactly symmetric on entry): a_mm <- -1/a_mm,
+// a_rm <- a_rm/a_mm, a_rc <- a_rc - a_rm a_mc/a_mm, pivot by pivot, the pivot
+// row broadcast through vb in LDS; symmetric products keep the block exactly
+// symmetric.  Leaves -block^{-1} in q; a non-positive pivot sets *bad when
+// report.  Every thread of the workgroup takes part.
+__device__ __forceinline__ void sweep_block(double (&q)[2][2], double (&vb)[2][kTB], int *bad, bool report) {
     const int t = threadIdx.x, ra = (t / 16) * 2, cb = (t % 16) * 2;
-    const int K0 = k * kTB;
-    // this thread's 2 x 2 of the pivot block, from its lower half
-    double q[2][2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) {
-            const int r = ra + u, c = cb + v, i = K0 + max(r, c), j = K0 + min(r, c);
-            const double x = src[(size_t)min(i, n - 1) * n + min(j, n - 1)];
-            q[u][v] = i < n ? x : (r == c ? 1.0 : 0.0);
-        }
-    if (ti != k) tile_load_lower(X, src, n, ti, k);
     if (ra == 0) {
         vb[0][cb] = q[0][0];
         vb[0][cb + 1] = q[0][1];
     }
     __syncthreads();
-    // scalar sweeps: a_mm <- -1/a_mm, a_rm <- a_rm/a_mm, a_rc <- a_rc - a_rm a_mc/a_mm
     for (int m = 0; m < kTB; ++m) {
         const double *v = vb[m & 1];
         const double piv = v[m];
-        if (!(piv > 0.0) && ti == 0 && t == 0) atomicOr(bad, 1);
+        if (!(piv > 0.0) && report && t == 0) atomicOr(bad, 1);
         const double rp = 1.0 / piv;
         const double vr[2] = {v[ra], v[ra + 1]}, vc[2] = {v[cb], v[cb + 1]};
 #pragma unroll
@@ -1490,6 +1474,41 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel(int n, const double *srcb, 
         }
         __syncthreads();
     }
+}
+
+// Pivot block column of sweep k: Q = -(A_KK)^{-1} from qin (swept by the
+// previous update launch) or, for the first pivot block (qin null), swept by
+// every workgroup itself while A_iK is loading; then tile row k gets Q and any
+// other one -A_iK Q.  One workgroup per tile row.
+__global__ __launch_bounds__(kBlock) void k_gj_panel(int n, const double *srcb, double *dstb, int k,
+                                                     const double *qin, int *bad) {
+    __shared__ Tile X, Qs;
+    __shared__ double vb[2][kTB];
+    const double *src = bat(srcb, n);
+    double *dst = bat(dstb, n);
+    const int ti = blockIdx.x;
+    const int t = threadIdx.x, ra = (t / 16) * 2, cb = (t % 16) * 2;
+    const int K0 = k * kTB;
+    double q[2][2];
+    if (qin) {
+        const double *qz = qin + (size_t)blockIdx.z * kTB * kTB;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) q[u][v] = qz[(ra + u) * kTB + cb + v];
+    } else {
+        // this thread's 2 x 2 of the pivot block, from its lower half
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                const int r = ra + u, c = cb + v, i = K0 + max(r, c), j = K0 + min(r, c);
+                const double x = src[(size_t)min(i, n - 1) * n + min(j, n - 1)];
+                q[u][v] = i < n ? x : (r == c ? 1.0 : 0.0);
+            }
+    }
+    if (ti != k) tile_load_lower(X, src, n, ti, k);
+    if (!qin) sweep_block(q, vb, bad, ti == 0);
     double out[2][2];
     if (ti == k) {
 #pragma unroll
@@ -1525,13 +1544,23 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel(int n, const double *srcb, 
 // Every tile outside the pivot row and column of sweep k:
 // A_ij <- A_ij - A_iK' A_Kj, A_iK' (new, from k_gj_panel) in dst, A_Kj and A_ij
 // (old) in src.  Workgroup p serves the p-th lower tile of the matrix with
-// tile row and column k taken out.
-__global__ __launch_bounds__(kBlock) void k_gj_update(int n, const double *srcb, double *dstb, int k) {
+// tile row and column k taken out, except that workgroup 0 (dispatched first)
+// takes the next pivot block, tile (k + 1, k + 1): it also sweeps its new value
+// (symmetric from the lower half, identity on a ragged block's padding) into
+// qout for the next panel launch.
+__global__ __launch_bounds__(kBlock) void k_gj_update(int n, const double *srcb, double *dstb, int k,
+                                                      double *qout, int *bad) {
     __shared__ Tile X, Y;
+    __shared__ double vb[2][kTB];
     const double *src = bat(srcb, n);
     double *dst = bat(dstb, n);
+    const int T0 = (n + kTB - 1) / kTB;
+    const long pd = (long)k * (k + 1) / 2 + k;  // tile (k + 1, k + 1) in the reduced numbering
+    const bool next = k + 1 < T0;
+    long p = blockIdx.x;
+    if (next) p = p == 0 ? pd : (p == pd ? 0 : p);
     int ti, tj;
-    tile_from_p(blockIdx.x, ti, tj);
+    tile_from_p(p, ti, tj);
     ti += ti >= k;
     tj += tj >= k;
     const int t = threadIdx.x, ra = (t / 16) * 2, cb = (t % 16) * 2;
@@ -1554,8 +1583,31 @@ __global__ __launch_bounds__(kBlock) void k_gj_update(int n, const double *srcb,
 #pragma unroll
         for (int v = 0; v < 2; ++v) {
             const int i = ti * kTB + ra + u, j = tj * kTB + cb + v;
-            if (i < n && j < n) dst[(size_t)i * n + j] = a[u][v] - z[u][v];
+            a[u][v] -= z[u][v];
+            if (i < n && j < n) dst[(size_t)i * n + j] = a[u][v];
         }
+    if (!(next && blockIdx.x == 0)) return;  // uniform per workgroup
+    __syncthreads();  // every thread is done reading X
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) X[ra + u][cb + v] = a[u][v];
+    __syncthreads();
+    const int D0 = (k + 1) * kTB;
+    double q[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            const int r = ra + u, c = cb + v;
+            q[u][v] = D0 + max(r, c) < n ? X[max(r, c)][min(r, c)] : (r == c ? 1.0 : 0.0);
+        }
+    sweep_block(q, vb, bad, true);
+    double *qz = qout + (size_t)blockIdx.z * kTB * kTB;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) qz[(ra + u) * kTB + cb + v] = q[u][v];
 }
 
 // inv = -S for the fully swept S in src (lower tiles): output tile (bx, by) of
@@ -1678,6 +1730,7 @@ struct DenseJob {
     int n = 0, nb = 0;
     const DCsr *mats[2] = {nullptr, nullptr};
     double *D = nullptr, *acc = nullptr, *inv = nullptr;
+    double *qb = nullptr;  // the next pivot block's -A_KK^{-1}, per matrix
     DenseOp op[2];
     int *bad = nullptr;
 };
@@ -1699,10 +1752,10 @@ void launch_dense(const DenseJob &j, hipStream_t st) {
     double *buf[2] = {j.D, j.acc};
     for (int k = 0; k < T0; ++k) {
         hipLaunchKernelGGL(k_gj_panel, dim3(T0, 1, nb), dim3(kBlock), 0, st, n, buf[k & 1], buf[(k + 1) & 1], k,
-                           j.bad);
+                           k > 0 ? (const double *)j.qb : nullptr, j.bad);
         if (T0 > 1)
             hipLaunchKernelGGL(k_gj_update, dim3((T0 - 1) * T0 / 2, 1, nb), dim3(kBlock), 0, st, n, buf[k & 1],
-                               buf[(k + 1) & 1], k);
+                               buf[(k + 1) & 1], k, j.qb, j.bad);
     }
     hipLaunchKernelGGL(k_gj_out, dim3(T0, T0, nb), dim3(kBlock), 0, st, n, buf[T0 & 1], j.inv);
     for (int b = 0; b < nb; ++b)
@@ -2320,6 +2373,7 @@ struct Setup {
     void plan_rest(DenseJob &j, bool ops) {
         const size_t nn = (size_t)j.n * j.n;
         j.acc = c.arena.alloc<double>(j.nb * nn);
+        j.qb = c.arena.alloc<double>((size_t)j.nb * kTB * kTB);
         j.inv = c.arena.alloc<double>(j.nb * nn);
         j.bad = c.iscratch + kFlagPivot;
         if (ops)
@@ -2334,7 +2388,7 @@ struct Setup {
     // the temporaries (D included) back to the arena, or to *defer when the
     // work runs on a stream that the arena's reuse does not follow
     void release_job(DenseJob &j, std::vector<void *> *defer) {
-        for (void *p : {(void *)j.D, (void *)j.acc}) {
+        for (void *p : {(void *)j.D, (void *)j.acc, (void *)j.qb}) {
             if (defer) defer->push_back(p);
             else c.arena.release(p);
         }
