@@ -106,10 +106,13 @@ def assemble(coords: np.ndarray, elems: np.ndarray, kappa: np.ndarray):
 def dirichlet_stiffness(A: CSR, dirichlet: np.ndarray) -> CSR:
     """A_0 = D A D + (I - D), D = diag(1 - dirichlet): Dirichlet rows and
     columns are removed from the pattern and the Dirichlet diagonal is 1.
-    This is the state space Y in H^1_0 of Section 2 written on all nodes."""
+    This is the state space Y in H^1_0 of Section 2 written on all nodes.
+    Stored zeros of A are not entries of A_0: an off-diagonal entry is kept
+    only when it is nonzero (on the uniform meshes the diagonal edges of the
+    triangles and of the cubes' tetrahedra carry exactly zero stiffness)."""
     bc = dirichlet.astype(bool)
     r = A.rows()
-    keep = ~bc[r] & ~bc[A.col]
+    keep = ~bc[r] & ~bc[A.col] & ((A.val != 0.0) | (r == A.col))
     rr = np.concatenate([r[keep], np.nonzero(bc)[0]])
     cc = np.concatenate([A.col[keep], np.nonzero(bc)[0]])
     vv = np.concatenate([A.val[keep], np.ones(int(bc.sum()))])

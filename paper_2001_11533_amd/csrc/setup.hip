@@ -128,12 +128,18 @@ __global__ void k_diag(int n, const int *rp, const int *ci, const double *v, con
     }
 }
 
-// A_0 = D A D + (I - D): Dirichlet rows and columns leave the pattern, the
-// Dirichlet diagonal is one.
-__global__ void k_a0_count(int n, const int *rp, const int *ci, const uint8_t *mask, int *cnt) {
+// A_0 = D A D + (I - D) (D = diag(1 - mask), mask null: D = I): Dirichlet rows
+// and columns leave the pattern, the Dirichlet diagonal is one, and A's stored
+// zeros are dropped (an off-diagonal entry stays only when it is nonzero, the
+// diagonal always); counts, then the fill.
+__device__ __forceinline__ bool a0_keep(int i, int k, double v, const uint8_t *mask) {
+    return !(mask && mask[k]) && (v != 0.0 || k == i);
+}
+
+__global__ void k_a0_count(int n, const int *rp, const int *ci, const double *v, const uint8_t *mask, int *cnt) {
     const int gl = row_lane();
     for (int i = row_first(); i < n; i += row_stride()) {
-        if (mask[i]) {
+        if (mask && mask[i]) {
             if (gl == 0) cnt[i] = 1;
             continue;
         }
@@ -141,7 +147,7 @@ __global__ void k_a0_count(int n, const int *rp, const int *ci, const uint8_t *m
         const int e = rp[i + 1];
         for (int p0 = rp[i]; p0 < e; p0 += kRowLanes) {
             const int p = p0 + gl;
-            c += __popc(group_bits(p < e && !mask[ci[p]]));
+            c += __popc(group_bits(p < e && a0_keep(i, ci[p], v[p], mask)));
         }
         if (gl == 0) cnt[i] = c;
     }
@@ -152,7 +158,7 @@ __global__ void k_a0_fill(int n, const int *rp, const int *ci, const double *v, 
     const int gl = row_lane();
     for (int i = row_first(); i < n; i += row_stride()) {
         int o = rp0[i];
-        if (mask[i]) {
+        if (mask && mask[i]) {
             if (gl == 0) {
                 ci0[o] = i;
                 v0[o] = 1.0;
@@ -162,7 +168,7 @@ __global__ void k_a0_fill(int n, const int *rp, const int *ci, const double *v, 
         const int e = rp[i + 1];
         for (int p0 = rp[i]; p0 < e; p0 += kRowLanes) {
             const int p = p0 + gl;
-            const bool keep = p < e && !mask[ci[p]];
+            const bool keep = p < e && a0_keep(i, ci[p], v[p], mask);
             const unsigned b = group_bits(keep);
             if (keep) {
                 const int r = __popc(b & lanes_below());
@@ -2433,11 +2439,17 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
         AMG_HIP(hipMemcpyAsync(c.mask0, dirichlet, N, hipMemcpyDefault, s));
         c.has_mask = true;
         l0.mask = c.mask0;
+    }
+    {
+        // the Dirichlet reduction, which also drops A's stored zeros (on the
+        // uniform meshes every diagonal edge of a cube's tetrahedra carries
+        // exactly zero stiffness: half of the stored entries)
         DCsr A0;
         A0.n = A0.m = N;
         int *cnt = c.arena.alloc<int>(N + 1);
         A0.rp = c.arena.alloc<int>(N + 1);
-        hipLaunchKernelGGL(k_a0_count, dim3(gsz((long)(N) * kRowLanes)), dim3(kBlock), 0, s, N, A.rp, A.ci, c.mask0, cnt);
+        hipLaunchKernelGGL(k_a0_count, dim3(gsz((long)(N) * kRowLanes)), dim3(kBlock), 0, s, N, A.rp, A.ci, A.v,
+                           c.mask0, cnt);
         A0.nnz = su.scan(cnt, A0.rp, N);
         A0.ci = c.arena.alloc<int>(A0.nnz);
         A0.v = c.arena.alloc<double>(A0.nnz);
@@ -2449,8 +2461,6 @@ void build_hierarchy(Ctx &c, const amg_csr &Ain, const amg_csr &Min, const uint8
         c.arena.release(A.ci);
         c.arena.release(A.v);
         l0.A = A0;
-    } else {
-        l0.A = A;
     }
     c.lev.clear();
     c.lev.push_back(l0);

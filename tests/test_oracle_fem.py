@@ -127,11 +127,23 @@ def test_element_matrices_against_independent_formulas(dim):
 
 
 def test_dirichlet_stiffness_pattern_counts():
-    # nnz of the Dirichlet-reduced stiffness of the 32x32 and 64^3 workloads
+    # nnz of the Dirichlet-reduced stiffness.  On the uniform meshes the diagonal
+    # edges carry exactly zero stiffness (right triangles: the edge opposite the
+    # right angle; the cubes' tetrahedra likewise), and A_0 keeps no stored
+    # zeros: interior rows hold the 5-point (2D) and 7-point (3D) stencils, minus
+    # the couplings to Dirichlet nodes, plus one diagonal per Dirichlet node;
+    # the mass matrix keeps the full pattern
     m = inputs.mesh2d(32)
     A, M = fem.assemble(m.coords, m.elems, inputs.kappa_const(m))
     A0 = fem.dirichlet_stiffness(A, m.boundary.astype(bool))
-    assert (m.nverts, M.nnz, A0.nnz) == (1089, 7361, 6609)
+    ni = 31
+    assert (m.nverts, M.nnz, A0.nnz) == (1089, 7361, ni * ni * 5 - 4 * ni + (1089 - ni * ni))
+    m3 = inputs.mesh3d(8)
+    A3, M3 = fem.assemble(m3.coords, m3.elems, inputs.kappa_lognormal(m3, 1.0))
+    A30 = fem.dirichlet_stiffness(A3, m3.boundary.astype(bool))
+    ni = 7
+    assert A30.nnz == ni ** 3 * 7 - 6 * ni ** 2 + (m3.nverts - ni ** 3)
+    assert A3.nnz == M3.nnz > A30.nnz
     bc = np.nonzero(m.boundary)[0]
     for d in bc[:5]:
         s, e = A0.rowptr[d], A0.rowptr[d + 1]
