@@ -41,10 +41,10 @@ HBM_PEAK_GBS = 8000.0
 
 # The kernel with the largest summed device time inside the headline solves,
 # read from the kernel trace of this benchmark's headline steps
-# (profiles/solve_c3_kernel_trace.txt): the level-0 float32 coarse correction
-# fused with the first post-smoothing step (tpro_kernel, amg_time_kernel entry
-# 3), just ahead of the level-0 product of the FP64 inner CG (entry 4).
-DOMINANT = "tpro"
+# (profiles/solve_c3_kernel_trace.txt): the level-0 product of the FP64 inner
+# CG (amg_time_kernel entry 4), ahead of the level-0 float32 coarse correction
+# fused with the first post-smoothing step (tpro_kernel, entry 3).
+DOMINANT = "cg_product"
 
 
 def log(*a):
@@ -67,14 +67,15 @@ def counter_traffic(name):
     """HBM bytes per launch of a timed kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE runs (means over its timing loop's launches), scaled
     by the same counters' reading of a plain 256 MiB copy; None once the kernel
-    sources have changed since."""
+    sources (the kernels, their launches, or the setup that lays out their
+    data) have changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"{name}_hbm_counters.json")
     if not os.path.exists(path):
         return None
     m = json.load(open(path))
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "solver.hpp"):
+    for f in ("kernels.hpp", "solver.hpp", "setup.hip"):
         h.update(open(os.path.join(ROOT, "paper_2001_11533_amd", "csrc", f), "rb").read())
     if h.hexdigest() != m.get("sources_sha256"):
         return None
