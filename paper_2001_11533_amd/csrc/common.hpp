@@ -188,6 +188,7 @@ struct DCsr {
     // copy exists only when every slice spans fewer than 65536 columns), and the
     // rows of a slice are padded to its longest with (offset 0, value 0)
     int nsl = 0;
+    bool sl_over8 = true;   // some slice is wider than 8 entries per row
     int *sl_off = nullptr;  // [nsl + 1]
     int *sl_base = nullptr; // [nsl]
     uint16_t *sl_cd = nullptr;

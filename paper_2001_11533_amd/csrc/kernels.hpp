@@ -484,11 +484,12 @@ __global__ __launch_bounds__(kBlock) void spmv_kernel(int nrows, const int *__re
 }
 
 // The same product over the sliced-ELL copy (single column): one wavefront
-// per slice of 64 rows, one lane per row; a lane issues the loads of up to 16
-// entries of its row at once, with no dependence on row pointers.  Columns are
+// per slice of 64 rows, one lane per row; a lane issues the loads of up to U
+// entries of its row at once, with no dependence on row pointers (U = 8 when
+// no slice is wider, as for 5- and 7-point rows, else 16).  Columns are
 // 16-bit offsets from the slice's base column (6 bytes per float32 entry).
 // xrot rotates the XCD-contiguous block ranges by xrot XCDs (0 in solves).
-template <typename T, int NV, class GX, class EP, class PRO = NoPro>
+template <typename T, int NV, class GX, class EP, class PRO = NoPro, int U = 16>
 __global__ __launch_bounds__(kBlock) void sell_kernel(int nrows, int nsl, const int *__restrict__ soff,
                                                       const int *__restrict__ sbase,
                                                       const uint16_t *__restrict__ cd, const T *__restrict__ av, GX gx,
@@ -512,7 +513,6 @@ __global__ __launch_bounds__(kBlock) void sell_kernel(int nrows, int nsl, const 
     double acc[NVA];
 #pragma unroll
     for (int v = 0; v < NVA; ++v) acc[v] = 0.0;
-    constexpr int U = 16;
     for (int sl = s0 + wv; sl < s1; sl += WPB) {
         const int row = sl * 64 + lane;
         const bool live = row < nrows;

@@ -1635,8 +1635,11 @@ __global__ __launch_bounds__(kBlock) void k_gj_out(int n, const double *srcb, do
 // sliced-ELL copy of a CSR matrix, one wavefront per slice of 64 rows:
 // widths (64 x the longest row of the slice), then the column-major fill
 // per slice of 64 rows: 64 x the longest row, the smallest column (rows are
-// sorted) and a flag when the slice spans 65536 columns or more
-__global__ void k_sell_width(int n, int nsl, const int *rp, const int *ci, int *cnt, int *base, int *wide) {
+// sorted), a flag when the slice spans 65536 columns or more and one when its
+// longest row has more than 8 entries (plain stores of 1: no atomics queue on
+// the one address)
+__global__ void k_sell_width(int n, int nsl, const int *rp, const int *ci, int *cnt, int *base, int *wide,
+                             int *over8) {
     const int lane = threadIdx.x % 64;
     const int w = (blockIdx.x * blockDim.x + threadIdx.x) / 64, nw = gridDim.x * blockDim.x / 64;
     for (int sl = w; sl < nsl; sl += nw) {
@@ -1653,6 +1656,7 @@ __global__ void k_sell_width(int n, int nsl, const int *rp, const int *ci, int *
             cnt[sl] = len * 64;
             base[sl] = hi >= lo ? lo : 0;
             if (hi >= lo && hi - lo > 65535) *wide = 1;
+            if (len > 8) *over8 = 1;
         }
     }
 }
@@ -2317,12 +2321,13 @@ struct Setup {
         int *cnt = c.arena.alloc<int>(nsl + 1);
         int *off = c.arena.alloc<int>(nsl + 1);
         int *base = c.arena.alloc<int>(nsl);
-        zero(isc + 13, sizeof(int));
+        zero(isc + 13, 2 * sizeof(int));
         hipLaunchKernelGGL(k_sell_width, dim3(gwave(nsl)), dim3(kBlock), 0, s, A.n, nsl, A.rp, A.ci, cnt, base,
-                           isc + 13);
+                           isc + 13, isc + 14);
         scan(cnt, off, nsl, false);
-        // the total (isc[8]) and the wide-slice flag (isc[13]) in one read
-        AMG_HIP(hipMemcpyAsync(hisc + 8, isc + 8, 6 * sizeof(int), hipMemcpyDeviceToHost, s));
+        // the total (isc[8]) and the flags of a wide slice (isc[13]) and of a
+        // slice wider than 8 entries (isc[14]) in one read
+        AMG_HIP(hipMemcpyAsync(hisc + 8, isc + 8, 7 * sizeof(int), hipMemcpyDeviceToHost, s));
         AMG_HIP(hipStreamSynchronize(s));
         const int tot = hisc[8];
         c.arena.release(cnt);
@@ -2333,6 +2338,7 @@ struct Setup {
         }
         A.sl_off = off;
         A.sl_base = base;
+        A.sl_over8 = hisc[14] != 0;
         A.sl_cd = c.arena.alloc<uint16_t>(tot);
         A.sl_v = c.arena.alloc<double>(tot);
         hipLaunchKernelGGL(k_sell_fill, dim3(gwave(nsl)), dim3(kBlock), 0, s, A.n, nsl, A.rp, A.ci, A.v, A.sl_off,

@@ -90,8 +90,12 @@ template <int NB> struct Solver {
                 const int g = grid_rows(A.nsl, kBlock / 64, NV > 0 ? red_grid_max<NB>() : kMaxGridPlain);
                 Reducer<(NV > 0 ? NV : 1), NB> red{part[pbuf]};
                 if (NV > 0) pgrid[pbuf] = g;
-                hipLaunchKernelGGL((sell_kernel<T, NV, GX, EP, PRO>), dim3(g), dim3(kBlock), 0, s, A.n, A.nsl,
-                                   A.sl_off, A.sl_base, A.sl_cd, sv, gx, ep, red, stop, pro, xrot);
+                if (!A.sl_over8)
+                    hipLaunchKernelGGL((sell_kernel<T, NV, GX, EP, PRO, 8>), dim3(g), dim3(kBlock), 0, s, A.n,
+                                       A.nsl, A.sl_off, A.sl_base, A.sl_cd, sv, gx, ep, red, stop, pro, xrot);
+                else
+                    hipLaunchKernelGGL((sell_kernel<T, NV, GX, EP, PRO, 16>), dim3(g), dim3(kBlock), 0, s, A.n,
+                                       A.nsl, A.sl_off, A.sl_base, A.sl_cd, sv, gx, ep, red, stop, pro, xrot);
                 finish<NV>(pbuf, fin, stop);
                 return;
             }
