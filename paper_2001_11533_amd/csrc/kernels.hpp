@@ -368,14 +368,54 @@ template <int NB, bool JAC> struct FinFusedTail {
     __device__ void operator()(double (&rr)[1][NB], double (&rz)[1][NB]) const { step(rr[0], rz[0]); }
 };
 
+// Finalize functors that keep their CG's scalars in a member sc (CgScal *)
+// run on a copy of them in LDS: the workgroup loads the block at once and
+// writes it back after the step, so thread 0's loop over the columns makes
+// no chain of dependent global loads (one per column and field before).
+template <class F, class = void> struct fin_has_sc : std::false_type {};
+template <class F>
+struct fin_has_sc<F, std::void_t<decltype(std::declval<F &>().sc)>>
+    : std::is_same<decltype(std::declval<F &>().sc), CgScal *> {};
+
+constexpr int kScWords = (int)(sizeof(CgScal) / sizeof(unsigned long long));
+static_assert(sizeof(CgScal) % sizeof(unsigned long long) == 0, "CgScal is copied in 8-byte words");
+
+__device__ __forceinline__ unsigned long long sc_stage_load(const CgScal *sc) {
+    const int t = threadIdx.x;
+    return t < kScWords ? reinterpret_cast<const unsigned long long *>(sc)[t] : 0ull;
+}
+
+// the step on the LDS copy (loaded by sc_stage_load before the partial sums,
+// so both loads are in flight together), then the copy back
+template <class FIN, class STEP>
+__device__ __forceinline__ void fin_staged(const FIN &fin, unsigned long long w, STEP step) {
+    __shared__ CgScal lsc;
+    const int t = threadIdx.x;
+    if (t < kScWords) reinterpret_cast<unsigned long long *>(&lsc)[t] = w;
+    __syncthreads();
+    if (t == 0) {
+        FIN f = fin;
+        f.sc = &lsc;
+        step(f);
+    }
+    __syncthreads();
+    if (t < kScWords) reinterpret_cast<unsigned long long *>(fin.sc)[t] = reinterpret_cast<unsigned long long *>(&lsc)[t];
+}
+
 // One workgroup: totals of the partials, then the finalize step on thread 0.
 template <int NV, int NB, class FIN>
 __global__ __launch_bounds__(kFinBlock) void fin_kernel(const double *__restrict__ partial, int nblk, FIN fin,
                                                         const int *__restrict__ stop) {
     if (stop && *stop) return;
     __shared__ double tot[NV][NB];
-    sum_partials<NV, NB, kFinBlock>(partial, nblk, tot);
-    if (threadIdx.x == 0) fin(tot);
+    if constexpr (fin_has_sc<FIN>::value) {
+        const unsigned long long w = sc_stage_load(fin.sc);
+        sum_partials<NV, NB, kFinBlock>(partial, nblk, tot);
+        fin_staged(fin, w, [&](const FIN &f) { f(tot); });
+    } else {
+        sum_partials<NV, NB, kFinBlock>(partial, nblk, tot);
+        if (threadIdx.x == 0) fin(tot);
+    }
 }
 
 // The same with two partial buffers (one quantity each).
@@ -385,8 +425,14 @@ __global__ __launch_bounds__(kFinBlock) void fin2_kernel(const double *__restric
                                                          const int *__restrict__ stop) {
     if (stop && *stop) return;
     __shared__ double ta[1][NB], tb[1][NB];
-    sum_partials2<NB, kFinBlock>(pa, na, pb, nb, ta, tb);
-    if (threadIdx.x == 0) fin(ta, tb);
+    if constexpr (fin_has_sc<FIN>::value) {
+        const unsigned long long w = sc_stage_load(fin.sc);
+        sum_partials2<NB, kFinBlock>(pa, na, pb, nb, ta, tb);
+        fin_staged(fin, w, [&](const FIN &f) { f(ta, tb); });
+    } else {
+        sum_partials2<NB, kFinBlock>(pa, na, pb, nb, ta, tb);
+        if (threadIdx.x == 0) fin(ta, tb);
+    }
 }
 
 struct NoFin {
