@@ -415,3 +415,38 @@ def test_wide_slices_fall_back_to_csr():
     _, b0 = g0.time_kernel(1, prec=32, nb=1, reps=1)
     _, b1 = g1.time_kernel(1, prec=32, nb=1, reps=1)
     assert b1 > b0
+
+
+def test_wide_rows_take_sixteen_loads():
+    # Interior nodes of the 14^3 Kuhn cube moved by up to 0.1 h per coordinate:
+    # no stiffness entry is exactly zero any more, so A_0 keeps the 15-entry
+    # rows of the tetrahedral mesh graph and the level-0 sliced-ELL products
+    # (V-cycle sweeps, the FP64 CG product) take sixteen loads per lane instead
+    # of eight.  The reduced solve of the headline configuration against the
+    # oracle on the same mesh.  (Heights of a Kuhn tetrahedron are at least
+    # h / sqrt(2); nodes moving by at most 0.1 sqrt(3) h keep every element's
+    # orientation.)
+    import dataclasses
+
+    import paper_2001_11533_amd as amg
+    _need_gpu()
+    p = inputs.config("c3", n=14)
+    m = p.mesh
+    rng = np.random.default_rng(1411)
+    h = 1.0 / m.n
+    move = rng.uniform(-0.1 * h, 0.1 * h, size=m.coords.shape) * (m.boundary == 0)[:, None]
+    m = dataclasses.replace(m, coords=np.ascontiguousarray(m.coords + move))
+    p = dataclasses.replace(p, mesh=m)
+    rp, ci, va, vm = amg.assemble_p1(m.coords, m.elems, p.kappa)
+    g = amg.HessianSolver((rp, ci, va), (rp, ci, vm), p.dirichlet, beta=p.beta, inner_precision=32, smoother=1)
+    n0, nnz0, _, _ = g.level_size(0)
+    assert np.diff(g.csr(0, 0)[0]).max() == 15   # interior rows: the vertex and its 14 neighbours
+    h_, _, _ = osolve.build_problem(p, osa.Opts(beta=p.beta, smoother=1))
+    yd = p.yd[:, 0]
+    print(f"[parity] wide rows: N={m.nverts} nnz(A_0)={nnz0}", flush=True)
+    u, info = g.reduced_solve(cuda(yd), rtol=1e-8)
+    uo, _ = osolve.Oracle(h_).reduced_solve(yd, rtol=1e-12)
+    assert rel(u, uo) < 1e-8
+    o = osolve.Oracle(h_, mixed=True)
+    o.reduced_solve(yd, rtol=1e-8)
+    assert abs(info[0]["inner_iters_total"] - o.cnt.inner_iters) <= 0.2 * o.cnt.inner_iters + 5
