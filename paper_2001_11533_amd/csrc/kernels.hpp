@@ -315,16 +315,29 @@ __device__ bool fused_fin(const FusedFin<NB, JAC> &f, const double *&beta) {
     __shared__ double t1[JAC ? 2 : 1][NB], t2[1][NB];
     __shared__ double sb[NB];
     __shared__ int sall;
+    // the column scalars the step reads, loaded before the partial sums so that
+    // both loads are in flight together (nothing written in this kernel
+    // changes what the step decides from them: see above)
+    ColScal pre[NB];  // conv, bad, tol2 and rho only
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            pre[c].conv = f.sc->s[c].conv;
+            pre[c].bad = f.sc->s[c].bad;
+            pre[c].tol2 = f.sc->s[c].tol2;
+            pre[c].rho = f.sc->s[c].rho;
+        }
     if constexpr (JAC) sum_partials<2, NB>(f.p1, f.n1, t1);
     else sum_partials2<NB>(f.p1, f.n1, f.p2, f.n2, t1, t2);
     if (threadIdx.x == 0) {
         int all = 1;
+#pragma unroll
         for (int c = 0; c < NB; ++c) {
             ColScal &s = f.sc->s[c];
             const double rr = t1[0][c], rz = JAC ? t1[1][c] : t2[0][c];
-            const int was = s.conv;
+            const int was = pre[c].conv;
             int conv, bad;
-            const double b = cg_col_step(s, rr, rz, conv, bad);
+            const double b = cg_col_step(pre[c], rr, rz, conv, bad);
             if (blockIdx.x == 0 && !was) {
                 s.iters += 1;
                 s.rr = rr;
@@ -631,21 +644,29 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int n, T *__restrict_
     __shared__ double sh_a[NB];
     __shared__ int sh_live[NB];
     const int t = threadIdx.x;
+    // the column's scalars, loaded before the partial sums so that both loads
+    // are in flight together (workgroup 0 writes only fields read here by no one)
+    int conv0 = 0;
+    double rho0 = 0.0;
+    if (t < NB) {
+        conv0 = sc->s[t].conv;
+        rho0 = fused ? sc->s[t].rho_next : sc->s[t].rho;
+    }
     if (nblk_pq > 0) sum_partials<1, NB>(part_pq, nblk_pq, pq);
     if (nblk_pq == 0) {
         // alpha was formed by a finalize kernel (many partials)
         if (t < NB) {
             sh_a[t] = sc->s[t].alpha;
-            sh_live[t] = !sc->s[t].conv;
+            sh_live[t] = !conv0;
         }
     } else if (t < NB) {
         ColScal &s = sc->s[t];
         const double v = pq[0][t];
         double a = 0.0;
-        int live = !s.conv;
+        int live = !conv0;
         if (live) {
             if (v > 0.0) {
-                a = (fused ? s.rho_next : s.rho) / v;
+                a = rho0 / v;
             } else {
                 live = 0;
                 if (blockIdx.x == 0) {
@@ -659,7 +680,7 @@ __global__ __launch_bounds__(kBlock) void cg_update_kernel(int n, T *__restrict_
         if (blockIdx.x == 0) {
             s.alpha = a;
             s.pq = v;
-            if (fused && !s.conv) s.rho = s.rho_next;
+            if (fused && !conv0) s.rho = rho0;
         }
     }
     __syncthreads();
