@@ -114,6 +114,27 @@ def cpu_oracle(p):
     return cpu, uref
 
 
+def big_kernels(amg, inputs, torch, dev):
+    """The level-0 kernels on the 128^3 matrix (N = 2,146,689): time per launch
+    over 50 back-to-back launches with HIP events, algorithmic bytes and their
+    fraction of the HBM peak."""
+    p5 = inputs.config("c5", nb=16)
+    rp5, ci5, va5, vm5 = amg.assemble_p1(p5.mesh.coords, p5.mesh.elems, p5.kappa)
+    A5 = tuple(torch.as_tensor(x).to(dev) for x in (rp5, ci5, va5))
+    M5 = tuple(torch.as_tensor(x).to(dev) for x in (rp5, ci5, vm5))
+    mk5 = torch.as_tensor(p5.dirichlet).to(dev)
+    del rp5, ci5, va5, vm5
+    s5 = amg.HessianSolver(A5, M5, mk5, beta=p5.beta, inner_precision=32, smoother=1, autotune=1)
+    big = {}
+    for key, which, prec in (("presweep_f32", 1, 32), ("presweep_f64", 1, 64), ("spmv_f32", 0, 32),
+                             ("tpro_f32", 3, 32), ("cg_product_f64", 4, 64), ("vcycle_f32", 2, 32)):
+        ms5, by5 = s5.time_kernel(which, prec=prec, nb=1, reps=50)
+        big[key] = {"us": ms5 * 1e3, "MB": by5 / 1e6, "GBps": by5 / (ms5 * 1e-3) / 1e9,
+                    "frac": by5 / (ms5 * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    s5.close()
+    return big
+
+
 def run_c5(amg, inputs, torch, dev, tune_path, compare_untuned):
     """The 128^3 workload's 16 desired states in one batched solve: setup and
     solve timed with HIP events (inputs resident in HBM), with the autotuner's
@@ -180,6 +201,9 @@ def main():
                          "written back at the end of tuning")
     ap.add_argument("--c5-only", action="store_true",
                     help="only the 128^3 batch of 16 desired states (setup + solve), for its kernel statistics")
+    ap.add_argument("--kernels-128-only", action="store_true",
+                    help="only the level-0 kernel timings on the 128^3 matrix and the copy that calibrates the "
+                         "profiler's counters (for counter runs)")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline steps, the level-0 kernel timings and the copy that calibrates the "
                          "profiler's counters (for kernel traces and counter runs)")
@@ -225,6 +249,15 @@ def main():
     torch.cuda.synchronize()
 
     tune_path = args.tune_cache or os.path.join(tempfile.mkdtemp(), "tune.json")
+    if args.kernels_128_only:
+        big = big_kernels(amg, inputs, torch, dev)
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"metric": "level-0 kernels on the 128^3 matrix (counter runs)", "roofline_128cube": big}),
+              flush=True)
+        return
     if args.c5_only:
         c5 = run_c5(amg, inputs, torch, dev, tune_path, False)
         print(json.dumps({"metric": "reduced-Hessian batched solve, 3D 128^3 P1, 16 desired states",
@@ -371,20 +404,7 @@ def main():
     # ---- the same kernels on the 128^3 level-0 matrix (N = 2,146,689, 263 MB
     # float32): past the caches, where launch overheads no longer dominate; and
     # the 128^3 workload's 16 desired states in one batched solve ----
-    p5 = inputs.config("c5", nb=16)
-    rp5, ci5, va5, vm5 = amg.assemble_p1(p5.mesh.coords, p5.mesh.elems, p5.kappa)
-    A5 = tuple(torch.as_tensor(x).to(dev) for x in (rp5, ci5, va5))
-    M5 = tuple(torch.as_tensor(x).to(dev) for x in (rp5, ci5, vm5))
-    mk5 = torch.as_tensor(p5.dirichlet).to(dev)
-    del rp5, ci5, va5, vm5
-    s5 = amg.HessianSolver(A5, M5, mk5, beta=p5.beta, inner_precision=32, smoother=1, autotune=1)
-    big = {}
-    for key, which, prec in (("presweep_f32", 1, 32), ("presweep_f64", 1, 64), ("spmv_f32", 0, 32),
-                             ("tpro_f32", 3, 32), ("cg_product_f64", 4, 64), ("vcycle_f32", 2, 32)):
-        ms5, by5 = s5.time_kernel(which, prec=prec, nb=1, reps=50)
-        big[key] = {"us": ms5 * 1e3, "MB": by5 / 1e6, "GBps": by5 / (ms5 * 1e-3) / 1e9,
-                    "frac": by5 / (ms5 * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    s5.close()
+    big = big_kernels(amg, inputs, torch, dev)
     log(f"[bench] 128^3 level 0: pre-sweep f32 {big['presweep_f32']['GBps']:.0f} GB/s, "
         f"CG product f64 {big['cg_product_f64']['GBps']:.0f} GB/s")
     del A5, M5, mk5
