@@ -407,7 +407,6 @@ def main():
     big = big_kernels(amg, inputs, torch, dev)
     log(f"[bench] 128^3 level 0: pre-sweep f32 {big['presweep_f32']['GBps']:.0f} GB/s, "
         f"CG product f64 {big['cg_product_f64']['GBps']:.0f} GB/s")
-    del A5, M5, mk5
     c5 = None if args.no_c5 else run_c5(amg, inputs, torch, dev, tune_path, True)
 
     # ---- a plain device copy of 256 MiB: the reference that scales the
