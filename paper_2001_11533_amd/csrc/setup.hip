@@ -1390,18 +1390,34 @@ __device__ __forceinline__ const double *bat(const double *D, int n) { return D 
 // kTB x kTB tiles in LDS; 256 threads each own a 2x2 block of a product tile.
 typedef double Tile[kTB][kTB + 1];
 
-// acc += P Q for the thread's 2x2 block (rows ra, ra+1; columns cb, cb+1)
-__device__ __forceinline__ void tile_mac(const Tile &P, const Tile &Q, double acc[2][2]) {
-    const int ra = (threadIdx.x / 16) * 2, cb = (threadIdx.x % 16) * 2;
-#pragma unroll 8
-    for (int m = 0; m < kTB; ++m) {
-        const double a0 = P[ra][m], a1 = P[ra + 1][m];
-        const double b0 = Q[m][cb], b1 = Q[m][cb + 1];
-        acc[0][0] += a0 * b0;
-        acc[0][1] += a0 * b1;
-        acc[1][0] += a1 * b0;
-        acc[1][1] += a1 * b1;
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// The thread's 2x2 block (rows ra, ra+1; columns cb, cb+1) of the product
+// P Q of two tiles, on the FP64 matrix cores: wavefront w forms the 16 x 16
+// block (w / 2, w % 2) in kTB / 4 steps of v_mfma_f64_16x16x4f64 (lane l gives
+// P[16 bi + l % 16][4 s + l / 16] and Q[4 s + l / 16][16 bj + l % 16], and holds
+// Z[16 bi + l / 16 + 4 r][16 bj + l % 16] in its r-th result), the blocks pass
+// through the tile Z to the threads that own them.  Reads LDS once per operand
+// element and wavefront, against once per output pair on the vector ALUs.
+static_assert(kTB == 32 && kBlock == 256, "tile_mma: four wavefronts, each one 16 x 16 block of a 32 x 32 tile");
+__device__ __forceinline__ void tile_mma(const Tile &P, const Tile &Q, Tile &Z, double acc[2][2]) {
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int bi = (w >> 1) * 16, bj = (w & 1) * 16;
+    v4d c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < kTB; s4 += 4) {
+        const double a = P[bi + (l & 15)][s4 + (l >> 4)];
+        const double b = Q[s4 + (l >> 4)][bj + (l & 15)];
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Z[bi + (l >> 4) + 4 * r][bj + (l & 15)] = c[r];
+    __syncthreads();
+    const int ra = (threadIdx.x / 16) * 2, cb = (threadIdx.x % 16) * 2;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = Z[ra + u][cb + v];
 }
 
 // ---- inverse by block Gauss-Jordan sweeps ----
@@ -1488,7 +1504,7 @@ __device__ __forceinline__ void sweep_block(double (&q)[2][2], double (&vb)[2][k
 // other one -A_iK Q.  One workgroup per tile row.
 __global__ __launch_bounds__(kBlock) void k_gj_panel(int n, const double *srcb, double *dstb, int k,
                                                      const double *qin, int *bad) {
-    __shared__ Tile X, Qs;
+    __shared__ Tile X, Qs, Z;
     __shared__ double vb[2][kTB];
     const double *src = bat(srcb, n);
     double *dst = bat(dstb, n);
@@ -1527,8 +1543,8 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel(int n, const double *srcb, 
 #pragma unroll
             for (int v = 0; v < 2; ++v) Qs[ra + u][cb + v] = q[u][v];
         __syncthreads();
-        double z[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-        tile_mac(X, Qs, z);
+        double z[2][2];
+        tile_mma(X, Qs, Z, z);
 #pragma unroll
         for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -1556,7 +1572,7 @@ __global__ __launch_bounds__(kBlock) void k_gj_panel(int n, const double *srcb, 
 // qout for the next panel launch.
 __global__ __launch_bounds__(kBlock) void k_gj_update(int n, const double *srcb, double *dstb, int k,
                                                       double *qout, int *bad) {
-    __shared__ Tile X, Y;
+    __shared__ Tile X, Y, Z;
     __shared__ double vb[2][kTB];
     const double *src = bat(srcb, n);
     double *dst = bat(dstb, n);
@@ -1582,8 +1598,8 @@ __global__ __launch_bounds__(kBlock) void k_gj_update(int n, const double *srcb,
             a[u][v] = (i < n && j < n) ? x : 0.0;
         }
     __syncthreads();
-    double z[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    tile_mac(X, Y, z);
+    double z[2][2];
+    tile_mma(X, Y, Z, z);
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
